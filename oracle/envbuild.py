@@ -25,7 +25,9 @@ compression: a QR sweep left to right (left-orthonormal sites), then an SVD swee
 keeping k = min(chi, rows, cols) singular values at every bond (LAPACK order).  The result has
 right-orthonormal sites 1..Lc-1; the norm is taken out of site 0, so the stored MPS has unit
 2-norm and lognorm[r] = ln ||E_r||_2 (gauge invariant, the quantity compared across
-implementations).
+implementations).  For range only, the factor carried to the next site (R after each QR step, U S after each
+SVD step) is divided by its Frobenius norm and the log of that norm is accumulated; positive
+factors leave the compressed, normalised state unchanged.
 
 Tensor convention: A[c] has shape (chi_left, 2, chi_right); physical index 0 <-> spin +1,
 1 <-> spin -1.
@@ -76,11 +78,14 @@ def compress(mps, chi):
     """
     T = [t.copy() for t in mps]
     Lc = len(T)
+    log_carried = 0.0
     for c in range(Lc - 1):                                   # QR sweep, left to right
         dl, d, dr = T[c].shape
         Q, R = np.linalg.qr(T[c].reshape(dl * d, dr))
+        nR = float(np.linalg.norm(R))
+        log_carried += math.log(nR)
         T[c] = Q.reshape(dl, d, Q.shape[1])
-        T[c + 1] = np.tensordot(R, T[c + 1], axes=(1, 0))
+        T[c + 1] = np.tensordot(R / nR, T[c + 1], axes=(1, 0))
     cuts = {}
     for c in range(Lc - 1, 0, -1):                            # SVD sweep, right to left
         dl, d, dr = T[c].shape
@@ -88,11 +93,13 @@ def compress(mps, chi):
         k = min(chi, S.shape[0])
         if k < S.shape[0] and S[k - 1] > 0:
             cuts[c] = (S[k - 1] / S[0], (S[k - 1] - S[k]) / S[k - 1])
+        nS = float(np.linalg.norm(S[:k]))
+        log_carried += math.log(nS)
         T[c] = Vt[:k].reshape(k, d, dr)
-        T[c - 1] = np.tensordot(T[c - 1], U[:, :k] * S[:k], axes=(2, 0))
+        T[c - 1] = np.tensordot(T[c - 1], U[:, :k] * (S[:k] / nS), axes=(2, 0))
     n = float(np.linalg.norm(T[0]))
     T[0] = T[0] / n
-    return T, math.log(n), cuts
+    return T, log_carried + math.log(n), cuts
 
 
 def sensitivity(env, eps):

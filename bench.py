@@ -1,0 +1,209 @@
+"""Benchmark of the TNMC hot path on one MI355X.
+
+One step = one pass of the whole hot path over one batch: couplings (a1) -> environments (a2,
+a3) -> K proposals per realization with log q and exact energies (a4, a5) -> independence
+Metropolis over them (a6).  Default workload: 64 realizations of the 64 x 64 open +-J lattice at
+p = 0.109 on the Nishimori line, chi = 32, 1000 proposals each, FP32 batched (one launch per
+stage for the whole batch).  Also measured: the FP64 plain form (FP64 environments, one
+realization per call, one proposal per call) on a bounded sample, and the CPU FP64 oracle on the
+host (bounded sample, extrapolated; labelled).
+
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "accepted spin-updates/s + acceptance rate, BF16/FP32 batched vs FP64 plain"
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def build_flops_per_site(chi):
+    """Algorithmic work of one site of the canonical compression (QR of a 4chi x 2chi matrix
+    with Q, SVD of a 2chi x 2chi matrix, the two contractions), ~270 chi^3."""
+    return 270.0 * chi ** 3
+
+
+def run_gpu(args):
+    import torch
+    from paper_2409_06538_amd import binding
+    import synth
+
+    w = synth.WORKLOADS[args.workload]
+    L, chi, p, K = w["L"], w["chi"], w["p"], args.proposals or w["proposals"]
+    seeds = list(w["seeds"])
+    n = len(seeds)
+    beta = binding.nishimori_beta(p)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    b = binding.Batch([L] * n, [beta] * n, seeds, chi, args.precision, K=K, device=dev)
+    out = (torch.empty(b.spins_shape(K), dtype=torch.int64, device=dev),
+           torch.empty((n, K), dtype=torch.float64, device=dev),
+           torch.empty((n, K), dtype=torch.int32, device=dev))
+    accum = torch.zeros((n, binding.OBS_COUNT), dtype=torch.float64, device=dev)
+    ev = []
+
+    def step(timed):
+        b.make_couplings(seeds, p)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e2 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.build_env(want_lnZ=False)
+        e1.record()
+        b.propose(K, args.seed, first_proposal=0, out=out)
+        e2.record()
+        chains = b.new_chains(1)
+        acc, _ = b.accept(out, chains, seed=args.seed, accum=accum)
+        if timed:
+            ev.append((e0, e1, e2))
+        return acc
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    accs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        accs.append(step(True))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    accepted = int(sum(int(a.sum().item()) for a in accs))
+    attempted = args.steps * n * (K - 1)
+    build_ms = sum(a.elapsed_time(bb) for a, bb, _ in ev) / len(ev)
+    prop_ms = sum(bb.elapsed_time(c) for _, bb, c in ev) / len(ev)
+    wall = t1 - t0
+    res = {
+        "L": L, "chi": chi, "n": n, "K": K, "p": p, "beta": beta,
+        "wall_s": wall, "ms_per_step": 1e3 * wall / args.steps,
+        "accepted": accepted, "attempted": attempted,
+        "value": accepted * L * L / wall,
+        "acceptance": accepted / attempted,
+        "build_ms": build_ms, "propose_ms": prop_ms,
+    }
+    flops = build_flops_per_site(chi) * (L - 1) * L * n
+    peak = FP32_VECTOR_PEAK_TFLOPS if args.precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
+    achieved = flops / (build_ms * 1e-3) / 1e12
+    res["roofline"] = {"kernel": "env_build_kernel", "bound": "alu", "achieved": achieved,
+                       "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                       "traffic": None,
+                       "launch_ms": build_ms,
+                       "algorithmic_flops_per_launch": flops}
+    return res
+
+
+def run_fp64_plain(args, L, chi, p, K_full, n_prop=20):
+    """FP64 environments, one realization per call, one proposal per call (bounded sample)."""
+    import torch
+    from paper_2409_06538_amd import binding
+    beta = binding.nishimori_beta(p)
+    dev = torch.device("cuda:0")
+    b = binding.Batch([L], [beta], [0], chi, "fp64", K=1, device=dev)
+    b.make_couplings([0], p)
+    b.build_env(want_lnZ=False)     # warm-up launch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.build_env(want_lnZ=False)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    chains = b.new_chains(1)
+    accepted = 0
+    t0 = time.perf_counter()
+    for k in range(n_prop):
+        prop = b.propose(1, args.seed, first_proposal=k)
+        acc, _ = b.accept(prop, chains, seed=args.seed, first_step=k)
+        accepted += int(acc.sum().item())
+    torch.cuda.synchronize()
+    t_prop = (time.perf_counter() - t0) / n_prop
+    pa = accepted / max(1, n_prop - 1)
+    t_real = t_build + K_full * t_prop
+    return {"value": (K_full - 1) * pa * L * L / t_real, "unit": "spin-updates/s",
+            "acceptance": pa, "build_s": t_build, "s_per_proposal": t_prop,
+            "sample": f"1 realization (seed 0): FP64 build + {n_prop} single-proposal calls, "
+                      f"extrapolated to {K_full} proposals"}
+
+
+def run_cpu_baseline(L, chi, p, K_full, seed, n_prop=12):
+    """The oracle on one host core: one realization, full build + n_prop proposals (vectorised),
+    extrapolated to K_full proposals per realization."""
+    from threadpoolctl import threadpool_limits
+    from oracle import accept, energy, envbuild, instance, sampler
+    with threadpool_limits(limits=1):
+        beta = instance.nishimori_beta(p)
+        Jh, Jv = instance.couplings(0, L, p)
+        t0 = time.perf_counter()
+        env = envbuild.build_env(Jh, Jv, beta, chi)
+        t_build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        smp = sampler.run(env, Jh, Jv, beta, K=n_prop, seed=seed, realization=0)
+        E = energy.energy(smp["spins"], Jh, Jv)
+        ch = accept.chain(E, smp["logq"], beta, seed=seed, realization=0)
+        t_prop = (time.perf_counter() - t0) / n_prop
+    pa = float(ch["accepted"].sum()) / (n_prop - 1)
+    t_real = t_build + K_full * t_prop
+    return {"value": (K_full - 1) * pa * L * L / t_real, "unit": "spin-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"1 realization (seed 0), full FP64 environment build ({t_build:.1f} s) + "
+                      f"{n_prop} proposals ({t_prop:.2f} s each), extrapolated to {K_full} "
+                      f"proposals per realization; single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rbim64")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--proposals", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}): the realizations of a "
+              "batch are independent, so N GPUs would each run their own share; this build "
+              "measures one GPU's share.", file=sys.stderr)
+        sys.exit(2)
+    res = run_gpu(args)
+    plain = None if args.no_plain else run_fp64_plain(args, res["L"], res["chi"], res["p"], res["K"])
+    cpu = None if args.no_cpu else run_cpu_baseline(res["L"], res["chi"], res["p"], res["K"], args.seed)
+    line = {
+        "metric": METRIC,
+        "value": res["value"],
+        "unit": "spin-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {res['n']} realizations of the {res['L']}x"
+                               f"{res['L']} open +-J lattice, p={res['p']}, Nishimori beta, "
+                               f"chi={res['chi']}, {res['K']} proposals each, "
+                               f"{args.precision} batched",
+                   "L": res["L"], "chi": res["chi"], "realizations": res["n"],
+                   "proposals": res["K"], "p": res["p"], "precision": args.precision},
+        "acceptance": res["acceptance"],
+        "accepted": res["accepted"],
+        "attempted": res["attempted"],
+        "build_ms": res["build_ms"],
+        "propose_ms": res["propose_ms"],
+        "fp64_plain": plain,
+        "roofline": res["roofline"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

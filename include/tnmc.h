@@ -1,0 +1,170 @@
+/*
+ * tnmc.h -- C ABI of the MI355X tensor-network Monte Carlo (TNMC) hot path for the 2D +-J
+ * random-bond Ising model (RBIM).
+ *
+ * Paper: T. Chen, E. Guo, W. Zhang, P. Zhang, Y. Deng, "Tensor network Monte Carlo simulations
+ * for the two-dimensional random bond Ising model", arXiv:2409.06538.
+ *
+ * Problem (Sec. II, Sec. III A): an L x L square lattice with free boundaries, couplings
+ * J_ij = +-1 on nearest-neighbour bonds, i.i.d. with P(J = -1) = p, energy
+ * E(s) = -sum J_ij s_i s_j (Eq. (8)), Boltzmann weight exp(-beta E) (Eq. (1)).  TNMC contracts the
+ * tensor network of Z (Eq. (2)) with bond dimension truncated to chi (Sec. II B), samples
+ * whole-lattice proposals from the approximate conditionals q(s_i | s_<i) (Eqs. (4)-(6)) and
+ * removes the truncation bias with the Metropolis filter (Eq. (3)).
+ *
+ * Conventions shared by every entry point
+ *  - Rows r = 0..L-1 top to bottom, columns c = 0..L-1 left to right.  W(L) = ceil(L / 64).
+ *  - Bit-packed +-1 values: bit (c % 64) of word (c / 64) is 1 iff the value is -1; padding bits
+ *    are 0.  Couplings: Jh has L rows x W(L) words (bit c of row r is the bond (r,c)-(r,c+1),
+ *    c < L-1); Jv has L-1 rows x W(L) words (bit c of row r is the bond (r,c)-(r+1,c)).
+ *    Spins: one configuration is Lmax rows x W(Lmax) words, where Lmax is the largest L of the
+ *    batch (rows and bits beyond a realization's own L are 0).
+ *  - Pointers named d_* are DEVICE pointers owned by the caller; host arrays (tnmc_instance
+ *    tables, seeds) are read during the call only.  The library allocates no device memory: every
+ *    buffer, including the workspace, comes from the caller (sizes from the *_bytes queries).
+ *  - Every call enqueues work on `stream` and returns without synchronising.  Argument errors are
+ *    detected on the host and returned synchronously (nothing is enqueued then).  Launch failures
+ *    return TNMC_EHIP.  No exception crosses this interface.
+ *  - Results are a pure function of (inputs, seeds, counters, precision): re-running is
+ *    bit-identical.  Random draws use Philox4x64-10 (Salmon et al., SC'11): draw i of the stream
+ *    keyed (k0, k1) with counter words (c1, c2, c3) is word (i & 3) of the block at counter
+ *    (i >> 2, c1, c2, c3), turned into u = (w >> 11) * 2^-53 in [0, 1).
+ *  - Concurrent calls that share a workspace race; use one workspace per stream.
+ */
+#ifndef TNMC_H
+#define TNMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TNMC_OK = 0,
+  TNMC_EINVAL = -1,   /* bad argument (sizes, null pointers, unsupported chi or L) */
+  TNMC_ENOMEM = -2,   /* workspace smaller than tnmc_workspace_bytes */
+  TNMC_EHIP = -3,     /* a HIP call or kernel launch failed */
+  TNMC_ENUMERIC = -4, /* reserved: non-finite values reported by tnmc_status_check */
+  TNMC_ESTATE = -5    /* chain state inconsistent with the call */
+} tnmc_status;
+
+/* Storage/arithmetic precision of the environments and of the contractions.  The running
+ * log-normalisation of the environments, log q(s), energies' Boltzmann factors and the
+ * acceptance ratio are FP64 in every mode. */
+typedef enum { TNMC_FP64 = 0, TNMC_FP32 = 1 } tnmc_precision;
+
+/* One disorder realization.  An array of these (host memory) describes a batch. */
+typedef struct {
+  int32_t L;          /* lattice side, 2 <= L <= 1024 */
+  int32_t pad_;
+  double beta;        /* inverse temperature, > 0 (Nishimori line: ln((1-p)/p) / 2, Sec. III A) */
+  uint64_t id;        /* realization id: third counter word of its proposal and accept streams */
+  uint64_t* d_Jh;     /* L x W(L) words (written by tnmc_make_couplings, else caller-filled) */
+  uint64_t* d_Jv;     /* (L-1) x W(L) words */
+  void* d_env;        /* tnmc_env_bytes(L, chi, prec) bytes: written by tnmc_build_env */
+  double* d_lognorm;  /* L doubles: lambda_r = ln ||E_r||_2, written by tnmc_build_env */
+} tnmc_instance;
+
+/* Number of observable accumulators per realization (see tnmc_accept). */
+#define TNMC_OBS_COUNT 9
+
+/* Supported bond dimensions: chi in {4, 8, 16, 32}; L in [2, 1024]. */
+int tnmc_chi_supported(int32_t chi, tnmc_precision prec);
+
+/* Bytes of one realization's environments: L rows x L sites x 2 x chi x chi reals, layout
+ * [r][c][sigma][alpha][beta] (sigma 0 <-> +1), zero-padded where the bond is smaller than chi. */
+size_t tnmc_env_bytes(int32_t L, int32_t chi, tnmc_precision prec);
+
+/* Workspace bytes needed by every entry point below for this batch (the maximum over the
+ * calls, so one buffer serves them all; it holds the device copy of the instance table and the
+ * per-call scratch).  K = proposals per
+ * realization per call.  Returns 0 on invalid arguments. */
+size_t tnmc_workspace_bytes(const tnmc_instance* inst, int32_t n, int32_t chi, int32_t K,
+                            tnmc_precision prec);
+
+/* a1 -- couplings (Sec. III A): bond k of realization i is antiferromagnetic iff
+ * u_k < p, u_k = draw k of the stream keyed (seeds[i], 0) with counter words (0, 0, 0); the
+ * L(L-1) horizontal bonds come first in row-major order (k = r(L-1) + c), then the vertical
+ * bonds (k = L(L-1) + rL + c).  Writes d_Jh and d_Jv of every instance.  0 <= p <= 1. */
+tnmc_status tnmc_make_couplings(const tnmc_instance* inst, int32_t n, const uint64_t* seeds,
+                                double p, void* d_workspace, size_t workspace_bytes,
+                                hipStream_t stream);
+
+/* a2 + a3 -- environments (Sec. II B).  For every realization: E_{L-1} = 1; for r = L-1..1,
+ * E_{r-1} = compress_chi(T_r E_r) where T_r applies the row's Boltzmann matrices (Eq. (7)):
+ * (T_r f)(x) = sum_y prod_c exp(beta Jv[r-1][c] x_c y_c) prod_c exp(beta Jh[r][c] y_c y_{c+1}) f(y).
+ * compress_chi is the canonical SVD compression (left-orthonormalise by QR, then truncate
+ * right to left keeping the chi largest singular values at every bond).  Each E_r is stored as a
+ * unit-norm MPS in d_env (sites 1..L-1 right-orthonormal) with d_lognorm[r] = ln ||E_r||_2.
+ * d_lnZ (n doubles, device, may be NULL) receives ln Z_TN = lambda_0 + ln sum_x H_0(x) E_0(x)/||E_0||.
+ * The workspace must hold tnmc_workspace_bytes. */
+tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,
+                           void* d_workspace, size_t workspace_bytes, double* d_lnZ,
+                           hipStream_t stream);
+
+/* a4 + a5 -- K whole-lattice proposals per realization (Sec. II A-B, Eqs. (4)-(6)), sampled row
+ * by row and, within a row, column by column from the cached environments: right partial sums
+ * R_c(y) = sum_y' w_c(y,y') phi_{c+1}(y') A^{(c+1)}[y'] R_{c+1}(y') and a left running vector;
+ * Z_c(y) = [w_{c-1}(s_{c-1},y)] phi_c(y) l A^{(c)}[y] R_c(y), phi_c(y) = exp(beta Jv[r-1][c] s[r-1][c] y),
+ * w_c(y,y') = exp(beta Jh[r][c] y y').  Negative Z_c(y) count as 0; p+ = Z_c(+)/(Z_c(+)+Z_c(-))
+ * (1/2 if the sum is 0 or not finite), clamped to [1e-12, 1-1e-12]; s = +1 iff u < p+ with u
+ * = draw c of the stream keyed (seed, 1) with counter words (r, first_proposal + k, id).
+ * Outputs per (realization i, proposal k): d_spins [n][K][Lmax][W(Lmax)] words, d_logq [n][K]
+ * (FP64 sum of ln p+ or ln(1-p+)), d_E [n][K] int32 exact energy (a5: E = 2U - N_B, U the number
+ * of unsatisfied bonds).  d_fallbacks (n uint32, device, may be NULL) counts sites where p+ fell
+ * back to 1/2 (accumulated, not reset). */
+tnmc_status tnmc_propose(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,
+                         int32_t K, uint64_t seed, uint64_t first_proposal, void* d_workspace,
+                         size_t workspace_bytes, uint64_t* d_spins, double* d_logq, int32_t* d_E,
+                         uint32_t* d_fallbacks, hipStream_t stream);
+
+/* log q(s) of given configurations (the same conditionals as tnmc_propose, with the spins read
+ * from d_spins instead of drawn): d_spins [n][K][Lmax][W(Lmax)], d_logq [n][K]. */
+tnmc_status tnmc_logq(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,
+                      int32_t K, const uint64_t* d_spins, void* d_workspace,
+                      size_t workspace_bytes, double* d_logq, hipStream_t stream);
+
+/* a5 -- exact integer energies E(s) = -sum J_ij s_i s_j (Eq. (8)) of d_spins [n][K][Lmax][W] into
+ * d_E [n][K]. */
+tnmc_status tnmc_energy(const tnmc_instance* inst, int32_t n, int32_t K, const uint64_t* d_spins,
+                        int32_t* d_E, void* d_workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+
+/* a6 -- independence Metropolis chains (Eq. (3) with g(s'|s) = q(s'), Appendix A).  Each
+ * realization runs n_chain chains; chain j consumes proposals k = j*K/n_chain .. (j+1)*K/n_chain-1
+ * in order (K % n_chain == 0).  Per step: Delta = (-beta E' - log q') - (-beta E - log q); accept
+ * iff Delta >= 0 or u < exp(Delta), u = draw (first_step + t) of the stream keyed (seed, 2) with
+ * counter words (j, id, 0), t the step index within the chain; a chain whose d_chain_init byte is
+ * 0 takes its first proposal unconditionally (not counted as accepted) and sets the byte to 1.
+ * Chain state [n][n_chain]: d_chain_spins (Lmax x W words each), d_chain_E, d_chain_logq,
+ * d_chain_init -- read and updated.  Outputs: d_accepted [n][K] (1 = accepted), d_current [n][K]
+ * int32 (proposal index the chain holds after that step, -1 = a configuration from before this
+ * call).  If d_accum != NULL, the observables of Sec. III C of every chain after every step are
+ * added to d_accum [n][TNMC_OBS_COUNT]: count, sum E, sum E^2, sum m^2, sum m^4, sum m_edge^2,
+ * sum q, sum q^2, sum q^4 (q = overlap of chains 0 and 1, when n_chain >= 2; m_edge over the
+ * sites L/4 .. 3L/4-1 of each edge, divided by 2L). */
+tnmc_status tnmc_accept(const tnmc_instance* inst, int32_t n, int32_t n_chain, int32_t K,
+                        const uint64_t* d_prop_spins, const double* d_prop_logq,
+                        const int32_t* d_prop_E, uint64_t seed, uint64_t first_step,
+                        uint64_t* d_chain_spins, int32_t* d_chain_E, double* d_chain_logq,
+                        uint8_t* d_chain_init, uint8_t* d_accepted, int32_t* d_current,
+                        double* d_accum, void* d_workspace, size_t workspace_bytes,
+                        hipStream_t stream);
+
+/* Observables of the current chain states (one sample per chain), added to d_accum
+ * [n][TNMC_OBS_COUNT] with the layout of tnmc_accept. */
+tnmc_status tnmc_observables(const tnmc_instance* inst, int32_t n, int32_t n_chain,
+                             const uint64_t* d_chain_spins, const int32_t* d_chain_E,
+                             double* d_accum, void* d_workspace, size_t workspace_bytes,
+                             hipStream_t stream);
+
+const char* tnmc_status_string(tnmc_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TNMC_H */

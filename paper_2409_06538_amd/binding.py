@@ -1,0 +1,247 @@
+"""Thin Python binding of the C ABI in include/tnmc.h (ctypes; argument marshalling only).
+
+Every step of the hot path runs in the HIP kernels of ``libtnmc.so``; torch only allocates
+device memory and supplies the stream.  There is no CPU fallback: ``load()`` raises if the
+library has not been built (``python -m paper_2409_06538_amd.build``) or no GPU is visible.
+
+Names follow the C entry points: ``make_couplings``, ``build_env``, ``propose``, ``logq``,
+``energy``, ``accept``, ``observables``.
+"""
+import ctypes
+import math
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtnmc.so")
+
+FP64, FP32 = 0, 1
+PRECISIONS = {"fp64": FP64, "fp32": FP32}
+OBS_COUNT = 9
+OBS_NAMES = ("count", "E", "E2", "m2", "m4", "medge2", "q", "q2", "q4")
+
+_lib = None
+
+
+class Instance(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("pad_", ctypes.c_int32), ("beta", ctypes.c_double),
+                ("id", ctypes.c_uint64), ("d_Jh", ctypes.c_void_p), ("d_Jv", ctypes.c_void_p),
+                ("d_env", ctypes.c_void_p), ("d_lognorm", ctypes.c_void_p)]
+
+
+class TNMCError(RuntimeError):
+    pass
+
+
+def load():
+    """Load libtnmc.so (once) and declare its signatures; raise if unavailable."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TNMCError(f"{LIB_PATH} is missing: build it with "
+                        "`python -m paper_2409_06538_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(Instance)
+    vp, i32, u64, sz, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_double
+    sigs = {
+        "tnmc_chi_supported": (ctypes.c_int, [i32, ctypes.c_int]),
+        "tnmc_env_bytes": (sz, [i32, i32, ctypes.c_int]),
+        "tnmc_workspace_bytes": (sz, [P, i32, i32, i32, ctypes.c_int]),
+        "tnmc_make_couplings": (ctypes.c_int, [P, i32, vp, dbl, vp, sz, vp]),
+        "tnmc_build_env": (ctypes.c_int, [P, i32, i32, ctypes.c_int, vp, sz, vp, vp]),
+        "tnmc_propose": (ctypes.c_int, [P, i32, i32, ctypes.c_int, i32, u64, u64, vp, sz, vp, vp,
+                                        vp, vp, vp]),
+        "tnmc_logq": (ctypes.c_int, [P, i32, i32, ctypes.c_int, i32, vp, vp, sz, vp, vp]),
+        "tnmc_energy": (ctypes.c_int, [P, i32, i32, vp, vp, vp, sz, vp]),
+        "tnmc_accept": (ctypes.c_int, [P, i32, i32, i32, vp, vp, vp, u64, u64, vp, vp, vp, vp, vp,
+                                       vp, vp, vp, sz, vp]),
+        "tnmc_observables": (ctypes.c_int, [P, i32, i32, vp, vp, vp, vp, sz, vp]),
+        "tnmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    """Names of the C entry points this binding declares."""
+    return ["tnmc_chi_supported", "tnmc_env_bytes", "tnmc_workspace_bytes", "tnmc_make_couplings",
+            "tnmc_build_env", "tnmc_propose", "tnmc_logq", "tnmc_energy", "tnmc_accept",
+            "tnmc_observables", "tnmc_status_string"]
+
+
+def _check(status, what):
+    if status != 0:
+        msg = _lib.tnmc_status_string(status).decode()
+        raise TNMCError(f"{what} failed: {msg} ({status})")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def words_per_row(L):
+    return (L + 63) // 64
+
+
+def nishimori_beta(p):
+    """Inverse temperature on the Nishimori line exp(-2 beta) = p / (1 - p) (J = 1)."""
+    return 0.5 * math.log((1.0 - p) / p)
+
+
+class Batch:
+    """Device buffers for a batch of realizations plus the host instance table."""
+
+    def __init__(self, Ls, betas, ids, chi, precision="fp32", K=1, device="cuda:0"):
+        lib = load()
+        self.n = len(Ls)
+        self.Ls = [int(L) for L in Ls]
+        self.Lmax = max(self.Ls)
+        self.Wmax = words_per_row(self.Lmax)
+        self.chi = int(chi)
+        self.prec = PRECISIONS[precision]
+        self.precision = precision
+        self.dtype = torch.float64 if self.prec == FP64 else torch.float32
+        self.device = torch.device(device)
+        if not lib.tnmc_chi_supported(self.chi, self.prec):
+            raise TNMCError(f"chi={chi} not supported for {precision}")
+        self.Jh, self.Jv, self.env, self.lognorm = [], [], [], []
+        self.table = (Instance * self.n)()
+        for i, L in enumerate(self.Ls):
+            W = words_per_row(L)
+            jh = torch.zeros(L * W, dtype=torch.int64, device=self.device)
+            jv = torch.zeros((L - 1) * W, dtype=torch.int64, device=self.device)
+            nbytes = lib.tnmc_env_bytes(L, self.chi, self.prec)
+            env = torch.zeros(nbytes // (8 if self.prec == FP64 else 4), dtype=self.dtype,
+                              device=self.device)
+            lam = torch.zeros(L, dtype=torch.float64, device=self.device)
+            self.Jh.append(jh)
+            self.Jv.append(jv)
+            self.env.append(env)
+            self.lognorm.append(lam)
+            t = self.table[i]
+            t.L, t.pad_, t.beta, t.id = L, 0, float(betas[i]), int(ids[i])
+            t.d_Jh, t.d_Jv = jh.data_ptr(), jv.data_ptr()
+            t.d_env, t.d_lognorm = env.data_ptr(), lam.data_ptr()
+        self.K = 0
+        self.workspace = None
+        self.ensure_workspace(K)
+
+    # -- workspace -------------------------------------------------------------------------
+    def ensure_workspace(self, K):
+        if K <= self.K and self.workspace is not None:
+            return
+        nbytes = load().tnmc_workspace_bytes(self.table, self.n, self.chi, int(K), self.prec)
+        if nbytes == 0:
+            raise TNMCError("tnmc_workspace_bytes rejected the batch")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.K = int(K)
+
+    def _ws(self):
+        return ctypes.c_void_p(self.workspace.data_ptr()), ctypes.c_size_t(self.workspace.numel())
+
+    # -- entry points ----------------------------------------------------------------------
+    def make_couplings(self, seeds, p):
+        """tnmc_make_couplings: i.i.d. +-1 couplings with P(J=-1) = p from Philox."""
+        seeds = (ctypes.c_uint64 * self.n)(*[int(s) for s in seeds])
+        ws, nb = self._ws()
+        _check(load().tnmc_make_couplings(self.table, self.n, ctypes.cast(seeds, ctypes.c_void_p),
+                                          float(p), ws, nb, _stream()), "tnmc_make_couplings")
+
+    def set_couplings(self, i, jh_words, jv_words):
+        """Copy caller-packed coupling words (int64/uint64 arrays) into realization i."""
+        self.Jh[i].copy_(torch.as_tensor(jh_words.view("int64")).reshape(-1))
+        self.Jv[i].copy_(torch.as_tensor(jv_words.view("int64")).reshape(-1))
+
+    def build_env(self, want_lnZ=True):
+        """tnmc_build_env: environments, log-norms and (optionally) ln Z_TN per realization."""
+        lnZ = torch.zeros(self.n, dtype=torch.float64, device=self.device) if want_lnZ else None
+        ws, nb = self._ws()
+        _check(load().tnmc_build_env(self.table, self.n, self.chi, self.prec, ws, nb, _ptr(lnZ),
+                                     _stream()), "tnmc_build_env")
+        return lnZ
+
+    def spins_shape(self, K):
+        return (self.n, K, self.Lmax, self.Wmax)
+
+    def propose(self, K, seed, first_proposal=0, out=None, fallbacks=None):
+        """tnmc_propose: K proposals per realization -> (spins words, logq, E)."""
+        self.ensure_workspace(K)
+        if out is None:
+            spins = torch.empty(self.spins_shape(K), dtype=torch.int64, device=self.device)
+            logq = torch.empty((self.n, K), dtype=torch.float64, device=self.device)
+            E = torch.empty((self.n, K), dtype=torch.int32, device=self.device)
+        else:
+            spins, logq, E = out
+        ws, nb = self._ws()
+        _check(load().tnmc_propose(self.table, self.n, self.chi, self.prec, int(K), int(seed),
+                                   int(first_proposal), ws, nb, _ptr(spins), _ptr(logq), _ptr(E),
+                                   _ptr(fallbacks), _stream()), "tnmc_propose")
+        return spins, logq, E
+
+    def logq(self, spins):
+        """tnmc_logq: log q of given configurations (spins words [n][K][Lmax][Wmax])."""
+        K = spins.shape[1]
+        self.ensure_workspace(K)
+        out = torch.empty((self.n, K), dtype=torch.float64, device=self.device)
+        ws, nb = self._ws()
+        _check(load().tnmc_logq(self.table, self.n, self.chi, self.prec, int(K), _ptr(spins), ws,
+                                nb, _ptr(out), _stream()), "tnmc_logq")
+        return out
+
+    def energy(self, spins):
+        """tnmc_energy: exact integer energies of given configurations."""
+        K = spins.shape[1]
+        E = torch.empty((self.n, K), dtype=torch.int32, device=self.device)
+        ws, nb = self._ws()
+        _check(load().tnmc_energy(self.table, self.n, int(K), _ptr(spins), _ptr(E), ws, nb,
+                                  _stream()), "tnmc_energy")
+        return E
+
+    def new_chains(self, n_chain):
+        """Zeroed chain state for n_chain chains per realization."""
+        return {
+            "spins": torch.zeros((self.n, n_chain, self.Lmax, self.Wmax), dtype=torch.int64,
+                                 device=self.device),
+            "E": torch.zeros((self.n, n_chain), dtype=torch.int32, device=self.device),
+            "logq": torch.zeros((self.n, n_chain), dtype=torch.float64, device=self.device),
+            "init": torch.zeros((self.n, n_chain), dtype=torch.uint8, device=self.device),
+            "n_chain": n_chain,
+        }
+
+    def accept(self, proposals, chains, seed, first_step=0, accum=None):
+        """tnmc_accept: independence Metropolis over the proposals; updates `chains` in place."""
+        spins, logq, E = proposals
+        K = spins.shape[1]
+        self.ensure_workspace(K)
+        n_chain = chains["n_chain"]
+        accepted = torch.empty((self.n, K), dtype=torch.uint8, device=self.device)
+        current = torch.empty((self.n, K), dtype=torch.int32, device=self.device)
+        ws, nb = self._ws()
+        _check(load().tnmc_accept(self.table, self.n, n_chain, int(K), _ptr(spins), _ptr(logq),
+                                  _ptr(E), int(seed), int(first_step), _ptr(chains["spins"]),
+                                  _ptr(chains["E"]), _ptr(chains["logq"]), _ptr(chains["init"]),
+                                  _ptr(accepted), _ptr(current), _ptr(accum), ws, nb, _stream()),
+               "tnmc_accept")
+        return accepted, current
+
+    def observables(self, chains, accum):
+        """tnmc_observables: add one sample per chain (current states) to accum [n][9]."""
+        ws, nb = self._ws()
+        _check(load().tnmc_observables(self.table, self.n, chains["n_chain"], _ptr(chains["spins"]),
+                                       _ptr(chains["E"]), _ptr(accum), ws, nb, _stream()),
+               "tnmc_observables")
+
+    def env_tensor(self, i):
+        """Environments of realization i as (L, L, 2, chi, chi)."""
+        L = self.Ls[i]
+        return self.env[i].view(L, L, 2, self.chi, self.chi)

@@ -1,0 +1,235 @@
+// C ABI of the TNMC hot path (declared in include/tnmc.h): argument validation, workspace
+// layout and kernel launches.  No exception crosses this layer; no device memory is allocated.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "internal.hpp"
+#include "tnmc.h"
+
+using namespace tnmc;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+inline size_t elem_bytes(tnmc_precision p) { return p == TNMC_FP64 ? 8 : 4; }
+
+bool chi_ok(int32_t chi) { return chi == 4 || chi == 8 || chi == 16 || chi == 32; }
+bool prec_ok(tnmc_precision p) { return p == TNMC_FP64 || p == TNMC_FP32; }
+
+// Basic per-instance checks; returns Lmax or -1.
+int check_instances(const tnmc_instance* inst, int32_t n, bool need_env, bool need_J) {
+  if (inst == nullptr || n < 1) return -1;
+  int Lmax = 0;
+  for (int i = 0; i < n; ++i) {
+    const tnmc_instance& s = inst[i];
+    if (s.L < 2 || s.L > 1024) return -1;
+    if (!(s.beta > 0.0) || !std::isfinite(s.beta)) return -1;
+    if (need_J && (s.d_Jh == nullptr || s.d_Jv == nullptr)) return -1;
+    if (need_env && (s.d_env == nullptr || s.d_lognorm == nullptr)) return -1;
+    Lmax = std::max(Lmax, int(s.L));
+  }
+  return Lmax;
+}
+
+size_t desc_bytes(int32_t n) { return align_up(size_t(n) * sizeof(DevReal)); }
+
+size_t build_region(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision p) {
+  size_t b = 0;
+  for (int i = 0; i < n; ++i) b += align_up(env_build_scratch_bytes(p, chi, inst[i].L));
+  return b;
+}
+
+size_t propose_region(const tnmc_instance* inst, int32_t n, int32_t chi, int32_t K,
+                      tnmc_precision p) {
+  size_t b = 0;
+  for (int i = 0; i < n; ++i) b += align_up(propose_scratch_bytes(p, chi, inst[i].L, K));
+  return b;
+}
+
+size_t accept_region(int32_t n, int32_t K) { return 2 * align_up(size_t(n) * K * sizeof(int32_t)); }
+
+enum class Use { build, propose, none };
+
+// Build the device descriptor table in the workspace; per-realization slices for `use`.
+hipError_t upload_desc(const tnmc_instance* inst, int32_t n, int32_t chi, int32_t K,
+                       tnmc_precision p, Use use, void* ws, hipStream_t stream) {
+  std::vector<DevReal> h(n);
+  char* base = static_cast<char*>(ws) + desc_bytes(n);
+  size_t off = 0;
+  for (int i = 0; i < n; ++i) {
+    DevReal& d = h[i];
+    d.L = inst[i].L;
+    d.pad_ = 0;
+    d.beta = inst[i].beta;
+    d.id = inst[i].id;
+    d.Jh = inst[i].d_Jh;
+    d.Jv = inst[i].d_Jv;
+    d.env = inst[i].d_env;
+    d.lognorm = inst[i].d_lognorm;
+    d.ws = base + off;
+    if (use == Use::build) off += align_up(env_build_scratch_bytes(p, chi, inst[i].L));
+    else if (use == Use::propose) off += align_up(propose_scratch_bytes(p, chi, inst[i].L, K));
+  }
+  // Pageable source: the runtime stages it before returning, so `h` may go out of scope.
+  return hipMemcpyAsync(ws, h.data(), sizeof(DevReal) * n, hipMemcpyHostToDevice, stream);
+}
+
+inline tnmc_status hip_status(hipError_t e) { return e == hipSuccess ? TNMC_OK : TNMC_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+int tnmc_chi_supported(int32_t chi, tnmc_precision prec) { return chi_ok(chi) && prec_ok(prec); }
+
+size_t tnmc_env_bytes(int32_t L, int32_t chi, tnmc_precision prec) {
+  if (L < 2 || L > 1024 || !chi_ok(chi) || !prec_ok(prec)) return 0;
+  return size_t(L) * L * 2 * chi * chi * elem_bytes(prec);
+}
+
+size_t tnmc_workspace_bytes(const tnmc_instance* inst, int32_t n, int32_t chi, int32_t K,
+                            tnmc_precision prec) {
+  if (check_instances(inst, n, false, false) < 0 || !chi_ok(chi) || !prec_ok(prec) || K < 1)
+    return 0;
+  const size_t r = std::max({build_region(inst, n, chi, prec), propose_region(inst, n, chi, K, prec),
+                             accept_region(n, K), align_up(sizeof(uint64_t) * n)});
+  return desc_bytes(n) + r;
+}
+
+tnmc_status tnmc_make_couplings(const tnmc_instance* inst, int32_t n, const uint64_t* seeds,
+                                double p, void* d_workspace, size_t workspace_bytes,
+                                hipStream_t stream) {
+  const int Lmax = check_instances(inst, n, false, true);
+  if (Lmax < 0 || seeds == nullptr || !(p >= 0.0 && p <= 1.0) || d_workspace == nullptr)
+    return TNMC_EINVAL;
+  if (workspace_bytes < desc_bytes(n) + align_up(sizeof(uint64_t) * n)) return TNMC_ENOMEM;
+  char* d = static_cast<char*>(d_workspace);
+  hipError_t e = upload_desc(inst, n, 4, 1, TNMC_FP32, Use::none, d, stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d + desc_bytes(n), seeds, sizeof(uint64_t) * n, hipMemcpyHostToDevice,
+                       stream);
+  if (e == hipSuccess)
+    e = couplings_launch(reinterpret_cast<const DevReal*>(d), n,
+                         reinterpret_cast<const uint64_t*>(d + desc_bytes(n)), p, Lmax, stream);
+  return hip_status(e);
+}
+
+tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,
+                           void* d_workspace, size_t workspace_bytes, double* d_lnZ,
+                           hipStream_t stream) {
+  if (check_instances(inst, n, true, true) < 0 || !chi_ok(chi) || !prec_ok(prec) ||
+      d_workspace == nullptr)
+    return TNMC_EINVAL;
+  if (workspace_bytes < desc_bytes(n) + build_region(inst, n, chi, prec)) return TNMC_ENOMEM;
+  hipError_t e = upload_desc(inst, n, chi, 1, prec, Use::build, d_workspace, stream);
+  if (e != hipSuccess) return TNMC_EHIP;
+  return hip_status(env_build(prec, chi, static_cast<const DevReal*>(d_workspace), n, d_lnZ, stream));
+}
+
+static tnmc_status propose_common(const tnmc_instance* inst, int32_t n, int32_t chi,
+                                  tnmc_precision prec, int32_t K, uint64_t seed,
+                                  uint64_t first_proposal, const uint64_t* d_teacher,
+                                  void* d_workspace, size_t workspace_bytes, uint64_t* d_spins,
+                                  double* d_logq, int32_t* d_E, uint32_t* d_fallbacks,
+                                  hipStream_t stream) {
+  const int Lmax = check_instances(inst, n, true, true);
+  if (Lmax < 0 || !chi_ok(chi) || !prec_ok(prec) || K < 1 || d_workspace == nullptr ||
+      d_logq == nullptr)
+    return TNMC_EINVAL;
+  if (d_teacher == nullptr && (d_spins == nullptr || d_E == nullptr)) return TNMC_EINVAL;
+  if (workspace_bytes < desc_bytes(n) + propose_region(inst, n, chi, K, prec)) return TNMC_ENOMEM;
+  hipError_t e = upload_desc(inst, n, chi, K, prec, Use::propose, d_workspace, stream);
+  if (e != hipSuccess) return TNMC_EHIP;
+  return hip_status(propose(prec, chi, static_cast<const DevReal*>(d_workspace), n, K, Lmax, seed,
+                            first_proposal, d_teacher, d_spins, d_logq, d_E, d_fallbacks, stream));
+}
+
+tnmc_status tnmc_propose(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,
+                         int32_t K, uint64_t seed, uint64_t first_proposal, void* d_workspace,
+                         size_t workspace_bytes, uint64_t* d_spins, double* d_logq, int32_t* d_E,
+                         uint32_t* d_fallbacks, hipStream_t stream) {
+  if (d_spins == nullptr || d_E == nullptr) return TNMC_EINVAL;
+  return propose_common(inst, n, chi, prec, K, seed, first_proposal, nullptr, d_workspace,
+                        workspace_bytes, d_spins, d_logq, d_E, d_fallbacks, stream);
+}
+
+tnmc_status tnmc_logq(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,
+                      int32_t K, const uint64_t* d_spins, void* d_workspace,
+                      size_t workspace_bytes, double* d_logq, hipStream_t stream) {
+  if (d_spins == nullptr) return TNMC_EINVAL;
+  return propose_common(inst, n, chi, prec, K, 0, 0, d_spins, d_workspace, workspace_bytes,
+                        nullptr, d_logq, nullptr, nullptr, stream);
+}
+
+tnmc_status tnmc_energy(const tnmc_instance* inst, int32_t n, int32_t K, const uint64_t* d_spins,
+                        int32_t* d_E, void* d_workspace, size_t workspace_bytes,
+                        hipStream_t stream) {
+  const int Lmax = check_instances(inst, n, false, true);
+  if (Lmax < 0 || K < 1 || d_spins == nullptr || d_E == nullptr || d_workspace == nullptr)
+    return TNMC_EINVAL;
+  if (workspace_bytes < desc_bytes(n)) return TNMC_ENOMEM;
+  hipError_t e = upload_desc(inst, n, 4, 1, TNMC_FP32, Use::none, d_workspace, stream);
+  if (e == hipSuccess)
+    e = energy_launch(static_cast<const DevReal*>(d_workspace), n, K, Lmax, d_spins, d_E, stream);
+  return hip_status(e);
+}
+
+tnmc_status tnmc_accept(const tnmc_instance* inst, int32_t n, int32_t n_chain, int32_t K,
+                        const uint64_t* d_prop_spins, const double* d_prop_logq,
+                        const int32_t* d_prop_E, uint64_t seed, uint64_t first_step,
+                        uint64_t* d_chain_spins, int32_t* d_chain_E, double* d_chain_logq,
+                        uint8_t* d_chain_init, uint8_t* d_accepted, int32_t* d_current,
+                        double* d_accum, void* d_workspace, size_t workspace_bytes,
+                        hipStream_t stream) {
+  const int Lmax = check_instances(inst, n, false, false);
+  if (Lmax < 0 || n_chain < 1 || K < n_chain || K % n_chain != 0 || d_prop_spins == nullptr ||
+      d_prop_logq == nullptr || d_prop_E == nullptr || d_chain_spins == nullptr ||
+      d_chain_E == nullptr || d_chain_logq == nullptr || d_chain_init == nullptr ||
+      d_accepted == nullptr || d_current == nullptr || d_workspace == nullptr)
+    return TNMC_EINVAL;
+  if (workspace_bytes < desc_bytes(n) + accept_region(n, K)) return TNMC_ENOMEM;
+  hipError_t e = upload_desc(inst, n, 4, K, TNMC_FP32, Use::none, d_workspace, stream);
+  if (e != hipSuccess) return TNMC_EHIP;
+  char* base = static_cast<char*>(d_workspace) + desc_bytes(n);
+  int32_t* oldE = reinterpret_cast<int32_t*>(base);
+  int32_t* fin = reinterpret_cast<int32_t*>(base + align_up(size_t(n) * K * sizeof(int32_t)));
+  return hip_status(accept_launch(static_cast<const DevReal*>(d_workspace), n, n_chain, K, Lmax,
+                                  d_prop_spins, d_prop_logq, d_prop_E, seed, first_step,
+                                  d_chain_spins, d_chain_E, d_chain_logq, d_chain_init,
+                                  d_accepted, d_current, d_accum, oldE, fin, stream));
+}
+
+tnmc_status tnmc_observables(const tnmc_instance* inst, int32_t n, int32_t n_chain,
+                             const uint64_t* d_chain_spins, const int32_t* d_chain_E,
+                             double* d_accum, void* d_workspace, size_t workspace_bytes,
+                             hipStream_t stream) {
+  const int Lmax = check_instances(inst, n, false, false);
+  if (Lmax < 0 || n_chain < 1 || d_chain_spins == nullptr || d_chain_E == nullptr ||
+      d_accum == nullptr || d_workspace == nullptr)
+    return TNMC_EINVAL;
+  if (workspace_bytes < desc_bytes(n)) return TNMC_ENOMEM;
+  hipError_t e = upload_desc(inst, n, 4, 1, TNMC_FP32, Use::none, d_workspace, stream);
+  if (e == hipSuccess)
+    e = observables_launch(static_cast<const DevReal*>(d_workspace), n, n_chain, Lmax,
+                           d_chain_spins, d_chain_E, d_accum, stream);
+  return hip_status(e);
+}
+
+const char* tnmc_status_string(tnmc_status s) {
+  switch (s) {
+    case TNMC_OK: return "ok";
+    case TNMC_EINVAL: return "invalid argument";
+    case TNMC_ENOMEM: return "workspace too small";
+    case TNMC_EHIP: return "HIP call or kernel launch failed";
+    case TNMC_ENUMERIC: return "non-finite values";
+    case TNMC_ESTATE: return "inconsistent chain state";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

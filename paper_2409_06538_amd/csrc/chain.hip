@@ -1,0 +1,306 @@
+// Couplings (Sec. III A), exact energies (Eq. (8)), the independence Metropolis chain (Eq. (3)
+// with g(s'|s) = q(s'); Appendix A) and the observables of Sec. III C.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace tnmc {
+
+// ---------------------------------------------------------------------------------------------
+// Couplings: bond k antiferromagnetic iff u_k < p, u_k = draw k of the stream (seed, 0); the
+// L(L-1) horizontal bonds (k = r(L-1) + c) precede the vertical bonds (k = L(L-1) + rL + c).
+// One thread writes one 64-bit word of Jh or Jv.
+__global__ void couplings_kernel(const DevReal* reals, const uint64_t* seeds, double p, int Lmax) {
+  const int ri = blockIdx.y;
+  const DevReal R = reals[ri];
+  const int L = R.L, W = words_per_row(L);
+  const int words = (2 * L - 1) * W;   // L rows of Jh then L-1 rows of Jv
+  const uint64_t seed = seeds[ri];
+  for (int o = blockIdx.x * blockDim.x + threadIdx.x; o < words; o += gridDim.x * blockDim.x) {
+    const int row = o / W, w = o % W;
+    const bool horiz = row < L;
+    const int r = horiz ? row : row - L;
+    const int ncol = horiz ? L - 1 : L;
+    uint64_t bits = 0;
+    uint64_t cached = ~0ull;
+    Philox4 blk{};
+    for (int b = 0; b < 64; ++b) {
+      const int c = w * 64 + b;
+      if (c >= ncol) break;
+      const uint64_t k = horiz ? uint64_t(r) * (L - 1) + c
+                               : uint64_t(L) * (L - 1) + uint64_t(r) * L + c;
+      if ((k >> 2) != cached) {
+        blk = philox4x64_10(k >> 2, 0, 0, 0, seed, STREAM_COUPLINGS);
+        cached = k >> 2;
+      }
+      const int q = int(k & 3);
+      const uint64_t wd = q == 0 ? blk.w[0] : q == 1 ? blk.w[1] : q == 2 ? blk.w[2] : blk.w[3];
+      if (u53(wd) < p) bits |= (1ull << b);
+    }
+    uint64_t* dst = horiz ? const_cast<uint64_t*>(R.Jh) + size_t(r) * W
+                          : const_cast<uint64_t*>(R.Jv) + size_t(r) * W;
+    dst[w] = bits;
+  }
+}
+
+hipError_t couplings_launch(const DevReal* d_reals, int n, const uint64_t* d_seeds, double p,
+                            int Lmax, hipStream_t stream) {
+  const int W = words_per_row(Lmax);
+  const int words = (2 * Lmax - 1) * W;
+  dim3 grid((words + 255) / 256, n);
+  hipLaunchKernelGGL(couplings_kernel, grid, dim3(256), 0, stream, d_reals, d_seeds, p, Lmax);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Energy E = 2U - N_B from bit-packed spins, U = number of unsatisfied bonds, i.e. bonds with
+// bit(J) xor bit(s_i) xor bit(s_j) = 1.  One wavefront per configuration.
+__device__ __forceinline__ int unsat_rows(const uint64_t* s, const uint64_t* jh, const uint64_t* jv,
+                                          int L, int Wmax, int lane) {
+  const int W = words_per_row(L);
+  int u = 0;
+  for (int o = lane; o < L * W; o += WAVE) {
+    const int r = o / W, w = o % W;
+    const uint64_t cw = s[size_t(r) * Wmax + w];
+    const uint64_t nxt = (w + 1 < W) ? s[size_t(r) * Wmax + w + 1] : 0ull;
+    const uint64_t right = (cw >> 1) | (nxt << 63);
+    const int nb_h = (L - 1) - 64 * w;
+    const uint64_t mh = nb_h >= 64 ? ~0ull : (nb_h > 0 ? ((1ull << nb_h) - 1) : 0ull);
+    u += __popcll((cw ^ right ^ jh[size_t(r) * W + w]) & mh);
+    if (r + 1 < L) {
+      const int nb_v = L - 64 * w;
+      const uint64_t mv = nb_v >= 64 ? ~0ull : ((1ull << nb_v) - 1);
+      u += __popcll((cw ^ s[size_t(r + 1) * Wmax + w] ^ jv[size_t(r) * W + w]) & mv);
+    }
+  }
+  return u;
+}
+
+__global__ void energy_kernel(const DevReal* reals, int n, int K, int Lmax, const uint64_t* spins,
+                              int32_t* E) {
+  const int lane = threadIdx.x % WAVE;
+  const long cfg = long(blockIdx.x) * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (cfg >= long(n) * K) return;
+  const int ri = int(cfg / K);
+  const DevReal R = reals[ri];
+  const int Wmax = words_per_row(Lmax);
+  const uint64_t* s = spins + size_t(cfg) * Lmax * Wmax;
+  int u = unsat_rows(s, R.Jh, R.Jv, R.L, Wmax, lane);
+  u = wave_sum(u);
+  if (lane == 0) E[cfg] = 2 * u - 2 * R.L * (R.L - 1);
+}
+
+hipError_t energy_launch(const DevReal* d_reals, int n, int K, int Lmax, const uint64_t* d_spins,
+                         int32_t* d_E, hipStream_t stream) {
+  const long cfgs = long(n) * K;
+  const int per = 4;   // configurations per workgroup of 256 threads
+  hipLaunchKernelGGL(energy_kernel, dim3(unsigned((cfgs + per - 1) / per)), dim3(per * WAVE), 0,
+                     stream, d_reals, n, K, Lmax, d_spins, d_E);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Independence Metropolis: one thread runs one chain over its proposals in order.
+__global__ void accept_kernel(const DevReal* reals, int n, int n_chain, int K,
+                              const double* prop_logq, const int32_t* prop_E, uint64_t seed,
+                              uint64_t first_step, int32_t* chain_E, double* chain_logq,
+                              uint8_t* chain_init, uint8_t* accepted, int32_t* current,
+                              int32_t* oldE, int32_t* final_idx) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * n_chain) return;
+  const int ri = t / n_chain, j = t % n_chain;
+  const DevReal R = reals[ri];
+  const int Kc = K / n_chain;
+  int E = chain_E[t];
+  double lq = chain_logq[t];
+  bool init = chain_init[t] != 0;
+  oldE[t] = E;
+  int cur = -1;
+  for (int s = 0; s < Kc; ++s) {
+    const int k = j * Kc + s;
+    const size_t o = size_t(ri) * K + k;
+    const int Ep = prop_E[o];
+    const double lp = prop_logq[o];
+    const double u = philox_uniform(seed, STREAM_ACCEPT, first_step + uint64_t(s), uint64_t(j),
+                                    R.id, 0);
+    bool acc = false;
+    if (!init) {
+      init = true;
+      cur = k;
+      E = Ep;
+      lq = lp;
+    } else {
+      const double delta = (-R.beta * double(Ep) - lp) - (-R.beta * double(E) - lq);
+      if (delta >= 0.0 || u < exp(delta)) {
+        acc = true;
+        cur = k;
+        E = Ep;
+        lq = lp;
+      }
+    }
+    accepted[o] = acc ? 1 : 0;
+    current[o] = cur;
+  }
+  chain_E[t] = E;
+  chain_logq[t] = lq;
+  chain_init[t] = init ? 1 : 0;
+  final_idx[t] = cur;
+}
+
+// Copy each chain's final configuration (if it came from this batch) into the chain state.
+__global__ void chain_copy_kernel(int n, int n_chain, int K, int Lmax,
+                                  const uint64_t* prop_spins, uint64_t* chain_spins,
+                                  const int32_t* final_idx) {
+  const int t = blockIdx.y;
+  const int idx = final_idx[t];
+  if (idx < 0) return;
+  const int ri = t / n_chain;
+  const size_t words = size_t(Lmax) * words_per_row(Lmax);
+  const uint64_t* src = prop_spins + (size_t(ri) * K + idx) * words;
+  uint64_t* dst = chain_spins + size_t(t) * words;
+  for (size_t o = blockIdx.x * blockDim.x + threadIdx.x; o < words; o += gridDim.x * blockDim.x)
+    dst[o] = src[o];
+}
+
+// Observables of one configuration: m, m_edge (sites L/4 .. 3L/4-1 of each edge, / 2L).
+__device__ __forceinline__ void config_obs(const uint64_t* s, int L, int Wmax, int lane, int& neg,
+                                           int& edge_neg) {
+  const int W = words_per_row(L);
+  neg = 0;
+  edge_neg = 0;
+  const int a = L / 4, b = (3 * L) / 4;
+  for (int o = lane; o < L * W; o += WAVE) {
+    const int r = o / W, w = o % W;
+    const uint64_t cw = s[size_t(r) * Wmax + w];
+    neg += __popcll(cw);
+    if (r == 0 || r == L - 1) {
+      // columns a..b-1 of the top and bottom rows
+      for (int c = max(a, 64 * w); c < min(b, 64 * w + 64); ++c) edge_neg += int((cw >> (c - 64 * w)) & 1ull);
+    }
+    if (r >= a && r < b) {
+      if (w == 0) edge_neg += int(cw & 1ull);
+      if (w == (L - 1) / 64) edge_neg += int((cw >> ((L - 1) % 64)) & 1ull);
+    }
+  }
+}
+
+__device__ __forceinline__ int overlap_diff(const uint64_t* s0, const uint64_t* s1, int L, int Wmax,
+                                            int lane) {
+  const int W = words_per_row(L);
+  int d = 0;
+  for (int o = lane; o < L * W; o += WAVE) {
+    const int r = o / W, w = o % W;
+    d += __popcll(s0[size_t(r) * Wmax + w] ^ s1[size_t(r) * Wmax + w]);
+  }
+  return d;
+}
+
+// Accumulate the observables of every (chain, step) of one realization per workgroup, with a
+// fixed reduction order (bit-reproducible).  Each wavefront handles steps t = wave, wave + 4, ...
+// `steps` = K / n_chain; `current` == nullptr means one sample per chain from the chain state.
+__global__ void observables_kernel(const DevReal* reals, int n_chain, int K, int Lmax,
+                                   const uint64_t* prop_spins, const int32_t* prop_E,
+                                   const int32_t* current, const uint64_t* chain_spins,
+                                   const int32_t* chain_E, double* accum) {
+  constexpr int NWAVE = 4;
+  __shared__ double part[NWAVE][TNMC_OBS_COUNT];
+  const int ri = blockIdx.x;
+  const DevReal R = reals[ri];
+  const int L = R.L;
+  const int Wmax = words_per_row(Lmax);
+  const size_t words = size_t(Lmax) * Wmax;
+  const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+  const int steps = current ? K / n_chain : 1;
+  const double N = double(L) * L;
+  double acc[TNMC_OBS_COUNT];
+  for (int i = 0; i < TNMC_OBS_COUNT; ++i) acc[i] = 0.0;
+  for (int t = wv; t < steps; t += NWAVE) {
+    const uint64_t* cfg[2] = {nullptr, nullptr};
+    for (int j = 0; j < n_chain; ++j) {
+      const uint64_t* s;
+      int E;
+      if (current) {
+        const int idx = current[size_t(ri) * K + j * steps + t];
+        if (idx >= 0) {
+          s = prop_spins + (size_t(ri) * K + idx) * words;
+          E = prop_E[size_t(ri) * K + idx];
+        } else {
+          s = chain_spins + (size_t(ri) * n_chain + j) * words;
+          E = chain_E[size_t(ri) * n_chain + j];
+        }
+      } else {
+        s = chain_spins + (size_t(ri) * n_chain + j) * words;
+        E = chain_E[size_t(ri) * n_chain + j];
+      }
+      if (j < 2) cfg[j] = s;
+      int neg, eneg;
+      config_obs(s, L, Wmax, lane, neg, eneg);
+      neg = wave_sum(neg);
+      eneg = wave_sum(eneg);
+      const double m = (N - 2.0 * neg) / N;
+      const double nedge = 2.0 * L;   // 4 segments of L/2 sites (L even); general: see below
+      const int seg = (3 * L) / 4 - L / 4;
+      const double me = (4.0 * seg - 2.0 * eneg) / nedge;
+      acc[0] += 1.0;
+      acc[1] += double(E);
+      acc[2] += double(E) * double(E);
+      acc[3] += m * m;
+      acc[4] += m * m * m * m;
+      acc[5] += me * me;
+    }
+    if (n_chain >= 2) {
+      int d = overlap_diff(cfg[0], cfg[1], L, Wmax, lane);
+      d = wave_sum(d);
+      const double q = (N - 2.0 * d) / N;
+      acc[6] += q;
+      acc[7] += q * q;
+      acc[8] += q * q * q * q;
+    }
+  }
+  if (lane == 0)
+    for (int i = 0; i < TNMC_OBS_COUNT; ++i) part[wv][i] = acc[i];
+  __syncthreads();
+  if (threadIdx.x < TNMC_OBS_COUNT) {
+    double s = 0.0;
+    for (int w = 0; w < NWAVE; ++w) s += part[w][threadIdx.x];
+    accum[size_t(ri) * TNMC_OBS_COUNT + threadIdx.x] += s;
+  }
+}
+
+hipError_t accept_launch(const DevReal* d_reals, int n, int n_chain, int K, int Lmax,
+                         const uint64_t* d_prop_spins, const double* d_prop_logq,
+                         const int32_t* d_prop_E, uint64_t seed, uint64_t first_step,
+                         uint64_t* d_chain_spins, int32_t* d_chain_E, double* d_chain_logq,
+                         uint8_t* d_chain_init, uint8_t* d_accepted, int32_t* d_current,
+                         double* d_accum, int32_t* d_ws_oldE, int32_t* d_ws_final,
+                         hipStream_t stream) {
+  const int chains = n * n_chain;
+  hipLaunchKernelGGL(accept_kernel, dim3((chains + 63) / 64), dim3(64), 0, stream, d_reals, n,
+                     n_chain, K, d_prop_logq, d_prop_E, seed, first_step, d_chain_E, d_chain_logq,
+                     d_chain_init, d_accepted, d_current, d_ws_oldE, d_ws_final);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  if (d_accum) {
+    // steps sitting on a configuration from before this call use the saved energies
+    hipLaunchKernelGGL(observables_kernel, dim3(n), dim3(256), 0, stream, d_reals, n_chain, K,
+                       Lmax, d_prop_spins, d_prop_E, d_current, d_chain_spins, d_ws_oldE, d_accum);
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  const size_t words = size_t(Lmax) * words_per_row(Lmax);
+  dim3 grid(unsigned((words + 255) / 256), chains);
+  hipLaunchKernelGGL(chain_copy_kernel, grid, dim3(256), 0, stream, n, n_chain, K, Lmax,
+                     d_prop_spins, d_chain_spins, d_ws_final);
+  return hipGetLastError();
+}
+
+hipError_t observables_launch(const DevReal* d_reals, int n, int n_chain, int Lmax,
+                              const uint64_t* d_chain_spins, const int32_t* d_chain_E,
+                              double* d_accum, hipStream_t stream) {
+  hipLaunchKernelGGL(observables_kernel, dim3(n), dim3(256), 0, stream, d_reals, n_chain, n_chain,
+                     Lmax, nullptr, nullptr, nullptr, d_chain_spins, d_chain_E, d_accum);
+  return hipGetLastError();
+}
+
+}  // namespace tnmc

@@ -1,0 +1,52 @@
+// Host/device interface between the C ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tnmc.h"
+
+namespace tnmc {
+
+// Device-side descriptor of one realization (built by the C ABI layer in the workspace).
+struct DevReal {
+  int L;
+  int pad_;
+  double beta;
+  uint64_t id;
+  const uint64_t* Jh;
+  const uint64_t* Jv;
+  void* env;
+  double* lognorm;
+  void* ws;   // this realization's slice of the workspace (call-specific use)
+};
+
+hipError_t couplings_launch(const DevReal* d_reals, int n, const uint64_t* d_seeds, double p,
+                            int Lmax, hipStream_t stream);
+
+hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n, double* d_lnZ,
+                     hipStream_t stream);
+size_t env_build_scratch_bytes(tnmc_precision prec, int chi, int L);
+
+hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, int K, int Lmax,
+                   uint64_t seed, uint64_t first, const uint64_t* d_teacher, uint64_t* d_spins,
+                   double* d_logq, int32_t* d_E, uint32_t* d_fallbacks, hipStream_t stream);
+size_t propose_scratch_bytes(tnmc_precision prec, int chi, int L, int K);
+
+hipError_t energy_launch(const DevReal* d_reals, int n, int K, int Lmax, const uint64_t* d_spins,
+                         int32_t* d_E, hipStream_t stream);
+
+hipError_t accept_launch(const DevReal* d_reals, int n, int n_chain, int K, int Lmax,
+                         const uint64_t* d_prop_spins, const double* d_prop_logq,
+                         const int32_t* d_prop_E, uint64_t seed, uint64_t first_step,
+                         uint64_t* d_chain_spins, int32_t* d_chain_E, double* d_chain_logq,
+                         uint8_t* d_chain_init, uint8_t* d_accepted, int32_t* d_current,
+                         double* d_accum, int32_t* d_ws_oldE, int32_t* d_ws_final,
+                         hipStream_t stream);
+
+hipError_t observables_launch(const DevReal* d_reals, int n, int n_chain, int Lmax,
+                              const uint64_t* d_chain_spins, const int32_t* d_chain_E,
+                              double* d_accum, hipStream_t stream);
+
+}  // namespace tnmc

@@ -18,7 +18,7 @@ constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 inline size_t elem_bytes(tnmc_precision p) { return p == TNMC_FP64 ? 8 : 4; }
 
-bool chi_ok(int32_t chi) { return chi == 4 || chi == 8 || chi == 16 || chi == 32; }
+bool chi_ok(int32_t chi) { return chi == 2 || chi == 4 || chi == 8 || chi == 16 || chi == 32; }
 bool prec_ok(tnmc_precision p) { return p == TNMC_FP64 || p == TNMC_FP32; }
 
 // Basic per-instance checks; returns Lmax or -1.

@@ -31,12 +31,63 @@ struct JacobiTol<double> {
   static constexpr double rot = 1e-14;
   // columns whose remaining norm is below rank * ||T||_F are dropped by the pivoted QR
   static constexpr double rank = 1e-15;
+  // a kept row whose Cholesky pivot (squared residual norm) falls below eta is dependent
+  static constexpr double eta = 1e-12;
 };
 template <>
 struct JacobiTol<float> {
   static constexpr float rot = 2e-6f;
   static constexpr float rank = 3e-7f;
+  static constexpr float eta = 1e-5f;
 };
+
+// Orthonormalise rows 0..k-1 of V (row stride ldv, n columns) in place by Cholesky QR applied
+// twice; G (k x (CHI+1) workspace) holds the Gram matrix and then its Cholesky factor.  Rows are
+// processed in order; a row whose pivot falls below eta lies in the span of the earlier rows (to
+// rounding) and is set to zero.  The span of the surviving rows is unchanged.
+template <typename T, int CHI, int NT>
+__device__ void cholqr2_rows(T* V, int ldv, int n, int k, T* G, T eta) {
+  constexpr int LDG = CHI + 1;
+  const int tid = threadIdx.x;
+  for (int pass = 0; pass < 2; ++pass) {
+    __syncthreads();
+    for (int o = tid; o < k * k; o += NT) {
+      const int a = o / k, b = o % k;
+      if (b <= a) {
+        T d = 0;
+        for (int j = 0; j < n; ++j) d += V[a * ldv + j] * V[b * ldv + j];
+        G[a * LDG + b] = d;
+      }
+    }
+    __syncthreads();
+    if (tid < WAVE) {
+      for (int a = 0; a < k; ++a) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const T piv = G[a * LDG + a];
+        const bool alive = piv > eta;
+        const T l = alive ? sqrt(piv) : T(1);
+        for (int i = a + 1 + tid; i < k; i += WAVE) G[i * LDG + a] = alive ? G[i * LDG + a] / l : T(0);
+        if (tid == 0) G[a * LDG + a] = alive ? l : T(0);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        const int m = k - a - 1;
+        for (int o = tid; o < m * m; o += WAVE) {
+          const int i = a + 1 + o / m, j = a + 1 + o % m;
+          if (j <= i) G[i * LDG + j] -= G[i * LDG + a] * G[j * LDG + a];
+        }
+      }
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += NT) {
+      for (int a = 0; a < k; ++a) {
+        const T laa = G[a * LDG + a];
+        T v = V[a * ldv + j];
+        for (int b = 0; b < a; ++b) v -= G[a * LDG + b] * V[b * ldv + j];
+        V[a * ldv + j] = (laa > T(0)) ? v / laa : T(0);
+      }
+    }
+  }
+  __syncthreads();
+}
 
 constexpr int MAX_SWEEPS = 40;
 
@@ -483,7 +534,9 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         }
         bufS[al * N2 + perm[kk]] = v;
       }
-      __syncthreads();
+      // the kept rows span the right subspace but small ones are orthogonal to the large ones
+      // only up to rot * ||T|| / sigma: make them orthonormal (span unchanged)
+      cholqr2_rows<T, CHI, NT>(bufS, N2, N2, kept, bufR, T(JacobiTol<T>::eta));
       // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
       T* bout = Aout + size_t(c) * site;
       for (int o = tid; o < int(site); o += NT) {
@@ -590,6 +643,7 @@ hipError_t launch_env_build(const DevReal* d_reals, int n, double* d_lnZ, hipStr
 template <typename T>
 size_t env_build_smem_bytes(int chi) {
   switch (chi) {
+    case 2: return EnvSmem<T, 2>::bytes;
     case 4: return EnvSmem<T, 4>::bytes;
     case 8: return EnvSmem<T, 8>::bytes;
     case 16: return EnvSmem<T, 16>::bytes;
@@ -602,6 +656,7 @@ hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n
                      hipStream_t stream) {
   if (prec == TNMC_FP64) {
     switch (chi) {
+      case 2: return launch_env_build<double, 2>(d_reals, n, d_lnZ, stream);
       case 4: return launch_env_build<double, 4>(d_reals, n, d_lnZ, stream);
       case 8: return launch_env_build<double, 8>(d_reals, n, d_lnZ, stream);
       case 16: return launch_env_build<double, 16>(d_reals, n, d_lnZ, stream);
@@ -609,6 +664,7 @@ hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n
     }
   } else {
     switch (chi) {
+      case 2: return launch_env_build<float, 2>(d_reals, n, d_lnZ, stream);
       case 4: return launch_env_build<float, 4>(d_reals, n, d_lnZ, stream);
       case 8: return launch_env_build<float, 8>(d_reals, n, d_lnZ, stream);
       case 16: return launch_env_build<float, 16>(d_reals, n, d_lnZ, stream);

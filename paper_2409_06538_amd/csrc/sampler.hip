@@ -244,9 +244,9 @@ hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, 
     return launch_propose<TY, C>(d_reals, n, K, Lmax, seed, first, d_teacher, d_spins, d_logq,  \
                                  d_E, d_fallbacks, stream);
   if (prec == TNMC_FP64) {
-    switch (chi) { TNMC_PROP_CASE(double, 4) TNMC_PROP_CASE(double, 8) TNMC_PROP_CASE(double, 16) TNMC_PROP_CASE(double, 32) }
+    switch (chi) { TNMC_PROP_CASE(double, 2) TNMC_PROP_CASE(double, 4) TNMC_PROP_CASE(double, 8) TNMC_PROP_CASE(double, 16) TNMC_PROP_CASE(double, 32) }
   } else {
-    switch (chi) { TNMC_PROP_CASE(float, 4) TNMC_PROP_CASE(float, 8) TNMC_PROP_CASE(float, 16) TNMC_PROP_CASE(float, 32) }
+    switch (chi) { TNMC_PROP_CASE(float, 2) TNMC_PROP_CASE(float, 4) TNMC_PROP_CASE(float, 8) TNMC_PROP_CASE(float, 16) TNMC_PROP_CASE(float, 32) }
   }
 #undef TNMC_PROP_CASE
   return hipErrorInvalidValue;

@@ -105,8 +105,8 @@ struct EnvSmem {
                                                                          : size_t(LDA) * N2;
   static constexpr size_t bufR = size_t(N2) * LDT;
   static constexpr size_t bufS = size_t(2) * CHI * CHI;
-  static constexpr size_t reals = bufA + bufR + bufS + 4 * N2 + NT / 64 + 8;
-  static constexpr size_t ints = 2 * N2 + 8;
+  static constexpr size_t reals = bufA + bufR + bufS + 3 * N2 + NT / 64 + 8;
+  static constexpr size_t ints = 2 * N2 + 8 + 1024;
   static constexpr size_t bytes = reals * sizeof(T) + ints * sizeof(int);
 };
 
@@ -121,7 +121,7 @@ __device__ __forceinline__ T bond_weight(const uint64_t* row_bits, int c, int sa
 
 template <typename T, int CHI>
 __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevReal* reals,
-                                                                        double* lnZ_out) {
+                                                                     double* lnZ_out) {
   using S = EnvSmem<T, CHI>;
   constexpr int N2 = S::N2, MQ = S::MQ, LDA = S::LDA, LDT = S::LDT, NT = S::NT;
   constexpr int EPT = (N2 + 7) / 8;   // elements per thread of a Jacobi row
@@ -129,14 +129,14 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   T* bufA = reinterpret_cast<T*>(smem_raw);
   T* bufR = bufA + S::bufA;
   T* bufS = bufR + S::bufR;
-  T* tau = bufS + S::bufS;          // N2
-  T* cn2 = tau + N2;                // N2 column norms^2 / row norms^2
-  T* sc = cn2 + N2;                 // N2 scalars scratch
+  T* cn2 = bufS + S::bufS;          // N2 column norms^2
+  T* sc = cn2 + N2;                 // 2 N2 scalars scratch
   T* red = sc + 2 * N2;             // NT/64
   T* misc = red + NT / 64;          // 8
   int* perm = reinterpret_cast<int*>(misc + 8);   // N2
   int* ord = perm + N2;                           // N2
   int* imisc = ord + N2;                          // 8
+  int* rexp = imisc + 8;                          // MAX_L exponents of the carried R_c
 
   const int tid = threadIdx.x;
   const DevReal R = reals[blockIdx.x];
@@ -144,9 +144,11 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   const int W = words_per_row(L);
   const T ep = T(exp(R.beta)), em = T(exp(-R.beta));
   T* env = reinterpret_cast<T*>(R.env);
-  T* qs = reinterpret_cast<T*>(R.ws);                 // L x MQ x N2 scratch (column-major Q_c)
+  T* rs = reinterpret_cast<T*>(R.ws);                 // L x N2 x N2 scratch: R_c column-major
   const size_t site = size_t(2) * CHI * CHI;
   const size_t rowst = site * L;
+  T* Zb = bufA;                      // Z_c: N2 x N2 column-major (rows (a,alpha), cols (x,beta))
+  T* Tw = bufA + size_t(N2) * LDT;   // T_c: N2 x N2 column-major
 
   // E_{L-1} = 1: every site is 1/sqrt(2) at [sigma][0][0].
   for (size_t e = tid; e < rowst; e += NT) {
@@ -164,12 +166,12 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     const uint64_t* jv = R.Jv + size_t(r - 1) * W;    // vertical bonds between rows r-1 and r
     long long log2acc = 0;
 
-    // ---------------- QR sweep (left to right) ----------------
-    for (int c = 0; c < L; ++c) {
+    // ---------------- left-to-right: R factors only ----------------
+    // M_c = R_{c-1} At_c (rows (i,x), cols (b,ap)); R_c = R factor of M_c, rescaled by 2^-e_c.
+    for (int c = 0; c < L - 1; ++c) {
       __syncthreads();
       for (int e = tid; e < int(site); e += NT) bufS[e] = Ain[size_t(c) * site + e];
       __syncthreads();
-      // weights: wv[x][b], wh[a][b] (wh unused at c = 0)
       T wv[2][2], wh[2][2];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
@@ -179,8 +181,6 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) wh[a][b] = (c > 0) ? bond_weight<T>(jh, c - 1, a, b, ep, em) : T(0);
-      const bool last = (c == L - 1);
-      // M[(i,x)][(b,ap)] (column-major, col = b*CHI+ap, row = i*2+x)
       for (int o = tid; o < N2 * N2; o += NT) {
         const int i = o % N2;
         const int col = o / N2;
@@ -196,39 +196,11 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
             d += p * bufS[(b * CHI + al) * CHI + ap];
           }
         }
-        if (!last) {
-          bufA[col * LDA + i * 2 + 0] = wv[0][b] * d;
-          bufA[col * LDA + i * 2 + 1] = wv[1][b] * d;
-        } else {
-          // right bond of the last site: b is summed; the result sits in block b = 0
-          if (b == 0) {
-            bufA[col * LDA + i * 2 + 0] = wv[0][0] * d;
-            bufA[col * LDA + i * 2 + 1] = wv[1][0] * d;
-          }
-        }
-      }
-      if (last) {
-        __syncthreads();
-        // add the b = 1 block into b = 0, then clear b = 1
-        for (int o = tid; o < N2 * CHI; o += NT) {
-          const int i = o % N2, ap = o / N2;
-          T d = 0;
-          const T wa = wh[0][1], wb = wh[1][1];
-          for (int al = 0; al < CHI; ++al) {
-            const T p = bufR[al * LDT + i] * wa + bufR[(CHI + al) * LDT + i] * wb;
-            d += p * bufS[(CHI + al) * CHI + ap];
-          }
-          bufA[ap * LDA + i * 2 + 0] += wv[0][1] * d;
-          bufA[ap * LDA + i * 2 + 1] += wv[1][1] * d;
-          bufA[(CHI + ap) * LDA + i * 2 + 0] = T(0);
-          bufA[(CHI + ap) * LDA + i * 2 + 1] = T(0);
-        }
-        __syncthreads();
-        break;   // M_{L-1} stays in bufA
+        bufA[col * LDA + i * 2 + 0] = wv[0][b] * d;
+        bufA[col * LDA + i * 2 + 1] = wv[1][b] * d;
       }
       __syncthreads();
-
-      // Householder QR of M (MQ x N2), reflectors stored below the diagonal (LAPACK style).
+      // Householder QR of M (MQ x N2); only R is kept, so reflectors are not stored.
       for (int j = 0; j < N2; ++j) {
         if (tid < WAVE) {
           T ss = 0;
@@ -245,15 +217,14 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
               t = (beta - alpha) / beta;
               scal = T(1) / (alpha - beta);
             }
-            tau[j] = t;
             misc[0] = beta;
             misc[1] = scal;
+            misc[3] = t;
           }
         }
         __syncthreads();
-        const T t = tau[j], scal = misc[1];
+        const T t = misc[3], scal = misc[1];
         if (t != T(0)) {
-          // columns k > j, four threads per column
           const int k = j + 1 + tid / 4;
           const int part = tid % 4;
           const bool act = (k < N2);
@@ -271,11 +242,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           }
         }
         __syncthreads();
-        for (int i = j + 1 + tid; i < MQ; i += NT) bufA[j * LDA + i] *= scal;
         if (tid == 0) bufA[j * LDA + j] = misc[0];
-        __syncthreads();
       }
-      // carry R (upper triangle) with a power-of-two rescale
+      __syncthreads();
+      // carry R (upper triangle) with a power-of-two rescale; keep it for the second sweep
       T mx = 0;
       for (int o = tid; o < N2 * N2; o += NT) {
         const int i = o % N2, k = o / N2;
@@ -284,77 +254,88 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       mx = block_max<NT>(mx, red);
       const int e = pow2_exponent(mx);
       log2acc += e;
+      if (tid == 0) rexp[c] = e;
+      T* rdst = rs + size_t(c) * N2 * N2;
       for (int o = tid; o < N2 * N2; o += NT) {
         const int i = o % N2, k = o / N2;
-        bufR[k * LDT + i] = (i <= k) ? T(ldexp(bufA[k * LDA + i], -e)) : T(0);
+        const T v = (i <= k) ? T(ldexp(bufA[k * LDA + i], -e)) : T(0);
+        bufR[k * LDT + i] = v;
+        rdst[o] = v;
       }
-      __syncthreads();
-      // form Q in place (backward accumulation of the reflectors)
-      for (int j = N2 - 1; j >= 0; --j) {
-        const T t = tau[j];
-        if (j < N2 - 1 && t != T(0)) {
-          const int k = j + 1 + tid / 4;
-          const int part = tid % 4;
-          const bool act = (k < N2);
-          T w = 0;
-          if (act) {
-            if (part == 0) w = bufA[k * LDA + j];
-            for (int i = j + 1 + part; i < MQ; i += 4) w += bufA[j * LDA + i] * bufA[k * LDA + i];
-          }
-          w += __shfl_xor(w, 1);
-          w += __shfl_xor(w, 2);
-          if (act) {
-            const T tw = t * w;
-            if (part == 0) bufA[k * LDA + j] -= tw;
-            for (int i = j + 1 + part; i < MQ; i += 4) bufA[k * LDA + i] -= tw * bufA[j * LDA + i];
-          }
-        }
-        __syncthreads();
-        for (int i = tid; i < MQ; i += NT) {
-          const T v = bufA[j * LDA + i];
-          bufA[j * LDA + i] = (i > j) ? -t * v : (i == j ? T(1) - t : T(0));
-        }
-        __syncthreads();
-      }
-      // Q_c to scratch (column-major, ld MQ)
-      T* q = qs + size_t(c) * MQ * N2;
-      for (int o = tid; o < MQ * N2; o += NT) q[o] = bufA[(o / MQ) * LDA + (o % MQ)];
     }
 
-    // ---------------- SVD sweep (right to left) ----------------
-    T* T0 = bufA;                 // N2 x N2 column-major, ld LDT: copy of T_c
-    T* Tw = bufA + size_t(N2) * LDT;
-    for (int c = L - 1; c >= 1; --c) {
+    // ---------------- right-to-left: truncation ----------------
+    // Carried Xt (N2 x CHI, column-major in bufR) with X_{c+1} = R_c Xt.  For the last site the
+    // right bond is summed, which is Xt[(b, 0)][0] = 1 for both b.
+    __syncthreads();
+    for (int o = tid; o < N2 * LDT; o += NT) bufR[o] = T(0);
+    __syncthreads();
+    if (tid == 0) { bufR[0 * LDT + 0] = T(1); bufR[0 * LDT + CHI] = T(1); }
+    for (int c = L - 1; c >= 0; --c) {
       __syncthreads();
-      if (c == L - 1) {
-        // T_{L-1}[i][(x, beta)] = M[(i,x)][(0, beta)]; only beta = 0 can be nonzero.
-        for (int o = tid; o < MQ; o += NT) bufR[o] = bufA[0 * LDA + o];
-        __syncthreads();
-        for (int o = tid; o < N2 * LDT; o += NT) Tw[o] = T(0);
-        __syncthreads();
-        for (int o = tid; o < MQ; o += NT) {
-          const int i = o / 2, x = o % 2;
-          Tw[(x * CHI + 0) * LDT + i] = bufR[o];
-        }
-      } else {
-        // T_c = Q_c X_{c+1}: rows (i,x) of Q_c, X in bufR (N2 x CHI, column-major ld LDT)
-        const T* q = qs + size_t(c) * MQ * N2;
-        for (int o = tid; o < MQ * CHI; o += NT) {
-          const int row = o % MQ, be = o / MQ;
-          T d = 0;
+      for (int e = tid; e < int(site); e += NT) bufS[e] = Ain[size_t(c) * site + e];
+      __syncthreads();
+      T wv[2][2], wh[2][2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) wv[x][b] = bond_weight<T>(jv, c, x, b, ep, em);
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          wh[a][b] = (c > 0) ? bond_weight<T>(jh, c - 1, a, b, ep, em) : (a == 0 ? T(1) : T(0));
+      // P_b = A_c[b] Xt_b (CHI x CHI each) into sc-free registers, then
+      // Z[(a,al)][(x,be)] = sum_b wh(a,b) wv(x,b) P_b[al][be]
+      for (int o = tid; o < CHI * CHI; o += NT) {
+        const int al = o % CHI, be = o / CHI;
+        T p0 = 0, p1 = 0;
 #pragma unroll 8
-          for (int j = 0; j < N2; ++j) d += q[size_t(j) * MQ + row] * bufR[be * LDT + j];
-          const int i = row / 2, x = row % 2;
-          Tw[(x * CHI + be) * LDT + i] = d;
+        for (int ap = 0; ap < CHI; ++ap) {
+          p0 += bufS[(0 * CHI + al) * CHI + ap] * bufR[be * LDT + ap];
+          p1 += bufS[(1 * CHI + al) * CHI + ap] * bufR[be * LDT + CHI + ap];
         }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int x = 0; x < 2; ++x)
+            Zb[(x * CHI + be) * LDT + a * CHI + al] = wh[a][0] * wv[x][0] * p0 + wh[a][1] * wv[x][1] * p1;
       }
       __syncthreads();
-      for (int o = tid; o < N2 * LDT; o += NT) T0[o] = Tw[o];
+      if (c == 0) {
+        // site 0: the left bond is (a = 0, alpha = 0); A_0[x][0][be] = Z[(0,0)][(x,be)]
+        T part = 0;
+        for (int o = tid; o < 2 * CHI; o += NT) {
+          const T d = Zb[o * LDT + 0];
+          sc[o] = d;
+          part += d * d;
+        }
+        const T nrm2 = block_sum<NT>(part, red);
+        const T nrm = sqrt(nrm2);
+        for (int o = tid; o < int(site); o += NT) {
+          const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
+          Aout[o] = (al == 0 && nrm > T(0)) ? sc[x * CHI + be] / nrm : T(0);
+        }
+        lambda += double(log2acc) * 0.69314718055994530942 + log(double(nrm));
+        if (tid == 0) R.lognorm[r - 1] = lambda;
+        break;
+      }
+      // R_{c-1} into bufR (Xt is no longer needed), then T = R_{c-1} Z (upper triangular R)
+      const T* rsrc = rs + size_t(c - 1) * N2 * N2;
+      for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = rsrc[o];
+      __syncthreads();
+      for (int o = tid; o < N2 * N2; o += NT) {
+        const int i = o % N2, col = o / N2;
+        T d = 0;
+        for (int a = i; a < N2; ++a) d += bufR[a * LDT + i] * Zb[col * LDT + a];
+        Tw[col * LDT + i] = d;
+      }
+      __syncthreads();
       // column norms, Frobenius norm
       for (int k = tid; k < N2; k += NT) {
-        T s = 0;
-        for (int i = 0; i < N2; ++i) s += Tw[k * LDT + i] * Tw[k * LDT + i];
-        cn2[k] = s;
+        T s2 = 0;
+        for (int i = 0; i < N2; ++i) s2 += Tw[k * LDT + i] * Tw[k * LDT + i];
+        cn2[k] = s2;
         perm[k] = k;
       }
       __syncthreads();
@@ -510,10 +491,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       }
       // row norms and descending order
       for (int i = tid; i < N2; i += NT) {
-        T s = 0;
+        T s2 = 0;
         if (i < rank)
-          for (int k = 0; k < N2; ++k) s += bufR[i * LDT + k] * bufR[i * LDT + k];
-        sc[i] = s;
+          for (int k = 0; k < N2; ++k) s2 += bufR[i * LDT + k] * bufR[i * LDT + k];
+        sc[i] = s2;
       }
       __syncthreads();
       for (int i = tid; i < rank; i += NT) {
@@ -543,13 +524,15 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
         bout[o] = bufS[al * N2 + x * CHI + be];
       }
-      // X_c = T0 V^T (N2 x CHI) into bufR (column-major, ld LDT), power-of-two rescale
+      // Xt_{c} = 2^-e_{c-1} Z V^T (N2 x CHI) into bufR (column-major, ld LDT), rescaled
+      const int ec = rexp[c - 1];
       T mx = 0;
       for (int o = tid; o < N2 * CHI; o += NT) {
         const int j = o % N2, al = o / N2;
         T d = 0;
 #pragma unroll 8
-        for (int col = 0; col < N2; ++col) d += T0[col * LDT + j] * bufS[al * N2 + col];
+        for (int col = 0; col < N2; ++col) d += Zb[col * LDT + j] * bufS[al * N2 + col];
+        d = T(ldexp(d, -ec));
         bufR[al * LDT + j] = d;
         mx = fmax(mx, fabs(d));
       }
@@ -560,29 +543,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         const int j = o % N2, al = o / N2;
         bufR[al * LDT + j] = T(ldexp(bufR[al * LDT + j], -e));
       }
-    }
-    // ---------------- site 0 ----------------
-    __syncthreads();
-    {
-      const T* q = qs;   // Q_0, rows (0, x)
-      // A_0[x][0][be] = sum_j Q_0[(0,x)][j] X[j][be]
-      T part = 0;
-      for (int o = tid; o < 2 * CHI; o += NT) {
-        const int x = o / CHI, be = o % CHI;
-        T d = 0;
-        for (int j = 0; j < N2; ++j) d += q[size_t(j) * MQ + x] * bufR[be * LDT + j];
-        sc[o] = d;
-        part += d * d;
-      }
-      const T nrm2 = block_sum<NT>(part, red);
-      const T nrm = sqrt(nrm2);
-      T* bout = Aout;
-      for (int o = tid; o < int(site); o += NT) {
-        const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
-        bout[o] = (al == 0 && nrm > T(0)) ? sc[x * CHI + be] / nrm : T(0);
-      }
-      lambda += double(log2acc) * 0.69314718055994530942 + log(double(nrm));
-      if (tid == 0) R.lognorm[r - 1] = lambda;
+      // clear the rows of Xt beyond CHI columns (bufR columns CHI.. hold nothing needed)
     }
     __syncthreads();
   }
@@ -592,32 +553,28 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     __syncthreads();
     const T* A0 = env;   // row 0
     const uint64_t* jh0 = R.Jh;
-    // v[s][be] for the current site, in sc (2*CHI); start with site 0
     for (int o = tid; o < 2 * CHI; o += NT) sc[o] = A0[(o / CHI) * CHI * CHI + (o % CHI)];
     double logacc = 0;
     for (int c = 1; c < L; ++c) {
       __syncthreads();
       const T* A = A0 + size_t(c) * site;
       T mx = 0;
-      T vals[2] = {0, 0};
-      int cnt = 0;
-      for (int o = tid; o < 2 * CHI; o += NT, ++cnt) {
+      T val = 0;
+      const int o = tid;
+      if (o < 2 * CHI) {
         const int sp = o / CHI, be = o % CHI;
-        T d = 0;
-        for (int s = 0; s < 2; ++s) {
-          const T w = bond_weight<T>(jh0, c - 1, s, sp, ep, em);
+        for (int s2 = 0; s2 < 2; ++s2) {
+          const T w = bond_weight<T>(jh0, c - 1, s2, sp, ep, em);
           T dd = 0;
-          for (int al = 0; al < CHI; ++al) dd += sc[s * CHI + al] * A[(sp * CHI + al) * CHI + be];
-          d += w * dd;
+          for (int al = 0; al < CHI; ++al) dd += sc[s2 * CHI + al] * A[(sp * CHI + al) * CHI + be];
+          val += w * dd;
         }
-        if (cnt < 2) vals[cnt] = d;
-        mx = fmax(mx, fabs(d));
+        mx = fabs(val);
       }
       mx = block_max<NT>(mx, red);
       const int e = pow2_exponent(mx);
       logacc += double(e) * 0.69314718055994530942;
-      cnt = 0;
-      for (int o = tid; o < 2 * CHI; o += NT, ++cnt) sc[o] = T(ldexp(vals[cnt], -e));
+      if (o < 2 * CHI) sc[o] = T(ldexp(val, -e));
     }
     __syncthreads();
     if (tid == 0) {
@@ -676,7 +633,7 @@ hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n
 
 size_t env_build_scratch_bytes(tnmc_precision prec, int chi, int L) {
   const size_t elem = (prec == TNMC_FP64) ? 8 : 4;
-  return size_t(L) * 4 * chi * 2 * chi * elem;
+  return size_t(L) * 2 * chi * 2 * chi * elem;   // the carried R factor of every site
 }
 
 }  // namespace tnmc

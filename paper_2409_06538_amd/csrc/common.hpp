@@ -55,19 +55,93 @@ __device__ __forceinline__ double philox_uniform(uint64_t k0, uint64_t k1, uint6
 
 enum : uint64_t { STREAM_COUPLINGS = 0, STREAM_PROPOSAL = 1, STREAM_ACCEPT = 2 };
 
-// Sum over a whole wavefront (all 64 lanes end with the total).
+// Cross-lane moves within a row of 16 lanes (DPP).  Controls: quad_perm [1,0,3,2] = 0xB1,
+// quad_perm [2,3,0,1] = 0x4E, row_half_mirror = 0x141, row_mirror = 0x140.
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_i<CTRL>(int(b & 0xffffffffll));
+  const int hi = dpp_i<CTRL>(int(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v) {
+  return dpp_i<CTRL>(v);
+}
+
+__device__ __forceinline__ int readlane_i(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float readlane_v(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane_v(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(int(b & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane(int(b >> 32), l);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ int readlane_v(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// Sum over aligned groups of G lanes (G a power of two <= 64); every lane of a group gets the
+// group's sum.  All lanes of a group must be active.
+template <int G, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+  if (G >= 2) v += dpp<0xB1>(v);
+  if (G >= 4) v += dpp<0x4E>(v);
+  if (G >= 8) v += dpp<0x141>(v);
+  if (G >= 16) v += dpp<0x140>(v);
+  if (G >= 32) v += __shfl_xor(v, 16);
+  if (G >= 64) v += __shfl_xor(v, 32);
+  return v;
+}
+
+// Sum / max over a whole wavefront (all 64 lanes active); every lane gets the result.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  return v;
+  v = group_sum<16>(v);
+  return (readlane_v(v, 0) + readlane_v(v, 16)) + (readlane_v(v, 32) + readlane_v(v, 48));
 }
 
 template <typename T>
 __device__ __forceinline__ T wave_max(T v) {
+  v = fmax(v, dpp<0xB1>(v));
+  v = fmax(v, dpp<0x4E>(v));
+  v = fmax(v, dpp<0x141>(v));
+  v = fmax(v, dpp<0x140>(v));
+  return fmax(fmax(readlane_v(v, 0), readlane_v(v, 16)), fmax(readlane_v(v, 32), readlane_v(v, 48)));
+}
+
+// Arg-max over a whole wavefront (ties -> smaller index); every lane gets (value, index).
+template <typename T>
+__device__ __forceinline__ void wave_argmax(T& v, int& i) {
+#define TNMC_ARGMAX_STEP(CTRL)                                       \
+  {                                                                  \
+    const T ov = dpp<CTRL>(v);                                       \
+    const int oi = dpp<CTRL>(i);                                     \
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }           \
+  }
+  TNMC_ARGMAX_STEP(0xB1)
+  TNMC_ARGMAX_STEP(0x4E)
+  TNMC_ARGMAX_STEP(0x141)
+  TNMC_ARGMAX_STEP(0x140)
+#undef TNMC_ARGMAX_STEP
+  T bv = readlane_v(v, 0);
+  int bi = readlane_v(i, 0);
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
-  return v;
+  for (int r = 1; r < 4; ++r) {
+    const T ov = readlane_v(v, 16 * r);
+    const int oi = readlane_v(i, 16 * r);
+    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+  }
+  v = bv;
+  i = bi;
 }
 
 // Block-wide sum for NT threads (NT a multiple of 64); `red` holds NT/64 entries of LDS.

@@ -1,21 +1,24 @@
-// Boundary-MPS environment build (Sec. II B of arXiv:2409.06538): row-transfer MPO applied to
-// an MPS, then canonical SVD compression back to bond dimension CHI.
+// Boundary-MPS environment build (Sec. II B of arXiv:2409.06538): the row-transfer MPO applied
+// to an MPS, then canonical SVD compression back to bond dimension CHI.
 //
-// One workgroup owns one realization and walks its rows r = L-1 .. 1 (the bottom environment
-// E_{r-1} needs E_r).  Per row:
-//   QR sweep, c = 0 .. L-1: M_c = R_{c-1} At_c, where At_c is the site tensor of the row operator
-//     applied to E_r (left bond (a, alpha), physical x, right bond (b, alpha')),
-//       At_c[(a,alpha), x, (b,alpha')] = wh(a,b) wv(x,b) A_c[b][alpha][alpha'],
-//     built on the fly from two coupling bits; M_c (4 CHI x 2 CHI) is factorised by Householder
-//     QR; Q_c goes to global scratch, R_c (rescaled by a power of two) is carried.
-//   SVD sweep, c = L-1 .. 1: T_c = Q_c X_{c+1} viewed as (2 CHI) x (2 x CHI); its right singular
-//     subspace is found by QR with column pivoting (stopping at the numerical rank) followed by
-//     one-sided Jacobi on the rows of the triangular factor; the CHI leading right singular
-//     vectors become site c of E_{r-1}, and X_c = T_c V_k is carried left.
-//   Site 0 keeps the norm, which is divided out: lambda_{r-1} = lambda_r + (power-of-two
-//   exponents) ln 2 + ln ||A_0||.
-// This reaches the same truncated state as the textbook QR-then-SVD sweep: every kept subspace is
-// the span of the CHI leading right singular vectors of the same matrix.
+// One workgroup owns one realization and walks its rows r = L-1 .. 1 (E_{r-1} needs E_r).  The
+// operator-applied site tensor is never stored:
+//   At_c[(a,alpha), x, (b,alpha')] = wh(a,b) wv(x,b) A_c[b][alpha][alpha'],
+// with wh, wv the Boltzmann weights (Eq. (7)) of the horizontal bond (c-1, c) of row r and of the
+// vertical bond between rows r-1 and r at column c.  Per row:
+//   left to right, c = 0 .. L-2: M_c = R_{c-1} At_c (rows (i, x), columns (b, alpha')), whose R
+//     factor R_c (Householder) is kept, rescaled by 2^-e_c.  This is the QR sweep of the canonical
+//     compression with Q_c never formed.
+//   right to left, c = L-1 .. 1: with X_{c+1} = R_c Xt_{c+1} the matrix of the SVD step is
+//     T_c = Q_c X_{c+1} = R_{c-1} Z_c,  Z_c[(a,alpha), (x,beta)] = sum_b wh wv (A_c[b] Xt_b)[alpha][beta];
+//     its CHI leading right singular vectors V become site c of E_{r-1}, and
+//     Xt_c = 2^-e_{c-1} Z_c V^T.  The SVD step is QR with column pivoting (stopping at the numerical
+//     rank), one-sided Jacobi on the rows of the triangular factor, and a Gram-Schmidt pass that
+//     makes the kept rows exactly orthonormal.
+//   site 0 keeps the norm, which is divided out: lambda_{r-1} = lambda_r + (sum of exponents) ln 2
+//     + ln ||A_0||.
+// Every matrix is held in LDS; GEMM-shaped products use register tiles; the factorisations use one
+// workgroup barrier per column.
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
@@ -27,11 +30,11 @@ template <typename T>
 struct JacobiTol;
 template <>
 struct JacobiTol<double> {
-  // rotate a row pair while |c| > tol * ||T||_F * max(|row_p|, |row_q|)
+  // rotate a row pair while |c| > rot * ||T||_F * max(|row_p|, |row_q|)
   static constexpr double rot = 1e-14;
   // columns whose remaining norm is below rank * ||T||_F are dropped by the pivoted QR
   static constexpr double rank = 1e-15;
-  // a kept row whose Cholesky pivot (squared residual norm) falls below eta is dependent
+  // a kept row whose Gram-Schmidt residual norm^2 falls below eta is dependent
   static constexpr double eta = 1e-12;
 };
 template <>
@@ -41,102 +44,228 @@ struct JacobiTol<float> {
   static constexpr float eta = 1e-5f;
 };
 
-// Orthonormalise rows 0..k-1 of V (row stride ldv, n columns) in place by Cholesky QR applied
-// twice; G (k x (CHI+1) workspace) holds the Gram matrix and then its Cholesky factor.  Rows are
-// processed in order; a row whose pivot falls below eta lies in the span of the earlier rows (to
-// rounding) and is set to zero.  The span of the surviving rows is unchanged.
-template <typename T, int CHI, int NT>
-__device__ void cholqr2_rows(T* V, int ldv, int n, int k, T* G, T eta) {
-  constexpr int LDG = CHI + 1;
-  const int tid = threadIdx.x;
-  for (int pass = 0; pass < 2; ++pass) {
-    __syncthreads();
-    for (int o = tid; o < k * k; o += NT) {
-      const int a = o / k, b = o % k;
-      if (b <= a) {
-        T d = 0;
-        for (int j = 0; j < n; ++j) d += V[a * ldv + j] * V[b * ldv + j];
-        G[a * LDG + b] = d;
-      }
-    }
-    __syncthreads();
-    if (tid < WAVE) {
-      for (int a = 0; a < k; ++a) {
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const T piv = G[a * LDG + a];
-        const bool alive = piv > eta;
-        const T l = alive ? sqrt(piv) : T(1);
-        for (int i = a + 1 + tid; i < k; i += WAVE) G[i * LDG + a] = alive ? G[i * LDG + a] / l : T(0);
-        if (tid == 0) G[a * LDG + a] = alive ? l : T(0);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        const int m = k - a - 1;
-        for (int o = tid; o < m * m; o += WAVE) {
-          const int i = a + 1 + o / m, j = a + 1 + o % m;
-          if (j <= i) G[i * LDG + j] -= G[i * LDG + a] * G[j * LDG + a];
-        }
-      }
-    }
-    __syncthreads();
-    for (int j = tid; j < n; j += NT) {
-      for (int a = 0; a < k; ++a) {
-        const T laa = G[a * LDG + a];
-        T v = V[a * ldv + j];
-        for (int b = 0; b < a; ++b) v -= G[a * LDG + b] * V[b * ldv + j];
-        V[a * ldv + j] = (laa > T(0)) ? v / laa : T(0);
-      }
-    }
-  }
-  __syncthreads();
+constexpr int MAX_SWEEPS = 40;
+// 32 threads per unit of CHI, at most 512 (8 waves, two per SIMD, so that LDS and barrier latency
+// of one wave overlaps with the other's work while each keeps 256 registers).
+__host__ __device__ constexpr int env_threads(int chi) {
+  return (32 * chi < 64) ? 64 : (32 * chi > 512 ? 512 : 32 * chi);
+}
+// threads per column in the Householder updates (a power of two; NT = TPC * 2 CHI)
+__host__ __device__ constexpr int env_tpc(int chi) { return env_threads(chi) / (2 * chi); }
+// threads per row pair in the Jacobi sweep and per row in the Gram-Schmidt pass
+__host__ __device__ constexpr int env_tpp(int chi) {
+  return (env_threads(chi) / chi < 2 * chi) ? env_threads(chi) / chi
+                                            : ((2 * chi < 32) ? 2 * chi : 32);
 }
 
-constexpr int MAX_SWEEPS = 40;
-
-__host__ __device__ constexpr int env_threads(int chi) { return (8 * chi < 64) ? 64 : 8 * chi; }
-
-// Shared-memory carve-up for one workgroup.
 template <typename T, int CHI>
 struct EnvSmem {
   static constexpr int N2 = 2 * CHI;     // bond of the operator-applied MPS; SVD matrix side
-  static constexpr int MQ = 4 * CHI;     // rows of the QR-sweep matrix
-  static constexpr int LDA = MQ + 1;     // column stride of M / Q
-  static constexpr int LDT = N2 + 1;     // column stride of T, T0, R, X; row stride of J
+  static constexpr int MQ = 4 * CHI;     // rows of M_c
+  static constexpr int LDA = MQ + 4;     // column stride of M (column-major)
+  static constexpr int LDT = N2 + 4;     // column stride of T, R, Xt (column-major); row stride of J
+  static constexpr int LDZ = N2 + 4;     // row stride of Z (row-major)
+  static constexpr int LDG = CHI + 1;    // row stride of the Gram / Cholesky factors
   static constexpr int NT = env_threads(CHI);
-  static constexpr size_t bufA = size_t(2) * N2 * LDT > size_t(LDA) * N2 ? size_t(2) * N2 * LDT
-                                                                         : size_t(LDA) * N2;
+  static constexpr int NW = NT / 64;
+  static constexpr int TILE = 2;
+  static constexpr size_t bufA_left = size_t(LDA) * N2;
+  static constexpr size_t bufA_right = size_t(N2) * LDZ + size_t(N2) * LDT;
+  // + MQ + N2: rows read past the end of the last column (values masked) stay in bounds
+  static constexpr size_t bufA = (bufA_left > bufA_right ? bufA_left : bufA_right) + MQ + N2;
   static constexpr size_t bufR = size_t(N2) * LDT;
   static constexpr size_t bufS = size_t(2) * CHI * CHI;
-  static constexpr size_t reals = bufA + bufR + bufS + 3 * N2 + NT / 64 + 8;
-  static constexpr size_t ints = 2 * N2 + 8 + 1024;
+  static constexpr size_t reals = bufA + bufR + bufS + 4 * N2 + 2 * NW + NT / 64 + 8;
+  static constexpr size_t ints = 3 * N2 + 2 * NW + 8 + 1024;
   static constexpr size_t bytes = reals * sizeof(T) + ints * sizeof(int);
 };
 
 template <typename T>
 __device__ __forceinline__ T bond_weight(const uint64_t* row_bits, int c, int sa, int sb, T ep,
                                          T em) {
-  // exp(beta J s_a s_b): J = -1 iff bit c is set; spins index 0 <-> +1, 1 <-> -1.
+  // exp(beta J s_a s_b): J = -1 iff bit c is set; spin index 0 <-> +1, 1 <-> -1.
   const bool af = (row_bits[c >> 6] >> (c & 63)) & 1ull;
   const bool parallel = (sa == sb);
   return (parallel != af) ? ep : em;
+}
+
+// C(M x N) = A(M x KD) B(KD x N) with TM x TN register tiles per thread; M % TM == N % TN == 0.
+// fa(i, k), fb(k, j) load operands, fc(i, j, v) stores a result.
+template <int TM, int TN, int KD, int NT, typename T, typename FA, typename FB, typename FC>
+__device__ __forceinline__ void gemm_tiles(int M, int N, FA fa, FB fb, FC fc) {
+  const int tm = M / TM, tn = N / TN;
+  for (int t = threadIdx.x; t < tm * tn; t += NT) {
+    const int i0 = (t % tm) * TM, j0 = (t / tm) * TN;
+    T acc[TM][TN];
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+      for (int s = 0; s < TN; ++s) acc[r][s] = T(0);
+#pragma unroll 8
+    for (int k = 0; k < KD; ++k) {
+      T av[TM], bv[TN];
+#pragma unroll
+      for (int r = 0; r < TM; ++r) av[r] = fa(i0 + r, k);
+#pragma unroll
+      for (int s = 0; s < TN; ++s) bv[s] = fb(k, j0 + s);
+#pragma unroll
+      for (int r = 0; r < TM; ++r)
+#pragma unroll
+        for (int s = 0; s < TN; ++s) acc[r][s] += av[r] * bv[s];
+    }
+#pragma unroll
+    for (int r = 0; r < TM; ++r)
+#pragma unroll
+      for (int s = 0; s < TN; ++s) fc(i0 + r, j0 + s, acc[r][s]);
+  }
+}
+
+// Householder QR of the column-major MQ x N2 matrix A (ld LDA); only R is produced: its strict
+// upper triangle stays in A, its diagonal goes to diag[].  One barrier per column: the threads that
+// update column j+1 also produce its sub-diagonal norm^2 for the next step (double-buffered in ss2),
+// and every thread derives the reflector of column j from it.
+template <typename T, int MQ, int N2, int LDA, int NT, int TPC>
+__device__ void householder_r(T* A, T* diag, T* ss2) {
+  constexpr int ER = (MQ + TPC - 1) / TPC;
+  const int tid = threadIdx.x;
+  const int g = tid / TPC, part = tid % TPC;   // group g owns column g
+  if (g == 0) {
+    T s = 0;
+    for (int i = 1 + part; i < MQ; i += TPC) s += A[i] * A[i];
+    s = group_sum<TPC>(s);
+    if (part == 0) ss2[0] = s;
+  }
+  __syncthreads();
+  for (int j = 0; j < N2; ++j) {
+    const T alpha = A[j * LDA + j];
+    const T ss = ss2[j & 1];
+    T tau = 0, beta = alpha, scal = 0;
+    if (ss > T(0)) {
+      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+      tau = (beta - alpha) / beta;
+      scal = T(1) / (alpha - beta);
+    }
+    if (tid == 0) diag[j] = beta;
+    if (g > j && g < N2) {
+      T v[ER], m[ER];
+      const T a0 = A[g * LDA + j];
+      T w = (part == 0) ? a0 : T(0);
+#pragma unroll
+      for (int e = 0; e < ER; ++e) {
+        const int i = j + 1 + part + TPC * e;   // may run past MQ: read in bounds, value masked
+        const T vi = A[j * LDA + i], mi = A[g * LDA + i];
+        const bool ok = i < MQ;
+        v[e] = ok ? vi * scal : T(0);
+        m[e] = ok ? mi : T(0);
+      }
+#pragma unroll
+      for (int e = 0; e < ER; ++e) w += v[e] * m[e];
+      w = group_sum<TPC>(w);
+      const T tw = tau * w;
+      if (part == 0) A[g * LDA + j] -= tw;
+      T nn = 0;
+#pragma unroll
+      for (int e = 0; e < ER; ++e) {
+        const int i = j + 1 + part + TPC * e;
+        if (i < MQ) {
+          const T nv = m[e] - tw * v[e];
+          A[g * LDA + i] = nv;
+          if (i > j + 1) nn += nv * nv;
+        }
+      }
+      nn = group_sum<TPC>(nn);
+      if (g == j + 1 && part == 0) ss2[(j + 1) & 1] = nn;
+    }
+    __syncthreads();
+  }
+}
+
+// Orthonormalise rows 0..k-1 of V (CHI x N2, row-major, ld N2) in place by modified Gram-Schmidt
+// applied twice, one barrier per row.  A group of TPP threads owns one row.  A row whose residual
+// norm^2 falls below eta (the rows start with unit norm) lies in the span of the earlier rows to
+// rounding and is set to zero; the span of the others is unchanged.
+template <typename T, int CHI, int NT>
+__device__ void mgs2_rows(T* V, int k, T eta) {
+  constexpr int N2 = 2 * CHI, TPP = env_tpp(CHI), EPR = (N2 + TPP - 1) / TPP;
+  const int grp = threadIdx.x / TPP, l = threadIdx.x % TPP;
+  const bool mine = grp < k;
+  T vb[EPR];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < EPR; ++e) {
+    const int j = l + TPP * e;
+    vb[e] = (mine && j < N2) ? V[grp * N2 + j] : T(0);
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int a = 0; a < k; ++a) {
+      T va[EPR];
+      T n2 = 0, d = 0;
+#pragma unroll
+      for (int e = 0; e < EPR; ++e) {
+        const int j = l + TPP * e;
+        const T ra = V[a * N2 + (j < N2 ? j : 0)];
+        va[e] = (mine && grp >= a && j < N2) ? (grp == a ? vb[e] : ra) : T(0);
+        n2 += va[e] * va[e];
+        d += va[e] * vb[e];
+      }
+      n2 = group_sum<TPP>(n2);
+      d = group_sum<TPP>(d);
+      if (mine && grp > a && n2 > eta) {
+        const T f = d / n2;
+#pragma unroll
+        for (int e = 0; e < EPR; ++e) {
+          const int j = l + TPP * e;
+          vb[e] -= f * va[e];
+          if (j < N2) V[grp * N2 + j] = vb[e];
+        }
+      }
+      if (mine && grp == a && !(n2 > eta)) {
+#pragma unroll
+        for (int e = 0; e < EPR; ++e) vb[e] = T(0);
+      }
+      __syncthreads();
+    }
+    T n2 = 0;
+#pragma unroll
+    for (int e = 0; e < EPR; ++e) n2 += vb[e] * vb[e];
+    n2 = group_sum<TPP>(n2);
+    const T f = (n2 > T(0)) ? T(1) / sqrt(n2) : T(0);
+#pragma unroll
+    for (int e = 0; e < EPR; ++e) {
+      const int j = l + TPP * e;
+      vb[e] *= f;
+      if (mine && j < N2) V[grp * N2 + j] = vb[e];
+    }
+    __syncthreads();
+  }
 }
 
 template <typename T, int CHI>
 __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevReal* reals,
                                                                      double* lnZ_out) {
   using S = EnvSmem<T, CHI>;
-  constexpr int N2 = S::N2, MQ = S::MQ, LDA = S::LDA, LDT = S::LDT, NT = S::NT;
-  constexpr int EPT = (N2 + 7) / 8;   // elements per thread of a Jacobi row
+  constexpr int N2 = S::N2, MQ = S::MQ, LDA = S::LDA, LDT = S::LDT, LDZ = S::LDZ, LDG = S::LDG;
+  constexpr int NT = S::NT, NW = S::NW, TL = S::TILE;
+  constexpr int TPP = env_tpp(CHI);   // threads per Jacobi row pair
+  constexpr int TPC = env_tpc(CHI);   // threads per column in the QR updates
+  constexpr int EPT = (N2 + TPP - 1) / TPP;   // elements per thread of a Jacobi row
+  constexpr int ER2 = (N2 + TPC - 1) / TPC;   // rows per thread in the pivoted QR
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* bufA = reinterpret_cast<T*>(smem_raw);
   T* bufR = bufA + S::bufA;
   T* bufS = bufR + S::bufR;
-  T* cn2 = bufS + S::bufS;          // N2 column norms^2
-  T* sc = cn2 + N2;                 // 2 N2 scalars scratch
-  T* red = sc + 2 * N2;             // NT/64
+  T* diag = bufS + S::bufS;         // N2
+  T* sc = diag + N2;                // 2 N2 scalars scratch
+  T* cnv = sc + 2 * N2;             // N2 (ss double buffer lives in its first 2 entries too)
+  T* candv = cnv + N2;              // 2 x NW argmax candidates
+  T* red = candv + 2 * NW;          // NT/64
   T* misc = red + NT / 64;          // 8
-  int* perm = reinterpret_cast<int*>(misc + 8);   // N2
+  int* perm = reinterpret_cast<int*>(misc + 8);   // N2 logical -> physical column
   int* ord = perm + N2;                           // N2
-  int* imisc = ord + N2;                          // 8
-  int* rexp = imisc + 8;                          // MAX_L exponents of the carried R_c
+  int* used = ord + N2;                           // N2
+  int* candi = used + N2;                         // 2 x NW
+  int* imisc = candi + 2 * NW;                    // 8
+  int* rexp = imisc + 8;                          // exponents of the carried R_c (L <= 1024)
 
   const int tid = threadIdx.x;
   const DevReal R = reals[blockIdx.x];
@@ -147,11 +276,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   T* rs = reinterpret_cast<T*>(R.ws);                 // L x N2 x N2 scratch: R_c column-major
   const size_t site = size_t(2) * CHI * CHI;
   const size_t rowst = site * L;
-  T* Zb = bufA;                      // Z_c: N2 x N2 column-major (rows (a,alpha), cols (x,beta))
-  T* Tw = bufA + size_t(N2) * LDT;   // T_c: N2 x N2 column-major
+  T* Zr = bufA;                                       // Z_c: N2 x N2 row-major, ld LDZ
+  T* Tw = bufA + size_t(N2) * LDZ;                    // T_c: N2 x N2 column-major, ld LDT
 
-  // E_{L-1} = 1: every site is 1/sqrt(2) at [sigma][0][0].
-  for (size_t e = tid; e < rowst; e += NT) {
+  for (size_t e = tid; e < rowst; e += NT) {         // E_{L-1} = 1
     const size_t inner = e % site;
     const int a = int((inner % (CHI * CHI)) / CHI), b = int(inner % CHI);
     env[size_t(L - 1) * rowst + e] = (a == 0 && b == 0) ? T(0.70710678118654752440) : T(0);
@@ -166,90 +294,46 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     const uint64_t* jv = R.Jv + size_t(r - 1) * W;    // vertical bonds between rows r-1 and r
     long long log2acc = 0;
 
-    // ---------------- left-to-right: R factors only ----------------
-    // M_c = R_{c-1} At_c (rows (i,x), cols (b,ap)); R_c = R factor of M_c, rescaled by 2^-e_c.
+    // ---------------- left to right: R factors ----------------
     for (int c = 0; c < L - 1; ++c) {
       __syncthreads();
       for (int e = tid; e < int(site); e += NT) bufS[e] = Ain[size_t(c) * site + e];
       __syncthreads();
-      T wv[2][2], wh[2][2];
+      T wv[2][2];
 #pragma unroll
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int b = 0; b < 2; ++b) wv[x][b] = bond_weight<T>(jv, c, x, b, ep, em);
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) wh[a][b] = (c > 0) ? bond_weight<T>(jh, c - 1, a, b, ep, em) : T(0);
-      for (int o = tid; o < N2 * N2; o += NT) {
-        const int i = o % N2;
-        const int col = o / N2;
-        const int b = col / CHI, ap = col % CHI;
-        T d = 0;
-        if (c == 0) {
-          d = (i < CHI) ? bufS[(b * CHI + i) * CHI + ap] : T(0);
-        } else {
-          const T wa = wh[0][b], wb = wh[1][b];
-#pragma unroll 8
-          for (int al = 0; al < CHI; ++al) {
-            const T p = bufR[al * LDT + i] * wa + bufR[(CHI + al) * LDT + i] * wb;
-            d += p * bufS[(b * CHI + al) * CHI + ap];
-          }
+      if (c == 0) {
+        for (int o = tid; o < N2 * N2; o += NT) {
+          const int i = o % N2, col = o / N2, b = col / CHI, ap = col % CHI;
+          const T d = (i < CHI) ? bufS[(b * CHI + i) * CHI + ap] : T(0);
+          bufA[col * LDA + 2 * i] = wv[0][b] * d;
+          bufA[col * LDA + 2 * i + 1] = wv[1][b] * d;
         }
-        bufA[col * LDA + i * 2 + 0] = wv[0][b] * d;
-        bufA[col * LDA + i * 2 + 1] = wv[1][b] * d;
+      } else {
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const T wa = bond_weight<T>(jh, c - 1, 0, b, ep, em);
+          const T wb = bond_weight<T>(jh, c - 1, 1, b, ep, em);
+          const T w0 = wv[0][b], w1 = wv[1][b];
+          gemm_tiles<TL, TL, CHI, NT, T>(
+              N2, CHI,
+              [&](int i, int al) { return bufR[al * LDT + i] * wa + bufR[(CHI + al) * LDT + i] * wb; },
+              [&](int al, int ap) { return bufS[(b * CHI + al) * CHI + ap]; },
+              [&](int i, int ap, T d) {
+                bufA[(b * CHI + ap) * LDA + 2 * i] = w0 * d;
+                bufA[(b * CHI + ap) * LDA + 2 * i + 1] = w1 * d;
+              });
+        }
       }
       __syncthreads();
-      // Householder QR of M (MQ x N2); only R is kept, so reflectors are not stored.
-      for (int j = 0; j < N2; ++j) {
-        if (tid < WAVE) {
-          T ss = 0;
-          for (int i = j + 1 + tid; i < MQ; i += WAVE) {
-            const T v = bufA[j * LDA + i];
-            ss += v * v;
-          }
-          ss = wave_sum(ss);
-          if (tid == 0) {
-            const T alpha = bufA[j * LDA + j];
-            T t = 0, beta = alpha, scal = 0;
-            if (ss > T(0)) {
-              beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-              t = (beta - alpha) / beta;
-              scal = T(1) / (alpha - beta);
-            }
-            misc[0] = beta;
-            misc[1] = scal;
-            misc[3] = t;
-          }
-        }
-        __syncthreads();
-        const T t = misc[3], scal = misc[1];
-        if (t != T(0)) {
-          const int k = j + 1 + tid / 4;
-          const int part = tid % 4;
-          const bool act = (k < N2);
-          T w = 0;
-          if (act) {
-            if (part == 0) w = bufA[k * LDA + j];
-            for (int i = j + 1 + part; i < MQ; i += 4) w += bufA[j * LDA + i] * scal * bufA[k * LDA + i];
-          }
-          w += __shfl_xor(w, 1);
-          w += __shfl_xor(w, 2);
-          if (act) {
-            const T tw = t * w;
-            if (part == 0) bufA[k * LDA + j] -= tw;
-            for (int i = j + 1 + part; i < MQ; i += 4) bufA[k * LDA + i] -= tw * bufA[j * LDA + i] * scal;
-          }
-        }
-        __syncthreads();
-        if (tid == 0) bufA[j * LDA + j] = misc[0];
-      }
-      __syncthreads();
-      // carry R (upper triangle) with a power-of-two rescale; keep it for the second sweep
+      householder_r<T, MQ, N2, LDA, NT, TPC>(bufA, diag, cnv);
+      // carry R with a power-of-two rescale; keep it for the second sweep
       T mx = 0;
       for (int o = tid; o < N2 * N2; o += NT) {
         const int i = o % N2, k = o / N2;
-        if (i <= k) mx = fmax(mx, fabs(bufA[k * LDA + i]));
+        if (i <= k) mx = fmax(mx, fabs(i == k ? diag[i] : bufA[k * LDA + i]));
       }
       mx = block_max<NT>(mx, red);
       const int e = pow2_exponent(mx);
@@ -258,19 +342,19 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       T* rdst = rs + size_t(c) * N2 * N2;
       for (int o = tid; o < N2 * N2; o += NT) {
         const int i = o % N2, k = o / N2;
-        const T v = (i <= k) ? T(ldexp(bufA[k * LDA + i], -e)) : T(0);
+        const T v = (i < k) ? T(ldexp(bufA[k * LDA + i], -e)) : (i == k ? T(ldexp(diag[i], -e)) : T(0));
         bufR[k * LDT + i] = v;
         rdst[o] = v;
       }
     }
 
-    // ---------------- right-to-left: truncation ----------------
-    // Carried Xt (N2 x CHI, column-major in bufR) with X_{c+1} = R_c Xt.  For the last site the
-    // right bond is summed, which is Xt[(b, 0)][0] = 1 for both b.
+    // ---------------- right to left: truncation ----------------
+    // Xt (N2 x CHI column-major in bufR); for the last site the right bond is summed over b,
+    // i.e. Xt[(b, 0)][0] = 1 for both b.
     __syncthreads();
     for (int o = tid; o < N2 * LDT; o += NT) bufR[o] = T(0);
     __syncthreads();
-    if (tid == 0) { bufR[0 * LDT + 0] = T(1); bufR[0 * LDT + CHI] = T(1); }
+    if (tid == 0) { bufR[0] = T(1); bufR[CHI] = T(1); }
     for (int c = L - 1; c >= 0; --c) {
       __syncthreads();
       for (int e = tid; e < int(site); e += NT) bufS[e] = Ain[size_t(c) * site + e];
@@ -285,28 +369,53 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
 #pragma unroll
         for (int b = 0; b < 2; ++b)
           wh[a][b] = (c > 0) ? bond_weight<T>(jh, c - 1, a, b, ep, em) : (a == 0 ? T(1) : T(0));
-      // P_b = A_c[b] Xt_b (CHI x CHI each) into sc-free registers, then
-      // Z[(a,al)][(x,be)] = sum_b wh(a,b) wv(x,b) P_b[al][be]
-      for (int o = tid; o < CHI * CHI; o += NT) {
-        const int al = o % CHI, be = o / CHI;
-        T p0 = 0, p1 = 0;
+      // Z[(a,al)][(x,be)] = sum_b wh(a,b) wv(x,b) (A_c[b] Xt_b)[al][be]
+      {
+        constexpr int tm = CHI / TL;
+        for (int t = tid; t < tm * tm; t += NT) {
+          const int al0 = (t % tm) * TL, be0 = (t / tm) * TL;
+          T p0[TL][TL], p1[TL][TL];
+#pragma unroll
+          for (int u = 0; u < TL; ++u)
+#pragma unroll
+            for (int v = 0; v < TL; ++v) { p0[u][v] = T(0); p1[u][v] = T(0); }
 #pragma unroll 8
-        for (int ap = 0; ap < CHI; ++ap) {
-          p0 += bufS[(0 * CHI + al) * CHI + ap] * bufR[be * LDT + ap];
-          p1 += bufS[(1 * CHI + al) * CHI + ap] * bufR[be * LDT + CHI + ap];
+          for (int ap = 0; ap < CHI; ++ap) {
+            T a0[TL], a1[TL], x0[TL], x1[TL];
+#pragma unroll
+            for (int u = 0; u < TL; ++u) {
+              a0[u] = bufS[(al0 + u) * CHI + ap];
+              a1[u] = bufS[(CHI + al0 + u) * CHI + ap];
+              x0[u] = bufR[(be0 + u) * LDT + ap];
+              x1[u] = bufR[(be0 + u) * LDT + CHI + ap];
+            }
+#pragma unroll
+            for (int u = 0; u < TL; ++u)
+#pragma unroll
+              for (int v = 0; v < TL; ++v) {
+                p0[u][v] += a0[u] * x0[v];
+                p1[u][v] += a1[u] * x1[v];
+              }
+          }
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+              const T f0 = wh[a][0] * wv[x][0], f1 = wh[a][1] * wv[x][1];
+#pragma unroll
+              for (int u = 0; u < TL; ++u)
+#pragma unroll
+                for (int v = 0; v < TL; ++v)
+                  Zr[(a * CHI + al0 + u) * LDZ + x * CHI + be0 + v] = f0 * p0[u][v] + f1 * p1[u][v];
+            }
         }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int x = 0; x < 2; ++x)
-            Zb[(x * CHI + be) * LDT + a * CHI + al] = wh[a][0] * wv[x][0] * p0 + wh[a][1] * wv[x][1] * p1;
       }
       __syncthreads();
       if (c == 0) {
-        // site 0: the left bond is (a = 0, alpha = 0); A_0[x][0][be] = Z[(0,0)][(x,be)]
+        // site 0: left bond (a = 0, alpha = 0): A_0[x][0][be] = Z[(0,0)][(x,be)]
         T part = 0;
         for (int o = tid; o < 2 * CHI; o += NT) {
-          const T d = Zb[o * LDT + 0];
+          const T d = Zr[o];
           sc[o] = d;
           part += d * d;
         }
@@ -320,152 +429,147 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         if (tid == 0) R.lognorm[r - 1] = lambda;
         break;
       }
-      // R_{c-1} into bufR (Xt is no longer needed), then T = R_{c-1} Z (upper triangular R)
+      // R_{c-1} into bufR, then T = R_{c-1} Z
       const T* rsrc = rs + size_t(c - 1) * N2 * N2;
       for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = rsrc[o];
       __syncthreads();
-      for (int o = tid; o < N2 * N2; o += NT) {
-        const int i = o % N2, col = o / N2;
-        T d = 0;
-        for (int a = i; a < N2; ++a) d += bufR[a * LDT + i] * Zb[col * LDT + a];
-        Tw[col * LDT + i] = d;
-      }
+      gemm_tiles<TL, TL, N2, NT, T>(
+          N2, N2, [&](int i, int a) { return bufR[a * LDT + i]; },
+          [&](int a, int col) { return Zr[a * LDZ + col]; },
+          [&](int i, int col, T v) { Tw[col * LDT + i] = v; });
       __syncthreads();
-      // column norms, Frobenius norm
-      for (int k = tid; k < N2; k += NT) {
-        T s2 = 0;
-        for (int i = 0; i < N2; ++i) s2 += Tw[k * LDT + i] * Tw[k * LDT + i];
-        cn2[k] = s2;
-        perm[k] = k;
-      }
-      __syncthreads();
-      T fro2 = 0;
-      for (int k = 0; k < N2; ++k) fro2 += cn2[k];
-      const T tolr2 = JacobiTol<T>::rank * JacobiTol<T>::rank * fro2;
 
-      // QR with column pivoting; stops at the numerical rank
+      // ---- QR with column pivoting, stopping at the numerical rank ----
+      // Group g (TPC threads) owns physical column g for the whole factorisation.
+      const int g = tid / TPC, part = tid % TPC;
+      const bool owner = g < N2;
+      bool active = owner;
+      T cn = 0;
+      if (owner) {
+        for (int i = part; i < N2; i += TPC) cn += Tw[g * LDT + i] * Tw[g * LDT + i];
+      }
+      cn = group_sum<TPC>(cn);
+      {
+        T bv = owner ? cn : T(-1);
+        int bi = owner ? g : N2;
+        wave_argmax(bv, bi);
+        if ((tid & (WAVE - 1)) == 0) { candv[tid / WAVE] = bv; candi[tid / WAVE] = bi; }
+      }
+      const T fro2 = block_sum<NT>((owner && part == 0) ? cn : T(0), red);
+      const T tolr2 = JacobiTol<T>::rank * JacobiTol<T>::rank * fro2;
       int rank = N2;
       for (int j = 0; j < N2; ++j) {
-        if (tid < WAVE) {
-          T best = -1;
-          int bi = j;
-          for (int k = j + tid; k < N2; k += WAVE) {
-            const T v = cn2[k];
-            if (v > best) { best = v; bi = k; }
+        const int buf = j & 1;
+        T best = candv[buf * NW];
+        int piv = candi[buf * NW];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+          const T ob = candv[buf * NW + w];
+          const int oi = candi[buf * NW + w];
+          if (ob > best || (ob == best && oi < piv)) { best = ob; piv = oi; }
+        }
+        if (!(best > tolr2)) { rank = j; break; }
+        const T alpha = Tw[piv * LDT + j];
+        const T ss = fmax(best - alpha * alpha, T(0));
+        T tau = 0, beta = alpha, scal = 0;
+        if (ss > T(0)) {
+          beta = -copysign(sqrt(alpha * alpha + ss), alpha);
+          tau = (beta - alpha) / beta;
+          scal = T(1) / (alpha - beta);
+        }
+        if (tid == 0) { diag[j] = beta; perm[j] = piv; }
+        if (g == piv) active = false;
+        T cand = T(-1);
+        T w = T(0), nn = T(0);
+        T v[ER2], m[ER2];
+        if (active) {
+          const T a0 = Tw[g * LDT + j];
+          if (part == 0) w = a0;
+#pragma unroll
+          for (int e = 0; e < ER2; ++e) {
+            const int i = j + 1 + part + TPC * e;   // may run past N2: read in bounds, value masked
+            const T vi = Tw[piv * LDT + i], mi = Tw[g * LDT + i];
+            const bool ok = i < N2;
+            v[e] = ok ? vi * scal : T(0);
+            m[e] = ok ? mi : T(0);
           }
 #pragma unroll
-          for (int off = 32; off > 0; off >>= 1) {
-            const T ob = __shfl_xor(best, off);
-            const int oi = __shfl_xor(bi, off);
-            if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-          }
-          if (tid == 0) { imisc[0] = bi; misc[2] = best; }
+          for (int e = 0; e < ER2; ++e) w += v[e] * m[e];
         }
-        __syncthreads();
-        if (!(misc[2] > tolr2)) { rank = j; break; }
-        const int piv = imisc[0];
-        if (piv != j) {
-          for (int i = tid; i < N2; i += NT) {
-            const T a = Tw[j * LDT + i];
-            Tw[j * LDT + i] = Tw[piv * LDT + i];
-            Tw[piv * LDT + i] = a;
-          }
-          if (tid == 0) {
-            const T a = cn2[j]; cn2[j] = cn2[piv]; cn2[piv] = a;
-            const int p = perm[j]; perm[j] = perm[piv]; perm[piv] = p;
-          }
-        }
-        __syncthreads();
-        if (tid < WAVE) {
-          T ss = 0;
-          for (int i = j + 1 + tid; i < N2; i += WAVE) {
-            const T v = Tw[j * LDT + i];
-            ss += v * v;
-          }
-          ss = wave_sum(ss);
-          if (tid == 0) {
-            const T alpha = Tw[j * LDT + j];
-            T t = 0, beta = alpha, scal = 0;
-            if (ss > T(0)) {
-              beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-              t = (beta - alpha) / beta;
-              scal = T(1) / (alpha - beta);
+        w = group_sum<TPC>(w);
+        if (active) {
+          const T tw = tau * w;
+          if (part == 0) Tw[g * LDT + j] -= tw;
+#pragma unroll
+          for (int e = 0; e < ER2; ++e) {
+            const int i = j + 1 + part + TPC * e;
+            if (i < N2) {
+              const T nv = m[e] - tw * v[e];
+              Tw[g * LDT + i] = nv;
+              nn += nv * nv;
             }
-            misc[0] = beta;
-            misc[1] = scal;
-            misc[3] = t;
           }
         }
-        __syncthreads();
+        nn = group_sum<TPC>(nn);
+        if (active) {
+          cn = nn;
+          cand = nn;
+        }
         {
-          const T t = misc[3], scal = misc[1];
-          const int k = j + 1 + tid / 4;
-          const int part = tid % 4;
-          const bool act = (k < N2);
-          T w = 0;
-          if (act && t != T(0)) {
-            if (part == 0) w = Tw[k * LDT + j];
-            for (int i = j + 1 + part; i < N2; i += 4) w += Tw[j * LDT + i] * scal * Tw[k * LDT + i];
+          T bv = cand;
+          int bi = active ? g : N2;
+          wave_argmax(bv, bi);
+          if ((tid & (WAVE - 1)) == 0) {
+            candv[(buf ^ 1) * NW + tid / WAVE] = bv;
+            candi[(buf ^ 1) * NW + tid / WAVE] = bi;
           }
-          w += __shfl_xor(w, 1);
-          w += __shfl_xor(w, 2);
-          T nn = 0;
-          if (act) {
-            const T tw = t * w;
-            if (part == 0) Tw[k * LDT + j] -= tw;
-            for (int i = j + 1 + part; i < N2; i += 4) {
-              const T v = Tw[k * LDT + i] - tw * Tw[j * LDT + i] * scal;
-              Tw[k * LDT + i] = v;
-              nn += v * v;
-            }
-          }
-          nn += __shfl_xor(nn, 1);
-          nn += __shfl_xor(nn, 2);
-          if (act && part == 0) cn2[k] = nn;
         }
-        __syncthreads();
-        if (tid == 0) Tw[j * LDT + j] = misc[0];
         __syncthreads();
       }
-
-      // J = rows 0..rank-1 of R (row-major in bufR, ld LDT); one zero row if rank is odd
+      if (owner && part == 0) used[g] = active ? 0 : 1;
+      __syncthreads();
+      if (tid == 0) {
+        int p = rank;
+        for (int col = 0; col < N2; ++col)
+          if (!used[col]) perm[p++] = col;
+      }
+      __syncthreads();
+      // J = rows 0..rank-1 of R in pivoted column order (row-major in bufR, ld LDT)
       const int nr = rank + (rank & 1);
       for (int o = tid; o < nr * N2; o += NT) {
-        const int i = o / N2, k = o % N2;
-        bufR[i * LDT + k] = (i < rank && k >= i) ? Tw[k * LDT + i] : T(0);
+        const int i = o / N2, kk = o % N2;
+        T val = T(0);
+        if (i < rank) val = (kk > i) ? Tw[perm[kk] * LDT + i] : (kk == i ? diag[i] : T(0));
+        bufR[i * LDT + kk] = val;
       }
       __syncthreads();
 
-      // one-sided Jacobi on the rows of J, parallel round-robin ordering
+      // ---- one-sided Jacobi on the rows of J, parallel round-robin ordering ----
       if (nr >= 2) {
-        const T scale = sqrt(fro2);
-        const T tol = JacobiTol<T>::rot * scale;
-        const int g = tid / 8, l = tid % 8;
+        const T tol = JacobiTol<T>::rot * sqrt(fro2);
+        const int gj = tid / TPP, l = tid % TPP;
         const int npair = nr / 2;
         for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
           int rotated = 0;
           for (int rd = 0; rd < nr - 1; ++rd) {
-            if (g < npair) {
+            if (gj < npair) {
               int p, q;
-              if (g == 0) { p = nr - 1; q = rd; }
-              else { p = (rd + g) % (nr - 1); q = (rd - g + nr - 1) % (nr - 1); }
+              if (gj == 0) { p = nr - 1; q = rd; }
+              else { p = (rd + gj) % (nr - 1); q = (rd - gj + nr - 1) % (nr - 1); }
               T xp[EPT], xq[EPT];
               T a = 0, b = 0, cc = 0;
 #pragma unroll
               for (int e = 0; e < EPT; ++e) {
-                const int k = l + 8 * e;
+                const int k = l + TPP * e;
                 xp[e] = (k < N2) ? bufR[p * LDT + k] : T(0);
                 xq[e] = (k < N2) ? bufR[q * LDT + k] : T(0);
                 a += xp[e] * xp[e];
                 b += xq[e] * xq[e];
                 cc += xp[e] * xq[e];
               }
-#pragma unroll
-              for (int off = 1; off < 8; off <<= 1) {
-                a += __shfl_xor(a, off);
-                b += __shfl_xor(b, off);
-                cc += __shfl_xor(cc, off);
-              }
+              a = group_sum<TPP>(a);
+              b = group_sum<TPP>(b);
+              cc = group_sum<TPP>(cc);
               if (a > T(0) && b > T(0) && fabs(cc) > tol * sqrt(fmax(a, b))) {
                 const T zeta = (b - a) / (T(2) * cc);
                 T t;
@@ -475,7 +579,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
                 const T sn = cs * t;
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) {
-                  const int k = l + 8 * e;
+                  const int k = l + TPP * e;
                   if (k < N2) {
                     bufR[p * LDT + k] = cs * xp[e] - sn * xq[e];
                     bufR[q * LDT + k] = sn * xp[e] + cs * xq[e];
@@ -489,7 +593,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           if (!__syncthreads_or(rotated)) break;
         }
       }
-      // row norms and descending order
+      // ---- row norms, descending order, kept rows (normalised) into V ----
       for (int i = tid; i < N2; i += NT) {
         T s2 = 0;
         if (i < rank)
@@ -504,38 +608,35 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       }
       __syncthreads();
       const int kept = rank < CHI ? rank : CHI;
-      // V rows (CHI x N2) in bufS: V[al][perm[kk]] = J[ord[al]][kk] / sigma
       for (int o = tid; o < CHI * N2; o += NT) {
         const int al = o / N2, kk = o % N2;
-        T v = 0;
+        T val = 0;
         if (al < kept) {
           const int row = ord[al];
           const T s2 = sc[row];
-          if (s2 > T(0)) v = bufR[row * LDT + kk] / sqrt(s2);
+          if (s2 > T(0)) val = bufR[row * LDT + kk] / sqrt(s2);
         }
-        bufS[al * N2 + perm[kk]] = v;
+        bufS[al * N2 + perm[kk]] = val;
       }
-      // the kept rows span the right subspace but small ones are orthogonal to the large ones
-      // only up to rot * ||T|| / sigma: make them orthonormal (span unchanged)
-      cholqr2_rows<T, CHI, NT>(bufS, N2, N2, kept, bufR, T(JacobiTol<T>::eta));
-      // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
-      T* bout = Aout + size_t(c) * site;
+      // small kept rows are orthogonal to the large ones only up to rot ||T|| / sigma: make the
+      // kept rows orthonormal (span unchanged)
+      mgs2_rows<T, CHI, NT>(bufS, kept, T(JacobiTol<T>::eta));
+      T* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
       for (int o = tid; o < int(site); o += NT) {
         const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
         bout[o] = bufS[al * N2 + x * CHI + be];
       }
-      // Xt_{c} = 2^-e_{c-1} Z V^T (N2 x CHI) into bufR (column-major, ld LDT), rescaled
+      // Xt_c = 2^-e_{c-1} Z V^T (N2 x CHI, column-major in bufR), then a power-of-two rescale
       const int ec = rexp[c - 1];
       T mx = 0;
-      for (int o = tid; o < N2 * CHI; o += NT) {
-        const int j = o % N2, al = o / N2;
-        T d = 0;
-#pragma unroll 8
-        for (int col = 0; col < N2; ++col) d += Zb[col * LDT + j] * bufS[al * N2 + col];
-        d = T(ldexp(d, -ec));
-        bufR[al * LDT + j] = d;
-        mx = fmax(mx, fabs(d));
-      }
+      gemm_tiles<TL, TL, N2, NT, T>(
+          N2, CHI, [&](int j, int col) { return Zr[j * LDZ + col]; },
+          [&](int col, int al) { return bufS[al * N2 + col]; },
+          [&](int j, int al, T val) {
+            const T d = T(ldexp(val, -ec));
+            bufR[al * LDT + j] = d;
+            mx = fmax(mx, fabs(d));
+          });
       mx = block_max<NT>(mx, red);
       const int e = pow2_exponent(mx);
       log2acc += e;
@@ -543,7 +644,6 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         const int j = o % N2, al = o / N2;
         bufR[al * LDT + j] = T(ldexp(bufR[al * LDT + j], -e));
       }
-      // clear the rows of Xt beyond CHI columns (bufR columns CHI.. hold nothing needed)
     }
     __syncthreads();
   }
@@ -558,11 +658,9 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     for (int c = 1; c < L; ++c) {
       __syncthreads();
       const T* A = A0 + size_t(c) * site;
-      T mx = 0;
-      T val = 0;
-      const int o = tid;
-      if (o < 2 * CHI) {
-        const int sp = o / CHI, be = o % CHI;
+      T mx = 0, val = 0;
+      if (tid < 2 * CHI) {
+        const int sp = tid / CHI, be = tid % CHI;
         for (int s2 = 0; s2 < 2; ++s2) {
           const T w = bond_weight<T>(jh0, c - 1, s2, sp, ep, em);
           T dd = 0;
@@ -574,7 +672,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       mx = block_max<NT>(mx, red);
       const int e = pow2_exponent(mx);
       logacc += double(e) * 0.69314718055994530942;
-      if (o < 2 * CHI) sc[o] = T(ldexp(val, -e));
+      if (tid < 2 * CHI) sc[tid] = T(ldexp(val, -e));
     }
     __syncthreads();
     if (tid == 0) {
@@ -587,26 +685,16 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
 template <typename T, int CHI>
 hipError_t launch_env_build(const DevReal* d_reals, int n, double* d_lnZ, hipStream_t stream) {
   using S = EnvSmem<T, CHI>;
-  static_assert(S::NT >= 4 * (S::N2 - 1), "four threads per trailing column");
+  static_assert(S::NT == env_tpc(CHI) * S::N2, "one group of TPC threads per column");
+  static_assert(env_tpp(CHI) * CHI <= S::NT && env_tpp(CHI) <= 64, "Jacobi pair groups");
   static_assert(2 * CHI <= S::NT, "");
+  static_assert(S::NT % 64 == 0, "");
   hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_kernel<T, CHI>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(S::bytes));
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL((env_build_kernel<T, CHI>), dim3(n), dim3(S::NT), S::bytes, stream, d_reals,
                      d_lnZ);
   return hipGetLastError();
-}
-
-template <typename T>
-size_t env_build_smem_bytes(int chi) {
-  switch (chi) {
-    case 2: return EnvSmem<T, 2>::bytes;
-    case 4: return EnvSmem<T, 4>::bytes;
-    case 8: return EnvSmem<T, 8>::bytes;
-    case 16: return EnvSmem<T, 16>::bytes;
-    case 32: return EnvSmem<T, 32>::bytes;
-    default: return 0;
-  }
 }
 
 hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n, double* d_lnZ,

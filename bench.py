@@ -25,6 +25,34 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 
 
+# HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE counters, each
+# scaled by the same counter on a plain 1 GiB copy (profiles/rbim64_fp32_hbm_traffic.md).  Valid
+# only for the kernel sources they were taken on: reported as null once those change.
+COUNTED_TRAFFIC = {
+    ("rbim64", "fp32"): {
+        "fetch_kib": 3846582.9375, "fetch_factor": 1048576.0 / 524306.1875,
+        "write_kib": 6160537.5, "write_factor": 1.0,
+        "sources_sha256": {
+            "envbuild.hip": "c2342458c6e82fdc783a1e9875d1be705b46e65822f35fd345f834eeabfa3c34",
+            "common.hpp": "2efa25530392e8807d613e9aabe42d3afcfa73e766988131a0dca016b25208c3",
+        },
+    },
+}
+
+
+def counted_traffic(workload, precision):
+    import hashlib
+    rec = COUNTED_TRAFFIC.get((workload, precision))
+    if rec is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_2409_06538_amd", "csrc")
+    for name, digest in rec["sources_sha256"].items():
+        with open(os.path.join(csrc, name), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return 1024.0 * (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"])
+
+
 def build_flops_per_site(chi):
     """Algorithmic work of one site of the canonical compression (QR of a 4chi x 2chi matrix
     with Q, SVD of a 2chi x 2chi matrix, the two contractions), ~270 chi^3."""
@@ -92,7 +120,7 @@ def run_gpu(args):
     achieved = flops / (build_ms * 1e-3) / 1e12
     res["roofline"] = {"kernel": "env_build_kernel", "bound": "alu", "achieved": achieved,
                        "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                       "traffic": None,
+                       "traffic": counted_traffic(args.workload, args.precision),
                        "launch_ms": build_ms,
                        "algorithmic_flops_per_launch": flops}
     return res
@@ -154,6 +182,18 @@ def run_cpu_baseline(L, chi, p, K_full, seed, n_prop=12):
                       f"proposals per realization; single thread"}
 
 
+def calib_copy(mib):
+    """One device-to-device copy of `mib` MiB: reads and writes exactly mib MiB each."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +205,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy one buffer of this many MiB once (a plain copy "
+                         "kernel of known size, the reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the realizations of a "
@@ -172,6 +215,8 @@ def main():
               "measures one GPU's share.", file=sys.stderr)
         sys.exit(2)
     res = run_gpu(args)
+    if args.calib_copy_mib:
+        calib_copy(args.calib_copy_mib)
     plain = None if args.no_plain else run_fp64_plain(args, res["L"], res["chi"], res["p"], res["K"])
     cpu = None if args.no_cpu else run_cpu_baseline(res["L"], res["chi"], res["p"], res["K"], args.seed)
     line = {

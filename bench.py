@@ -116,7 +116,7 @@ def run_gpu(args):
         "build_ms": build_ms, "propose_ms": prop_ms,
     }
     flops = build_flops_per_site(chi) * (L - 1) * L * n
-    peak = FP32_VECTOR_PEAK_TFLOPS if args.precision == "fp32" else FP64_VECTOR_PEAK_TFLOPS
+    peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
     achieved = flops / (build_ms * 1e-3) / 1e12
     res["roofline"] = {"kernel": "env_build_kernel", "bound": "alu", "achieved": achieved,
                        "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
@@ -200,7 +200,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rbim64")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
     ap.add_argument("--proposals", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -230,7 +230,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {res['n']} realizations of the {res['L']}x"
                                f"{res['L']} open +-J lattice, p={res['p']}, Nishimori beta, "

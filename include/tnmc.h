@@ -52,10 +52,14 @@ typedef enum {
   TNMC_ESTATE = -5    /* chain state inconsistent with the call */
 } tnmc_status;
 
-/* Storage/arithmetic precision of the environments and of the contractions.  The running
- * log-normalisation of the environments, log q(s), energies' Boltzmann factors and the
- * acceptance ratio are FP64 in every mode. */
-typedef enum { TNMC_FP64 = 0, TNMC_FP32 = 1 } tnmc_precision;
+/* Precision of the environments and of the contractions.  TNMC_FP64 and TNMC_FP32 store and
+ * compute in that type.  TNMC_BF16 stores the environments as bfloat16 (round to nearest even
+ * from the FP32 result of each site) and computes every contraction and factorisation in FP32;
+ * the stored, rounded tensors are the environments that later rows and the sampler use.  The
+ * running log-normalisation of the environments, log q(s), energies' Boltzmann factors and the
+ * acceptance ratio are FP64 in every mode.  Lower precision can only lower the acceptance rate:
+ * the Metropolis step keeps the chain exact whatever q is (Eq. (3)). */
+typedef enum { TNMC_FP64 = 0, TNMC_FP32 = 1, TNMC_BF16 = 2 } tnmc_precision;
 
 /* One disorder realization.  An array of these (host memory) describes a batch. */
 typedef struct {
@@ -75,7 +79,8 @@ typedef struct {
 /* Supported bond dimensions: chi in {2, 4, 8, 16, 32}; L in [2, 1024]. */
 int tnmc_chi_supported(int32_t chi, tnmc_precision prec);
 
-/* Bytes of one realization's environments: L rows x L sites x 2 x chi x chi reals, layout
+/* Bytes of one realization's environments: L rows x L sites x 2 x chi x chi elements of the
+ * storage type (8, 4 or 2 bytes), layout
  * [r][c][sigma][alpha][beta] (sigma 0 <-> +1), zero-padded where the bond is smaller than chi. */
 size_t tnmc_env_bytes(int32_t L, int32_t chi, tnmc_precision prec);
 

@@ -16,8 +16,10 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtnmc.so")
 
-FP64, FP32 = 0, 1
-PRECISIONS = {"fp64": FP64, "fp32": FP32}
+FP64, FP32, BF16 = 0, 1, 2
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
+# storage dtype of the environments per precision
+ENV_DTYPES = {FP64: torch.float64, FP32: torch.float32, BF16: torch.bfloat16}
 OBS_COUNT = 9
 OBS_NAMES = ("count", "E", "E2", "m2", "m4", "medge2", "q", "q2", "q4")
 
@@ -110,7 +112,7 @@ class Batch:
         self.chi = int(chi)
         self.prec = PRECISIONS[precision]
         self.precision = precision
-        self.dtype = torch.float64 if self.prec == FP64 else torch.float32
+        self.dtype = ENV_DTYPES[self.prec]
         self.device = torch.device(device)
         if not lib.tnmc_chi_supported(self.chi, self.prec):
             raise TNMCError(f"chi={chi} not supported for {precision}")
@@ -121,8 +123,7 @@ class Batch:
             jh = torch.zeros(L * W, dtype=torch.int64, device=self.device)
             jv = torch.zeros((L - 1) * W, dtype=torch.int64, device=self.device)
             nbytes = lib.tnmc_env_bytes(L, self.chi, self.prec)
-            env = torch.zeros(nbytes // (8 if self.prec == FP64 else 4), dtype=self.dtype,
-                              device=self.device)
+            env = torch.zeros(nbytes // self.dtype.itemsize, dtype=self.dtype, device=self.device)
             lam = torch.zeros(L, dtype=torch.float64, device=self.device)
             self.Jh.append(jh)
             self.Jv.append(jv)

@@ -16,10 +16,11 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
-inline size_t elem_bytes(tnmc_precision p) { return p == TNMC_FP64 ? 8 : 4; }
+// bytes of one stored environment element
+inline size_t elem_bytes(tnmc_precision p) { return p == TNMC_FP64 ? 8 : (p == TNMC_FP32 ? 4 : 2); }
 
 bool chi_ok(int32_t chi) { return chi == 2 || chi == 4 || chi == 8 || chi == 16 || chi == 32; }
-bool prec_ok(tnmc_precision p) { return p == TNMC_FP64 || p == TNMC_FP32; }
+bool prec_ok(tnmc_precision p) { return p == TNMC_FP64 || p == TNMC_FP32 || p == TNMC_BF16; }
 
 // Basic per-instance checks; returns Lmax or -1.
 int check_instances(const tnmc_instance* inst, int32_t n, bool need_env, bool need_J) {

@@ -172,6 +172,40 @@ __device__ __forceinline__ T block_max(T v, T* red) {
   return s;
 }
 
+// Environment storage types.  bfloat16 is the upper half of an IEEE binary32; narrowing rounds to
+// nearest, ties to even (NaN stays NaN).  Arithmetic always runs in the wider compute type.
+struct bf16_t {
+  uint16_t bits;
+};
+
+__device__ __forceinline__ float widen(float v) { return v; }
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ float widen(bf16_t v) { return __uint_as_float(uint32_t(v.bits) << 16); }
+
+template <typename E>
+struct Narrow;
+template <>
+struct Narrow<double> {
+  __device__ __forceinline__ static double from(double v) { return v; }
+};
+template <>
+struct Narrow<float> {
+  __device__ __forceinline__ static float from(float v) { return v; }
+};
+template <>
+struct Narrow<bf16_t> {
+  __device__ __forceinline__ static bf16_t from(float v) {
+    uint32_t u = __float_as_uint(v);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return bf16_t{uint16_t((u >> 16) | 0x40u)};
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return bf16_t{uint16_t(u >> 16)};
+  }
+};
+template <typename E, typename T>
+__device__ __forceinline__ E narrow(T v) {
+  return Narrow<E>::from(v);
+}
+
 // Exponent e with 2^(e-1) <= |x| < 2^e (0 for x == 0 or non-finite); scaling by 2^-e is exact.
 template <typename T>
 __device__ __forceinline__ int pow2_exponent(T x) {

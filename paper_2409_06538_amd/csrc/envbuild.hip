@@ -58,18 +58,31 @@ __host__ __device__ constexpr int env_tpp(int chi) {
                                             : ((2 * chi < 32) ? 2 * chi : 32);
 }
 
+// Left-sweep layout: M_c (MQ x N2) lives in registers.  Thread (g = tid / TPC, part = tid % TPC)
+// owns rows [part * RPT, part * RPT + RPT) of column g (rows >= MQ are zero padding).
+template <int CHI>
+struct LeftCfg {
+  static constexpr int N2 = 2 * CHI, MQ = 4 * CHI;
+  static constexpr int NT = env_threads(CHI);
+  static constexpr int TPC = NT / N2;
+  static constexpr int RPT = (MQ + TPC - 1) / TPC;
+  static constexpr int VLD = (TPC * RPT + 3) / 4 * 4;   // reflector buffer length
+  static constexpr int LDAT = CHI + 4;                  // A_c^T rows [b][ap][al]
+  static constexpr int LDRT = N2 + 4;                   // R~ rows [b][al][i]
+  static constexpr size_t lds = size_t(2) * CHI * LDAT + size_t(2) * CHI * LDRT + 2 * VLD + 8;
+};
+
 template <typename T, int CHI>
 struct EnvSmem {
   static constexpr int N2 = 2 * CHI;     // bond of the operator-applied MPS; SVD matrix side
   static constexpr int MQ = 4 * CHI;     // rows of M_c
-  static constexpr int LDA = MQ + 4;     // column stride of M (column-major)
   static constexpr int LDT = N2 + 4;     // column stride of T, R, Xt (column-major); row stride of J
   static constexpr int LDZ = N2 + 4;     // row stride of Z (row-major)
   static constexpr int LDG = CHI + 1;    // row stride of the Gram / Cholesky factors
   static constexpr int NT = env_threads(CHI);
   static constexpr int NW = NT / 64;
   static constexpr int TILE = 2;
-  static constexpr size_t bufA_left = size_t(LDA) * N2;
+  static constexpr size_t bufA_left = LeftCfg<CHI>::lds;
   static constexpr size_t bufA_right = size_t(N2) * LDZ + size_t(N2) * LDT;
   // + MQ + N2: rows read past the end of the last column (values masked) stay in bounds
   static constexpr size_t bufA = (bufA_left > bufA_right ? bufA_left : bufA_right) + MQ + N2;
@@ -120,61 +133,67 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, FA fa, FB fb, FC fc) {
   }
 }
 
-// Householder QR of the column-major MQ x N2 matrix A (ld LDA); only R is produced: its strict
-// upper triangle stays in A, its diagonal goes to diag[].  One barrier per column: the threads that
-// update column j+1 also produce its sub-diagonal norm^2 for the next step (double-buffered in ss2),
-// and every thread derives the reflector of column j from it.
-template <typename T, int MQ, int N2, int LDA, int NT, int TPC>
-__device__ void householder_r(T* A, T* diag, T* ss2) {
-  constexpr int ER = (MQ + TPC - 1) / TPC;
-  const int tid = threadIdx.x;
-  const int g = tid / TPC, part = tid % TPC;   // group g owns column g
-  if (g == 0) {
-    T s = 0;
-    for (int i = 1 + part; i < MQ; i += TPC) s += A[i] * A[i];
-    s = group_sum<TPC>(s);
-    if (part == 0) ss2[0] = s;
+// Householder reflector of column j from its owner group's registers m[] (rows > j are zeroed
+// by it): writes v (v_j = 1, zero above j) to vb, tau to taub, beta to diag[j].
+template <typename T, int TPC, int RPT>
+__device__ __forceinline__ void make_reflector(const T (&m)[RPT], int j, int row0, int MQ, T* vb,
+                                               T* taub, T* diag, int part) {
+  T s = 0, a = 0;
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int rho = row0 + t;
+    s += (rho > j) ? m[t] * m[t] : T(0);
+    a += (rho == j) ? m[t] : T(0);
   }
+  s = group_sum<TPC>(s);
+  a = group_sum<TPC>(a);
+  T tau = 0, beta = a, scal = 0;
+  if (s > T(0)) {
+    beta = -copysign(sqrt(a * a + s), a);
+    tau = (beta - a) / beta;
+    scal = T(1) / (a - beta);
+  }
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) {
+    const int rho = row0 + t;
+    vb[rho] = (rho > j && rho < MQ) ? m[t] * scal : (rho == j ? T(1) : T(0));
+  }
+  if (part == 0) {
+    *taub = tau;
+    diag[j] = beta;
+  }
+}
+
+// R factor of the register-resident M (R-only Householder QR), one barrier per column: after
+// applying reflector j, the owner of column j + 1 publishes reflector j + 1 into the other half
+// of the double buffer.  On return diag[] holds the diagonal of R; the strict upper triangle of
+// column g is m[t] at rows row0 + t < g.
+template <typename T, int CHI>
+__device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T* diag) {
+  using C = LeftCfg<CHI>;
+  constexpr int N2 = C::N2, MQ = C::MQ, TPC = C::TPC, RPT = C::RPT, VLD = C::VLD;
+  const int tid = threadIdx.x;
+  const int g = tid / TPC, part = tid % TPC, row0 = part * RPT;
+  if (g == 0) make_reflector<T, TPC, RPT>(m, 0, row0, MQ, vbuf, taub, diag, part);
   __syncthreads();
   for (int j = 0; j < N2; ++j) {
-    const T alpha = A[j * LDA + j];
-    const T ss = ss2[j & 1];
-    T tau = 0, beta = alpha, scal = 0;
-    if (ss > T(0)) {
-      beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-      tau = (beta - alpha) / beta;
-      scal = T(1) / (alpha - beta);
-    }
-    if (tid == 0) diag[j] = beta;
-    if (g > j && g < N2) {
-      T v[ER], m[ER];
-      const T a0 = A[g * LDA + j];
-      T w = (part == 0) ? a0 : T(0);
+    const T* vj = vbuf + (j & 1) * VLD;
+    const T tau = taub[j & 1];
+    if (g > j) {
+      T vv[RPT];
+      T w = 0;
 #pragma unroll
-      for (int e = 0; e < ER; ++e) {
-        const int i = j + 1 + part + TPC * e;   // may run past MQ: read in bounds, value masked
-        const T vi = A[j * LDA + i], mi = A[g * LDA + i];
-        const bool ok = i < MQ;
-        v[e] = ok ? vi * scal : T(0);
-        m[e] = ok ? mi : T(0);
+      for (int t = 0; t < RPT; ++t) {
+        vv[t] = vj[row0 + t];
+        w += vv[t] * m[t];
       }
-#pragma unroll
-      for (int e = 0; e < ER; ++e) w += v[e] * m[e];
       w = group_sum<TPC>(w);
       const T tw = tau * w;
-      if (part == 0) A[g * LDA + j] -= tw;
-      T nn = 0;
 #pragma unroll
-      for (int e = 0; e < ER; ++e) {
-        const int i = j + 1 + part + TPC * e;
-        if (i < MQ) {
-          const T nv = m[e] - tw * v[e];
-          A[g * LDA + i] = nv;
-          if (i > j + 1) nn += nv * nv;
-        }
-      }
-      nn = group_sum<TPC>(nn);
-      if (g == j + 1 && part == 0) ss2[(j + 1) & 1] = nn;
+      for (int t = 0; t < RPT; ++t) m[t] -= tw * vv[t];
+      if (g == j + 1)
+        make_reflector<T, TPC, RPT>(m, j + 1, row0, MQ, vbuf + ((j + 1) & 1) * VLD,
+                                    taub + ((j + 1) & 1), diag, part);
     }
     __syncthreads();
   }
@@ -240,11 +259,12 @@ __device__ void mgs2_rows(T* V, int k, T eta) {
   }
 }
 
-template <typename T, int CHI>
+// T: arithmetic type; E: storage type of the environments (T, or bf16_t with T = float).
+template <typename T, typename E, int CHI>
 __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevReal* reals,
                                                                      double* lnZ_out) {
   using S = EnvSmem<T, CHI>;
-  constexpr int N2 = S::N2, MQ = S::MQ, LDA = S::LDA, LDT = S::LDT, LDZ = S::LDZ, LDG = S::LDG;
+  constexpr int N2 = S::N2, MQ = S::MQ, LDT = S::LDT, LDZ = S::LDZ;
   constexpr int NT = S::NT, NW = S::NW, TL = S::TILE;
   constexpr int TPP = env_tpp(CHI);   // threads per Jacobi row pair
   constexpr int TPC = env_tpc(CHI);   // threads per column in the QR updates
@@ -272,7 +292,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   const int L = R.L;
   const int W = words_per_row(L);
   const T ep = T(exp(R.beta)), em = T(exp(-R.beta));
-  T* env = reinterpret_cast<T*>(R.env);
+  E* env = reinterpret_cast<E*>(R.env);
   T* rs = reinterpret_cast<T*>(R.ws);                 // L x N2 x N2 scratch: R_c column-major
   const size_t site = size_t(2) * CHI * CHI;
   const size_t rowst = site * L;
@@ -282,69 +302,103 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   for (size_t e = tid; e < rowst; e += NT) {         // E_{L-1} = 1
     const size_t inner = e % site;
     const int a = int((inner % (CHI * CHI)) / CHI), b = int(inner % CHI);
-    env[size_t(L - 1) * rowst + e] = (a == 0 && b == 0) ? T(0.70710678118654752440) : T(0);
+    env[size_t(L - 1) * rowst + e] = narrow<E>((a == 0 && b == 0) ? T(0.70710678118654752440) : T(0));
   }
   double lambda = 0.5 * double(L) * 0.69314718055994530942;
   if (tid == 0) R.lognorm[L - 1] = lambda;
 
   for (int r = L - 1; r >= 1; --r) {
-    const T* Ain = env + size_t(r) * rowst;
-    T* Aout = env + size_t(r - 1) * rowst;
+    const E* Ain = env + size_t(r) * rowst;
+    E* Aout = env + size_t(r - 1) * rowst;
     const uint64_t* jh = R.Jh + size_t(r) * W;        // horizontal bonds of row r
     const uint64_t* jv = R.Jv + size_t(r - 1) * W;    // vertical bonds between rows r-1 and r
     long long log2acc = 0;
 
     // ---------------- left to right: R factors ----------------
-    for (int c = 0; c < L - 1; ++c) {
-      __syncthreads();
-      for (int e = tid; e < int(site); e += NT) bufS[e] = Ain[size_t(c) * site + e];
-      __syncthreads();
-      T wv[2][2];
-#pragma unroll
-      for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) wv[x][b] = bond_weight<T>(jv, c, x, b, ep, em);
-      if (c == 0) {
-        for (int o = tid; o < N2 * N2; o += NT) {
-          const int i = o % N2, col = o / N2, b = col / CHI, ap = col % CHI;
-          const T d = (i < CHI) ? bufS[(b * CHI + i) * CHI + ap] : T(0);
-          bufA[col * LDA + 2 * i] = wv[0][b] * d;
-          bufA[col * LDA + 2 * i + 1] = wv[1][b] * d;
+    {
+      using C = LeftCfg<CHI>;
+      constexpr int TPC = C::TPC, RPT = C::RPT, LDAT = C::LDAT, LDRT = C::LDRT;
+      T* AsT = bufA;                                   // A_c^T: [b][ap][al], ld LDAT
+      T* Rt = AsT + size_t(2) * CHI * LDAT;            // R~_b = sum_a wh(a,b) R_{c-1}[:, (a, .)]
+      T* vbuf = Rt + size_t(2) * CHI * LDRT;           // 2 x VLD reflectors
+      T* taub = vbuf + 2 * C::VLD;                     // 2 taus
+      const int g = tid / TPC, part = tid % TPC, row0 = part * RPT;
+      const int gb = g / CHI, gap = g % CHI;           // column g = (b, alpha')
+      for (int c = 0; c < L - 1; ++c) {
+        __syncthreads();
+        for (int e = tid; e < int(site); e += NT) {
+          const int b = e / (CHI * CHI), al = (e / CHI) % CHI, ap = e % CHI;
+          AsT[(b * CHI + ap) * LDAT + al] = widen(Ain[size_t(c) * site + e]);
         }
-      } else {
+        if (c > 0) {
+          T wh2[2][2];   // wh2[a][b]
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          const T wa = bond_weight<T>(jh, c - 1, 0, b, ep, em);
-          const T wb = bond_weight<T>(jh, c - 1, 1, b, ep, em);
-          const T w0 = wv[0][b], w1 = wv[1][b];
-          gemm_tiles<TL, TL, CHI, NT, T>(
-              N2, CHI,
-              [&](int i, int al) { return bufR[al * LDT + i] * wa + bufR[(CHI + al) * LDT + i] * wb; },
-              [&](int al, int ap) { return bufS[(b * CHI + al) * CHI + ap]; },
-              [&](int i, int ap, T d) {
-                bufA[(b * CHI + ap) * LDA + 2 * i] = w0 * d;
-                bufA[(b * CHI + ap) * LDA + 2 * i + 1] = w1 * d;
-              });
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) wh2[a][b] = bond_weight<T>(jh, c - 1, a, b, ep, em);
+          for (int o = tid; o < 2 * CHI * N2; o += NT) {
+            const int b = o / (CHI * N2), al = (o / N2) % CHI, i = o % N2;
+            Rt[(b * CHI + al) * LDRT + i] =
+                wh2[0][b] * bufR[al * LDT + i] + wh2[1][b] * bufR[(CHI + al) * LDT + i];
+          }
         }
-      }
-      __syncthreads();
-      householder_r<T, MQ, N2, LDA, NT, TPC>(bufA, diag, cnv);
-      // carry R with a power-of-two rescale; keep it for the second sweep
-      T mx = 0;
-      for (int o = tid; o < N2 * N2; o += NT) {
-        const int i = o % N2, k = o / N2;
-        if (i <= k) mx = fmax(mx, fabs(i == k ? diag[i] : bufA[k * LDA + i]));
-      }
-      mx = block_max<NT>(mx, red);
-      const int e = pow2_exponent(mx);
-      log2acc += e;
-      if (tid == 0) rexp[c] = e;
-      T* rdst = rs + size_t(c) * N2 * N2;
-      for (int o = tid; o < N2 * N2; o += NT) {
-        const int i = o % N2, k = o / N2;
-        const T v = (i < k) ? T(ldexp(bufA[k * LDA + i], -e)) : (i == k ? T(ldexp(diag[i], -e)) : T(0));
-        bufR[k * LDT + i] = v;
-        rdst[o] = v;
+        __syncthreads();
+        const T w0 = bond_weight<T>(jv, c, 0, gb, ep, em);
+        const T w1 = bond_weight<T>(jv, c, 1, gb, ep, em);
+        const T* acol = AsT + (gb * CHI + gap) * LDAT;   // A[b][.][ap]
+        T m[RPT];
+        if (c == 0 || (RPT & 1)) {
+          // site 0 has no left bond: rows (i, x) with i the bond index of E_r (< CHI)
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) {
+            const int rho = row0 + t, i = rho >> 1;
+            T d = 0;
+            if (c == 0) {
+              d = (i < CHI) ? acol[i < CHI ? i : 0] : T(0);
+            } else if (rho < MQ) {
+              const T* rcol = Rt + size_t(gb) * CHI * LDRT + i;
+              for (int al = 0; al < CHI; ++al) d += rcol[al * LDRT] * acol[al];
+            }
+            m[t] = (rho < MQ) ? ((rho & 1) ? w1 : w0) * d : T(0);
+          }
+        } else {
+          constexpr int IPT = RPT / 2 > 0 ? RPT / 2 : 1;
+          const int i0 = row0 / 2;
+          T d[IPT];
+#pragma unroll
+          for (int u = 0; u < IPT; ++u) d[u] = T(0);
+          const T* rrow = Rt + size_t(gb) * CHI * LDRT + i0;
+#pragma unroll 4
+          for (int al = 0; al < CHI; ++al) {
+            const T a = acol[al];
+#pragma unroll
+            for (int u = 0; u < IPT; ++u) d[u] += rrow[al * LDRT + u] * a;
+          }
+#pragma unroll
+          for (int t = 0; t < RPT; ++t) m[t] = ((t & 1) ? w1 : w0) * d[t >> 1];
+        }
+        householder_regs<T, CHI>(m, vbuf, taub, diag);
+        // carry R with a power-of-two rescale; keep it for the second sweep
+        T mx = 0;
+#pragma unroll
+        for (int t = 0; t < RPT; ++t)
+          if (row0 + t < g) mx = fmax(mx, fabs(m[t]));
+        if (tid < N2) mx = fmax(mx, fabs(diag[tid]));
+        mx = block_max<NT>(mx, red);
+        const int e = pow2_exponent(mx);
+        log2acc += e;
+        if (tid == 0) rexp[c] = e;
+        T* rdst = rs + size_t(c) * N2 * N2 + size_t(g) * N2;
+        const T dg = diag[g];
+#pragma unroll
+        for (int t = 0; t < RPT; ++t) {
+          const int rho = row0 + t;
+          if (rho < N2) {
+            const T v = T(ldexp(rho < g ? m[t] : (rho == g ? dg : T(0)), -e));
+            bufR[g * LDT + rho] = v;
+            rdst[rho] = v;
+          }
+        }
       }
     }
 
@@ -357,7 +411,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     if (tid == 0) { bufR[0] = T(1); bufR[CHI] = T(1); }
     for (int c = L - 1; c >= 0; --c) {
       __syncthreads();
-      for (int e = tid; e < int(site); e += NT) bufS[e] = Ain[size_t(c) * site + e];
+      for (int e = tid; e < int(site); e += NT) bufS[e] = widen(Ain[size_t(c) * site + e]);
       __syncthreads();
       T wv[2][2], wh[2][2];
 #pragma unroll
@@ -423,7 +477,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         const T nrm = sqrt(nrm2);
         for (int o = tid; o < int(site); o += NT) {
           const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
-          Aout[o] = (al == 0 && nrm > T(0)) ? sc[x * CHI + be] / nrm : T(0);
+          Aout[o] = narrow<E>((al == 0 && nrm > T(0)) ? sc[x * CHI + be] / nrm : T(0));
         }
         lambda += double(log2acc) * 0.69314718055994530942 + log(double(nrm));
         if (tid == 0) R.lognorm[r - 1] = lambda;
@@ -621,10 +675,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       // small kept rows are orthogonal to the large ones only up to rot ||T|| / sigma: make the
       // kept rows orthonormal (span unchanged)
       mgs2_rows<T, CHI, NT>(bufS, kept, T(JacobiTol<T>::eta));
-      T* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
+      E* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
       for (int o = tid; o < int(site); o += NT) {
         const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
-        bout[o] = bufS[al * N2 + x * CHI + be];
+        bout[o] = narrow<E>(bufS[al * N2 + x * CHI + be]);
       }
       // Xt_c = 2^-e_{c-1} Z V^T (N2 x CHI, column-major in bufR), then a power-of-two rescale
       const int ec = rexp[c - 1];
@@ -651,20 +705,20 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   // ---------------- ln Z_TN from the top row ----------------
   if (lnZ_out != nullptr) {
     __syncthreads();
-    const T* A0 = env;   // row 0
+    const E* A0 = env;   // row 0
     const uint64_t* jh0 = R.Jh;
-    for (int o = tid; o < 2 * CHI; o += NT) sc[o] = A0[(o / CHI) * CHI * CHI + (o % CHI)];
+    for (int o = tid; o < 2 * CHI; o += NT) sc[o] = widen(A0[(o / CHI) * CHI * CHI + (o % CHI)]);
     double logacc = 0;
     for (int c = 1; c < L; ++c) {
       __syncthreads();
-      const T* A = A0 + size_t(c) * site;
+      const E* A = A0 + size_t(c) * site;
       T mx = 0, val = 0;
       if (tid < 2 * CHI) {
         const int sp = tid / CHI, be = tid % CHI;
         for (int s2 = 0; s2 < 2; ++s2) {
           const T w = bond_weight<T>(jh0, c - 1, s2, sp, ep, em);
           T dd = 0;
-          for (int al = 0; al < CHI; ++al) dd += sc[s2 * CHI + al] * A[(sp * CHI + al) * CHI + be];
+          for (int al = 0; al < CHI; ++al) dd += sc[s2 * CHI + al] * widen(A[(sp * CHI + al) * CHI + be]);
           val += w * dd;
         }
         mx = fabs(val);
@@ -682,40 +736,39 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   }
 }
 
-template <typename T, int CHI>
+template <typename T, typename E, int CHI>
 hipError_t launch_env_build(const DevReal* d_reals, int n, double* d_lnZ, hipStream_t stream) {
   using S = EnvSmem<T, CHI>;
   static_assert(S::NT == env_tpc(CHI) * S::N2, "one group of TPC threads per column");
   static_assert(env_tpp(CHI) * CHI <= S::NT && env_tpp(CHI) <= 64, "Jacobi pair groups");
   static_assert(2 * CHI <= S::NT, "");
   static_assert(S::NT % 64 == 0, "");
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_kernel<T, CHI>),
+  static_assert(LeftCfg<CHI>::lds <= S::bufA, "left-sweep buffers fit in bufA");
+  static_assert(LeftCfg<CHI>::TPC * LeftCfg<CHI>::RPT >= LeftCfg<CHI>::MQ, "rows covered");
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_kernel<T, E, CHI>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(S::bytes));
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((env_build_kernel<T, CHI>), dim3(n), dim3(S::NT), S::bytes, stream, d_reals,
+  hipLaunchKernelGGL((env_build_kernel<T, E, CHI>), dim3(n), dim3(S::NT), S::bytes, stream, d_reals,
                      d_lnZ);
   return hipGetLastError();
 }
 
 hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n, double* d_lnZ,
                      hipStream_t stream) {
+#define TNMC_ENV_CASE(TY, EY, C) \
+  case C: return launch_env_build<TY, EY, C>(d_reals, n, d_lnZ, stream);
+#define TNMC_ENV_CHIS(TY, EY) \
+  TNMC_ENV_CASE(TY, EY, 2) TNMC_ENV_CASE(TY, EY, 4) TNMC_ENV_CASE(TY, EY, 8) \
+  TNMC_ENV_CASE(TY, EY, 16) TNMC_ENV_CASE(TY, EY, 32)
   if (prec == TNMC_FP64) {
-    switch (chi) {
-      case 2: return launch_env_build<double, 2>(d_reals, n, d_lnZ, stream);
-      case 4: return launch_env_build<double, 4>(d_reals, n, d_lnZ, stream);
-      case 8: return launch_env_build<double, 8>(d_reals, n, d_lnZ, stream);
-      case 16: return launch_env_build<double, 16>(d_reals, n, d_lnZ, stream);
-      case 32: return launch_env_build<double, 32>(d_reals, n, d_lnZ, stream);
-    }
-  } else {
-    switch (chi) {
-      case 2: return launch_env_build<float, 2>(d_reals, n, d_lnZ, stream);
-      case 4: return launch_env_build<float, 4>(d_reals, n, d_lnZ, stream);
-      case 8: return launch_env_build<float, 8>(d_reals, n, d_lnZ, stream);
-      case 16: return launch_env_build<float, 16>(d_reals, n, d_lnZ, stream);
-      case 32: return launch_env_build<float, 32>(d_reals, n, d_lnZ, stream);
-    }
+    switch (chi) { TNMC_ENV_CHIS(double, double) }
+  } else if (prec == TNMC_FP32) {
+    switch (chi) { TNMC_ENV_CHIS(float, float) }
+  } else if (prec == TNMC_BF16) {
+    switch (chi) { TNMC_ENV_CHIS(float, bf16_t) }
   }
+#undef TNMC_ENV_CHIS
+#undef TNMC_ENV_CASE
   return hipErrorInvalidValue;
 }
 

@@ -27,7 +27,8 @@ __device__ __forceinline__ T spin_weight(bool af, bool parallel, T ep, T em) {
   return (parallel != af) ? ep : em;
 }
 
-template <typename T, int CHI>
+// T: arithmetic type; E: storage type of the environments.
+template <typename T, typename E, int CHI>
 __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, int K, int Lmax,
                                                           uint64_t seed, uint64_t first,
                                                           const uint64_t* teacher,
@@ -46,7 +47,7 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
   const bool active = k < K;
   const int kk = active ? k : K - 1;   // inactive lanes shadow a valid proposal, write nothing
   const T ep = T(exp(R.beta)), em = T(exp(-R.beta));
-  const T* env = reinterpret_cast<const T*>(R.env);
+  const E* env = reinterpret_cast<const E*>(R.env);
   const size_t site = size_t(2) * CHI * CHI;
   // v store for this realization: [c][y][alpha][k]
   T* vs = reinterpret_cast<T*>(R.ws);
@@ -62,7 +63,7 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
   const uint64_t* tin = teacher ? teacher + (size_t(ri) * K + kk) * size_t(Lmax) * Wmax : nullptr;
 
   for (int r = 0; r < L; ++r) {
-    const T* Arow = env + size_t(r) * site * L;
+    const E* Arow = env + size_t(r) * site * L;
     const uint64_t* jh = R.Jh + size_t(r) * W;
     const uint64_t* jv = (r > 0) ? R.Jv + size_t(r - 1) * W : nullptr;
 
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
       for (int a = 0; a < CHI; ++a) Rn[y][a] = (a == 0) ? T(1) : T(0);
     for (int c = L - 1; c >= 0; --c) {
       __syncthreads();
-      for (int e = tid; e < int(site); e += PROP_NT) Bs[e] = Arow[size_t(c) * site + e];
+      for (int e = tid; e < int(site); e += PROP_NT) Bs[e] = widen(Arow[size_t(c) * site + e]);
       __syncthreads();
       T v[2][CHI];
 #pragma unroll
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
     int sprev = 0;   // 0 <-> +1, 1 <-> -1 (spin at c-1 of this row)
     for (int c = 0; c < L; ++c) {
       __syncthreads();
-      for (int e = tid; e < int(site); e += PROP_NT) Bs[e] = Arow[size_t(c) * site + e];
+      for (int e = tid; e < int(site); e += PROP_NT) Bs[e] = widen(Arow[size_t(c) * site + e]);
       __syncthreads();
       T pre[2] = {T(1), T(1)};
       if (r > 0) {
@@ -225,13 +226,13 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
   }
 }
 
-template <typename T, int CHI>
+template <typename T, typename E, int CHI>
 hipError_t launch_propose(const DevReal* d_reals, int n, int K, int Lmax, uint64_t seed,
                           uint64_t first, const uint64_t* d_teacher, uint64_t* d_spins,
                           double* d_logq, int32_t* d_E, uint32_t* d_fallbacks,
                           hipStream_t stream) {
   dim3 grid((K + PROP_NT - 1) / PROP_NT, n);
-  hipLaunchKernelGGL((propose_kernel<T, CHI>), grid, dim3(PROP_NT), 0, stream, d_reals, K, Lmax,
+  hipLaunchKernelGGL((propose_kernel<T, E, CHI>), grid, dim3(PROP_NT), 0, stream, d_reals, K, Lmax,
                      seed, first, d_teacher, d_spins, d_logq, d_E, d_fallbacks);
   return hipGetLastError();
 }
@@ -239,15 +240,21 @@ hipError_t launch_propose(const DevReal* d_reals, int n, int K, int Lmax, uint64
 hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, int K, int Lmax,
                    uint64_t seed, uint64_t first, const uint64_t* d_teacher, uint64_t* d_spins,
                    double* d_logq, int32_t* d_E, uint32_t* d_fallbacks, hipStream_t stream) {
-#define TNMC_PROP_CASE(TY, C)                                                                   \
+#define TNMC_PROP_CASE(TY, EY, C)                                                               \
   case C:                                                                                       \
-    return launch_propose<TY, C>(d_reals, n, K, Lmax, seed, first, d_teacher, d_spins, d_logq,  \
-                                 d_E, d_fallbacks, stream);
+    return launch_propose<TY, EY, C>(d_reals, n, K, Lmax, seed, first, d_teacher, d_spins,      \
+                                     d_logq, d_E, d_fallbacks, stream);
+#define TNMC_PROP_CHIS(TY, EY) \
+  TNMC_PROP_CASE(TY, EY, 2) TNMC_PROP_CASE(TY, EY, 4) TNMC_PROP_CASE(TY, EY, 8) \
+  TNMC_PROP_CASE(TY, EY, 16) TNMC_PROP_CASE(TY, EY, 32)
   if (prec == TNMC_FP64) {
-    switch (chi) { TNMC_PROP_CASE(double, 2) TNMC_PROP_CASE(double, 4) TNMC_PROP_CASE(double, 8) TNMC_PROP_CASE(double, 16) TNMC_PROP_CASE(double, 32) }
-  } else {
-    switch (chi) { TNMC_PROP_CASE(float, 2) TNMC_PROP_CASE(float, 4) TNMC_PROP_CASE(float, 8) TNMC_PROP_CASE(float, 16) TNMC_PROP_CASE(float, 32) }
+    switch (chi) { TNMC_PROP_CHIS(double, double) }
+  } else if (prec == TNMC_FP32) {
+    switch (chi) { TNMC_PROP_CHIS(float, float) }
+  } else if (prec == TNMC_BF16) {
+    switch (chi) { TNMC_PROP_CHIS(float, bf16_t) }
   }
+#undef TNMC_PROP_CHIS
 #undef TNMC_PROP_CASE
   return hipErrorInvalidValue;
 }

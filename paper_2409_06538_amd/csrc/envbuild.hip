@@ -102,6 +102,51 @@ __device__ __forceinline__ T bond_weight(const uint64_t* row_bits, int c, int sa
   return (parallel != af) ? ep : em;
 }
 
+// Householder reflector parameters for a column with pivot entry a and sub-pivot norm^2 s:
+// beta = -sign(a) sqrt(a^2 + s), tau = (beta - a) / beta, scal = 1 / (a - beta) (the scale that
+// makes v_pivot = 1).  FP32 uses the hardware reciprocal square root and reciprocal (about 1 ulp
+// each; the reflector stays orthogonal to working precision), FP64 the IEEE operations.
+__device__ __forceinline__ void hh_params(double a, double s, double& beta, double& tau,
+                                          double& scal) {
+  beta = -copysign(sqrt(a * a + s), a);
+  tau = (beta - a) / beta;
+  scal = 1.0 / (a - beta);
+}
+__device__ __forceinline__ void hh_params(float a, float s, float& beta, float& tau,
+                                          float& scal) {
+  const float n2 = a * a + s;
+  const float r = __builtin_amdgcn_rsqf(n2);
+  const float nrm = n2 * r;
+  beta = -copysign(nrm, a);
+  tau = 1.0f + fabsf(a) * r;
+  scal = copysign(__builtin_amdgcn_rcpf(fabsf(a) + nrm), a);
+}
+
+// One-sided Jacobi rotation of a row pair with norms^2 a, b and inner product cc (cc != 0):
+// t = tan(theta) with the smaller-angle root, cs = 1 / sqrt(1 + t^2), sn = cs t.  cs and sn form
+// an exact rotation to working precision whatever the rounding of t; FP32 uses hardware
+// reciprocal and reciprocal square root.
+__device__ __forceinline__ void jacobi_rot(double a, double b, double cc, double& cs, double& sn) {
+  const double zeta = (b - a) / (2.0 * cc);
+  double t;
+  if (fabs(zeta) > 1e15) t = 0.5 / zeta;
+  else t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  cs = 1.0 / sqrt(1.0 + t * t);
+  sn = cs * t;
+}
+__device__ __forceinline__ void jacobi_rot(float a, float b, float cc, float& cs, float& sn) {
+  const float zeta = (b - a) * __builtin_amdgcn_rcpf(2.0f * cc);
+  float t;
+  if (fabsf(zeta) > 1e15f) {
+    t = 0.5f * __builtin_amdgcn_rcpf(zeta);
+  } else {
+    const float q = 1.0f + zeta * zeta;
+    t = copysign(__builtin_amdgcn_rcpf(fabsf(zeta) + q * __builtin_amdgcn_rsqf(q)), zeta);
+  }
+  cs = __builtin_amdgcn_rsqf(1.0f + t * t);
+  sn = cs * t;
+}
+
 // C(M x N) = A(M x KD) B(KD x N) with TM x TN register tiles per thread; M % TM == N % TN == 0.
 // fa(i, k), fb(k, j) load operands, fc(i, j, v) stores a result.
 template <int TM, int TN, int KD, int NT, typename T, typename FA, typename FB, typename FC>
@@ -138,21 +183,18 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, FA fa, FB fb, FC fc) {
 template <typename T, int TPC, int RPT>
 __device__ __forceinline__ void make_reflector(const T (&m)[RPT], int j, int row0, int MQ, T* vb,
                                                T* taub, T* diag, int part) {
-  T s = 0, a = 0;
+  T sp[4] = {T(0), T(0), T(0), T(0)}, a = 0;
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
     const int rho = row0 + t;
-    s += (rho > j) ? m[t] * m[t] : T(0);
+    sp[t & 3] += (rho > j) ? m[t] * m[t] : T(0);
     a += (rho == j) ? m[t] : T(0);
   }
+  T s = (sp[0] + sp[1]) + (sp[2] + sp[3]);
   s = group_sum<TPC>(s);
   a = group_sum<TPC>(a);
   T tau = 0, beta = a, scal = 0;
-  if (s > T(0)) {
-    beta = -copysign(sqrt(a * a + s), a);
-    tau = (beta - a) / beta;
-    scal = T(1) / (a - beta);
-  }
+  if (s > T(0)) hh_params(a, s, beta, tau, scal);
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
     const int rho = row0 + t;
@@ -181,12 +223,13 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
     const T tau = taub[j & 1];
     if (g > j) {
       T vv[RPT];
-      T w = 0;
+      T wp[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
         vv[t] = vj[row0 + t];
-        w += vv[t] * m[t];
+        wp[t & 3] += vv[t] * m[t];
       }
+      T w = (wp[0] + wp[1]) + (wp[2] + wp[3]);
       w = group_sum<TPC>(w);
       const T tw = tau * w;
 #pragma unroll
@@ -282,8 +325,8 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   T* misc = red + NT / 64;          // 8
   int* perm = reinterpret_cast<int*>(misc + 8);   // N2 logical -> physical column
   int* ord = perm + N2;                           // N2
-  int* used = ord + N2;                           // N2
-  int* candi = used + N2;                         // 2 x NW
+  int* unpk = ord + N2;                           // N2: 1 = column not picked as a pivot
+  int* candi = unpk + N2;                         // 2 x NW
   int* imisc = candi + 2 * NW;                    // 8
   int* rexp = imisc + 8;                          // exponents of the carried R_c (L <= 1024)
 
@@ -526,11 +569,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         const T alpha = Tw[piv * LDT + j];
         const T ss = fmax(best - alpha * alpha, T(0));
         T tau = 0, beta = alpha, scal = 0;
-        if (ss > T(0)) {
-          beta = -copysign(sqrt(alpha * alpha + ss), alpha);
-          tau = (beta - alpha) / beta;
-          scal = T(1) / (alpha - beta);
-        }
+        if (ss > T(0)) hh_params(alpha, ss, beta, tau, scal);
         if (tid == 0) { diag[j] = beta; perm[j] = piv; }
         if (g == piv) active = false;
         T cand = T(-1);
@@ -580,12 +619,16 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         }
         __syncthreads();
       }
-      if (owner && part == 0) used[g] = active ? 0 : 1;
+      // columns never picked follow the pivots in ascending order
+      if (owner && part == 0) unpk[g] = active ? 1 : 0;
       __syncthreads();
-      if (tid == 0) {
-        int p = rank;
-        for (int col = 0; col < N2; ++col)
-          if (!used[col]) perm[p++] = col;
+      {
+        static_assert(2 * CHI <= WAVE, "one wave ranks the unused columns");
+        if (tid < WAVE) {
+          const bool un = tid < N2 && unpk[tid];
+          const unsigned long long mask = __ballot(un);
+          if (un) perm[rank + __popcll(mask & ((1ull << tid) - 1ull))] = tid;
+        }
       }
       __syncthreads();
       // J = rows 0..rank-1 of R in pivoted column order (row-major in bufR, ld LDT)
@@ -599,7 +642,9 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       __syncthreads();
 
       // ---- one-sided Jacobi on the rows of J, parallel round-robin ordering ----
-      if (nr >= 2) {
+      // Needed only when the numerical rank exceeds CHI: otherwise every direction is kept, and
+      // the span of the rows of J (what site c of E_{r-1} depends on) is already final.
+      if (nr >= 2 && rank > CHI) {
         const T tol = JacobiTol<T>::rot * sqrt(fro2);
         const int gj = tid / TPP, l = tid % TPP;
         const int npair = nr / 2;
@@ -624,13 +669,9 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
               a = group_sum<TPP>(a);
               b = group_sum<TPP>(b);
               cc = group_sum<TPP>(cc);
-              if (a > T(0) && b > T(0) && fabs(cc) > tol * sqrt(fmax(a, b))) {
-                const T zeta = (b - a) / (T(2) * cc);
-                T t;
-                if (fabs(zeta) > T(1e15)) t = T(0.5) / zeta;
-                else t = copysign(T(1), zeta) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
-                const T cs = T(1) / sqrt(T(1) + t * t);
-                const T sn = cs * t;
+              if (a > T(0) && b > T(0) && cc * cc > tol * tol * fmax(a, b)) {
+                T cs, sn;
+                jacobi_rot(a, b, cc, cs, sn);
 #pragma unroll
                 for (int e = 0; e < EPT; ++e) {
                   const int k = l + TPP * e;
@@ -648,16 +689,28 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         }
       }
       // ---- row norms, descending order, kept rows (normalised) into V ----
-      for (int i = tid; i < N2; i += NT) {
-        T s2 = 0;
-        if (i < rank)
-          for (int k = 0; k < N2; ++k) s2 += bufR[i * LDT + k] * bufR[i * LDT + k];
-        sc[i] = s2;
+      {
+        const int gj = tid / TPP, l = tid % TPP;
+        for (int i0 = 0; i0 < N2; i0 += NT / TPP) {
+          const int i = i0 + gj;
+          T s2 = 0;
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            const int k = l + TPP * e;
+            const T x = (i < rank && k < N2) ? bufR[i * LDT + k] : T(0);
+            s2 += x * x;
+          }
+          s2 = group_sum<TPP>(s2);
+          if (l == 0 && i < N2) sc[i] = s2;
+        }
       }
       __syncthreads();
       for (int i = tid; i < rank; i += NT) {
-        int pos = 0;
-        for (int j2 = 0; j2 < rank; ++j2) pos += (sc[j2] > sc[i]) || (sc[j2] == sc[i] && j2 < i);
+        int pos = i;
+        if (rank > CHI) {   // only the CHI largest are kept; otherwise any order will do
+          pos = 0;
+          for (int j2 = 0; j2 < rank; ++j2) pos += (sc[j2] > sc[i]) || (sc[j2] == sc[i] && j2 < i);
+        }
         ord[pos] = i;
       }
       __syncthreads();

@@ -226,14 +226,360 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// MFMA form (chi a multiple of 16).  A wavefront owns 16 proposals; four wavefronts share each
+// site tensor through LDS.  Per site and per spin value y the right sweep is the product
+// V_y = B_c[y] R_y (chi x chi times chi x 16) and the left sweep U_y^T = B_c[y]^T l (the same
+// shape), both as 16x16x4 matrix-core tiles.  The k index of every product runs over the rows
+// that the output tile of the previous product leaves in the same lane, so R and l stay in
+// registers from site to site: no transposes.  Lane group q = lane / 16 holds, for proposal
+// p = lane % 16, rows 16 t + row(q, r) of R, l and V (t < chi / 16, r < 4).
+
+template <typename T>
+struct Mf;
+template <>
+struct Mf<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mac(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output row of a 16 x 16 tile held by lane group q in register r
+  __host__ __device__ static constexpr int row(int q, int r) { return 4 * q + r; }
+  // LDS column of index x (< 16) so that the four rows row(q, 0..3) are adjacent
+  __host__ __device__ static constexpr int pos(int x) { return x; }
+};
+template <>
+struct Mf<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  __device__ static v4 mac(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __host__ __device__ static constexpr int row(int q, int r) { return q + 4 * r; }
+  __host__ __device__ static constexpr int pos(int x) { return 4 * (x & 3) + (x >> 2); }
+};
+
+constexpr int MF_WAVES = 4;
+constexpr int MF_NT = 64 * MF_WAVES;
+constexpr int MF_PROP = 16 * MF_WAVES;   // proposals per workgroup
+
+template <typename T, typename E, int CHI>
+__global__ __launch_bounds__(MF_NT) void propose_mfma_kernel(const DevReal* reals, int K, int Lmax,
+                                                             uint64_t seed, uint64_t first,
+                                                             const uint64_t* teacher,
+                                                             uint64_t* spins_out, double* logq_out,
+                                                             int32_t* E_out, uint32_t* fallbacks) {
+  using M = Mf<T>;
+  using V4 = typename M::v4;
+  constexpr int RT = CHI / 16;                   // 16-row tiles of a site matrix
+  constexpr int NV = 2 * RT * 4;                 // V values per lane (y, tile, register)
+  constexpr int PV = 16 / int(sizeof(T));        // values per 16-byte chunk
+  constexpr int LDB = CHI + PV;                  // LDS row stride of a site matrix
+  constexpr int SITE = 2 * CHI * CHI;
+  constexpr int SPT = (SITE + MF_NT - 1) / MF_NT;   // site elements loaded per thread
+  __shared__ __align__(16) T Bs[2][2 * CHI * LDB];
+  __shared__ uint64_t rows[2][MAX_W][MF_PROP];
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int pl = lane & 15, q = lane >> 4;
+  const int slot = wv * 16 + pl;
+  const int ri = blockIdx.y;
+  const DevReal R = reals[ri];
+  const int L = R.L;
+  const int W = words_per_row(L);
+  const int Wmax = words_per_row(Lmax);
+  const int k = blockIdx.x * MF_PROP + slot;
+  const bool active = k < K;
+  const int kk = active ? k : K - 1;   // inactive slots shadow a valid proposal, write nothing
+  const T ep = T(exp(R.beta)), em = T(exp(-R.beta));
+  const E* env = reinterpret_cast<const E*>(R.env);
+  // V store of this wavefront: [c][chunk][lane][PV]
+  T* vbase = reinterpret_cast<T*>(R.ws) + (size_t(blockIdx.x) * L * MF_WAVES + wv) * (64 * NV) +
+             lane * PV;
+  const size_t vstep = size_t(MF_WAVES) * 64 * NV;   // per site
+  const uint64_t pid = first + uint64_t(kk);
+  const uint64_t* tin = teacher ? teacher + (size_t(ri) * K + kk) * size_t(Lmax) * Wmax : nullptr;
+
+  for (int e = tid; e < 2 * MAX_W * MF_PROP; e += MF_NT) (&rows[0][0][0])[e] = 0ull;
+  double logq = 0.0;
+  uint32_t nfb = 0;
+  int unsat = 0;
+  int pr = 0;   // rows[pr]: row above; rows[pr ^ 1]: row being drawn
+
+  E pf[SPT];
+  auto load_site = [&](int r, int c) {
+    const E* src = env + (size_t(r) * L + c) * SITE;
+#pragma unroll
+    for (int t = 0; t < SPT; ++t) {
+      const int e = tid + MF_NT * t;
+      if (SITE % MF_NT == 0 || e < SITE) pf[t] = src[e];
+    }
+  };
+  // right sweep: row alpha, column beta; left sweep (transposed): row beta, column alpha
+  auto store_site = [&](T* dst, bool transposed) {
+#pragma unroll
+    for (int t = 0; t < SPT; ++t) {
+      const int e = tid + MF_NT * t;
+      if (SITE % MF_NT == 0 || e < SITE) {
+        const int y = e / (CHI * CHI), a = (e / CHI) % CHI, b = e % CHI;
+        const int rr = transposed ? b : a, cc = transposed ? a : b;
+        dst[(y * CHI + rr) * LDB + (cc & ~15) + M::pos(cc & 15)] = widen(pf[t]);
+      }
+    }
+  };
+  // C = sum over the chi contraction index of Bsb[y][16 ro + pl][.] times the register operand
+  auto tile_products = [&](const T* Bsb, const T (&opnd)[2][RT][4], V4 (&acc)[2][RT]) {
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int ro = 0; ro < RT; ++ro) {
+        V4 a = {T(0), T(0), T(0), T(0)};
+        const T* ap = Bsb + (y * CHI + 16 * ro + pl) * LDB + 4 * q;
+#pragma unroll
+        for (int m = 0; m < RT; ++m) {
+          T av[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) av[r] = ap[16 * m + r];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) a = M::mac(av[r], opnd[y][m][r], a);
+        }
+        acc[y][ro] = a;
+      }
+  };
+  // maximum over the four lane groups of a proposal (identical in all four lanes)
+  auto group4_max = [&](T v) {
+    v = fmax(v, __shfl_xor(v, 16));
+    return fmax(v, __shfl_xor(v, 32));
+  };
+  auto group4_sum = [&](T v) {
+    v += __shfl_xor(v, 16);
+    return v + __shfl_xor(v, 32);
+  };
+
+  int b = 0;
+  for (int r = 0; r < L; ++r) {
+    const uint64_t* jh = R.Jh + size_t(r) * W;
+    const uint64_t* jv = (r > 0) ? R.Jv + size_t(r - 1) * W : nullptr;
+    const uint64_t* prow = &rows[pr][0][slot];       // word w at prow[w * MF_PROP]
+    uint64_t* crow = &rows[pr ^ 1][0][slot];
+
+    // ---- right sweep: V_c(y) = B_c[y] R_c(y) for c = L-1 .. 0 ----
+    T rc[2][RT][4];
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) rc[y][t][i] = (t == 0 && M::row(q, i) == 0) ? T(1) : T(0);
+    load_site(r, L - 1);
+    store_site(Bs[b], false);
+    __syncthreads();
+    for (int c = L - 1; c >= 0; --c) {
+      if (c > 0) load_site(r, c - 1);
+      V4 acc[2][RT];
+      tile_products(Bs[b], rc, acc);
+      T* vo = vbase + size_t(c) * vstep;
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int h = 0; h < 4; h += PV) {
+            const int chunk = ((y * RT + t) * 4 + h) / PV;
+            if constexpr (PV == 4) {
+              *reinterpret_cast<V4*>(vo + chunk * 64 * PV) = acc[y][t];
+            } else {
+              typedef T v2 __attribute__((ext_vector_type(2)));
+              v2 d = {acc[y][t][h], acc[y][t][h + 1]};
+              *reinterpret_cast<v2*>(vo + chunk * 64 * PV) = d;
+            }
+          }
+      if (c > 0) {
+        T ph[2] = {T(1), T(1)};
+        if (r > 0) {
+          const bool af = (jv[c >> 6] >> (c & 63)) & 1ull;
+          const bool sm = (prow[(c >> 6) * MF_PROP] >> (c & 63)) & 1ull;   // spin above is -1
+          ph[0] = spin_weight<T>(af, !sm, ep, em);
+          ph[1] = spin_weight<T>(af, sm, ep, em);
+        }
+        const bool afh = (jh[(c - 1) >> 6] >> ((c - 1) & 63)) & 1ull;
+        const T wpp = spin_weight<T>(afh, true, ep, em), wpm = spin_weight<T>(afh, false, ep, em);
+        T mx = 0;
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const T t0 = ph[0] * acc[0][t][i], t1 = ph[1] * acc[1][t][i];
+            rc[0][t][i] = wpp * t0 + wpm * t1;
+            rc[1][t][i] = wpm * t0 + wpp * t1;
+            mx = fmax(mx, fmax(fabs(rc[0][t][i]), fabs(rc[1][t][i])));
+          }
+        const int e = pow2_exponent(group4_max(mx));
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+          for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) rc[y][t][i] = T(ldexp(rc[y][t][i], -e));
+        store_site(Bs[b ^ 1], false);
+      }
+      __syncthreads();
+      if (c > 0) b ^= 1;
+    }
+
+    // ---- left sweep: draw s_c from Z_c(y) = pre(y) (l . V_c(y)), then l <- pre(s) B_c[s]^T l ----
+    T el[2][RT][4];   // el[0] = l (el[1] unused: same shape as the product operand)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) el[y][t][i] = (t == 0 && M::row(q, i) == 0) ? T(1) : T(0);
+    b ^= 1;
+    load_site(r, 0);
+    store_site(Bs[b], true);
+    __syncthreads();
+    Philox4 blk{};
+    int sprev = 0;   // 0 <-> +1, 1 <-> -1 (spin at c-1 of this row)
+    uint64_t curw = 0, tword = 0;
+    for (int c = 0; c < L; ++c) {
+      if (c + 1 < L) load_site(r, c + 1);
+      const T* vi = vbase + size_t(c) * vstep;
+      T vv[2][RT][4];
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+          for (int h = 0; h < 4; h += PV) {
+            const int chunk = ((y * RT + t) * 4 + h) / PV;
+#pragma unroll
+            for (int u = 0; u < PV; ++u) vv[y][t][h + u] = vi[chunk * 64 * PV + u];
+          }
+      T pre[2] = {T(1), T(1)};
+      if (r > 0) {
+        const bool af = (jv[c >> 6] >> (c & 63)) & 1ull;
+        const bool sm = (prow[(c >> 6) * MF_PROP] >> (c & 63)) & 1ull;
+        pre[0] = spin_weight<T>(af, !sm, ep, em);
+        pre[1] = spin_weight<T>(af, sm, ep, em);
+      }
+      if (c > 0) {
+        const bool afh = (jh[(c - 1) >> 6] >> ((c - 1) & 63)) & 1ull;
+        pre[0] *= spin_weight<T>(afh, sprev == 0, ep, em);
+        pre[1] *= spin_weight<T>(afh, sprev == 1, ep, em);
+      }
+      T zp = 0, zm = 0;
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          zp += el[0][t][i] * vv[0][t][i];
+          zm += el[0][t][i] * vv[1][t][i];
+        }
+      zp = pre[0] * group4_sum(zp);
+      zm = pre[1] * group4_sum(zm);
+      const double dzp = double(zp) > 0.0 ? double(zp) : 0.0;
+      const double dzm = double(zm) > 0.0 ? double(zm) : 0.0;
+      const double tot = dzp + dzm;
+      double pp;
+      if (!(tot > 0.0) || !isfinite(tot)) {
+        pp = 0.5;
+        ++nfb;
+      } else {
+        pp = dzp / tot;
+      }
+      pp = fmin(fmax(pp, P_CLAMP), 1.0 - P_CLAMP);
+      bool up;
+      if (teacher) {
+        if ((c & 63) == 0) tword = tin[size_t(r) * Wmax + (c >> 6)];
+        up = !((tword >> (c & 63)) & 1ull);
+      } else {
+        if ((c & 3) == 0) blk = philox4x64_10(uint64_t(c) >> 2, uint64_t(r), pid, R.id, seed, STREAM_PROPOSAL);
+        const int qq = c & 3;
+        const uint64_t wsel = qq == 0 ? blk.w[0] : qq == 1 ? blk.w[1] : qq == 2 ? blk.w[2] : blk.w[3];
+        up = u53(wsel) < pp;
+      }
+      logq += up ? log(pp) : log(1.0 - pp);
+      const int s = up ? 0 : 1;
+      if (!up) curw |= (1ull << (c & 63));
+      if ((c & 63) == 63 || c == L - 1) {
+        if (q == 0) crow[(c >> 6) * MF_PROP] = curw;
+        curw = 0;
+      }
+      // l <- pre(s) B_c[s]^T l (both products; each proposal keeps its own)
+      V4 u[2][RT];
+      tile_products(Bs[b], el, u);
+      T mx = 0;
+      const T ps = s == 0 ? pre[0] : pre[1];
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          el[0][t][i] = ps * (s == 0 ? u[0][t][i] : u[1][t][i]);
+          mx = fmax(mx, fabs(el[0][t][i]));
+        }
+      const int e = pow2_exponent(group4_max(mx));
+#pragma unroll
+      for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          el[0][t][i] = T(ldexp(el[0][t][i], -e));
+          el[1][t][i] = el[0][t][i];
+        }
+      sprev = s;
+      if (c + 1 < L) store_site(Bs[b ^ 1], true);
+      __syncthreads();
+      if (c + 1 < L) b ^= 1;
+    }
+    b ^= 1;
+
+    // ---- energy bookkeeping (one lane per proposal): unsatisfied bonds of row r and r-1, r ----
+    if (q == 0) {
+      for (int w = 0; w < W; ++w) {
+        const uint64_t cw = crow[w * MF_PROP];
+        const uint64_t nxt = (w + 1 < W) ? crow[(w + 1) * MF_PROP] : 0ull;
+        const uint64_t right = (cw >> 1) | (nxt << 63);
+        const int nb_h = (L - 1) - 64 * w;
+        const uint64_t mh = nb_h >= 64 ? ~0ull : (nb_h > 0 ? ((1ull << nb_h) - 1) : 0ull);
+        unsat += __popcll((cw ^ right ^ jh[w]) & mh);
+        if (r > 0) {
+          const int nb_v = L - 64 * w;
+          const uint64_t mv = nb_v >= 64 ? ~0ull : ((1ull << nb_v) - 1);
+          unsat += __popcll((prow[w * MF_PROP] ^ cw ^ jv[w]) & mv);
+        }
+      }
+      if (active && !teacher) {
+        uint64_t* so = spins_out + ((size_t(ri) * K + k) * Lmax + r) * Wmax;
+        for (int w = 0; w < Wmax; ++w) so[w] = (w < W) ? crow[w * MF_PROP] : 0ull;
+      }
+    }
+    pr ^= 1;
+  }
+  if (active && q == 0) {
+    logq_out[size_t(ri) * K + k] = logq;
+    if (!teacher) {
+      E_out[size_t(ri) * K + k] = 2 * unsat - 2 * L * (L - 1);
+      for (int r = L; r < Lmax; ++r) {
+        uint64_t* so = spins_out + ((size_t(ri) * K + k) * Lmax + r) * Wmax;
+        for (int w = 0; w < Wmax; ++w) so[w] = 0ull;
+      }
+    }
+    if (fallbacks && nfb) atomicAdd(fallbacks + ri, nfb);
+  }
+}
+
 template <typename T, typename E, int CHI>
 hipError_t launch_propose(const DevReal* d_reals, int n, int K, int Lmax, uint64_t seed,
                           uint64_t first, const uint64_t* d_teacher, uint64_t* d_spins,
                           double* d_logq, int32_t* d_E, uint32_t* d_fallbacks,
                           hipStream_t stream) {
-  dim3 grid((K + PROP_NT - 1) / PROP_NT, n);
-  hipLaunchKernelGGL((propose_kernel<T, E, CHI>), grid, dim3(PROP_NT), 0, stream, d_reals, K, Lmax,
-                     seed, first, d_teacher, d_spins, d_logq, d_E, d_fallbacks);
+  if constexpr (CHI % 16 == 0) {
+    dim3 grid((K + MF_PROP - 1) / MF_PROP, n);
+    hipLaunchKernelGGL((propose_mfma_kernel<T, E, CHI>), grid, dim3(MF_NT), 0, stream, d_reals, K,
+                       Lmax, seed, first, d_teacher, d_spins, d_logq, d_E, d_fallbacks);
+  } else {
+    dim3 grid((K + PROP_NT - 1) / PROP_NT, n);
+    hipLaunchKernelGGL((propose_kernel<T, E, CHI>), grid, dim3(PROP_NT), 0, stream, d_reals, K,
+                       Lmax, seed, first, d_teacher, d_spins, d_logq, d_E, d_fallbacks);
+  }
   return hipGetLastError();
 }
 
@@ -260,8 +606,10 @@ hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, 
 }
 
 size_t propose_scratch_bytes(tnmc_precision prec, int chi, int L, int K) {
+  static_assert(MF_PROP == PROP_NT, "both forms pad K to the same workgroup size");
   const size_t elem = (prec == TNMC_FP64) ? 8 : 4;
-  return size_t(L) * 2 * chi * size_t(K) * elem;
+  const size_t kpad = size_t(K + PROP_NT - 1) / PROP_NT * PROP_NT;
+  return size_t(L) * 2 * chi * kpad * elem;   // V_c(y) of one row for every proposal
 }
 
 }  // namespace tnmc

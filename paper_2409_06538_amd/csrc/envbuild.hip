@@ -312,7 +312,6 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   constexpr int TPP = env_tpp(CHI);   // threads per Jacobi row pair
   constexpr int TPC = env_tpc(CHI);   // threads per column in the QR updates
   constexpr int EPT = (N2 + TPP - 1) / TPP;   // elements per thread of a Jacobi row
-  constexpr int ER2 = (N2 + TPC - 1) / TPC;   // rows per thread in the pivoted QR
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* bufA = reinterpret_cast<T*>(smem_raw);
   T* bufR = bufA + S::bufA;
@@ -537,15 +536,25 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       __syncthreads();
 
       // ---- QR with column pivoting, stopping at the numerical rank ----
-      // Group g (TPC threads) owns physical column g for the whole factorisation.
-      const int g = tid / TPC, part = tid % TPC;
+      // Group g (TPC threads) owns physical column g; thread part keeps rows [part * RPT2, +RPT2)
+      // in registers and republishes them in Tw after each update, so that every thread reads the
+      // next pivot column from LDS and forms its reflector itself (one barrier per column).
+      constexpr int RPT2 = (N2 + TPC - 1) / TPC;
+      const int g = tid / TPC, part = tid % TPC, row0 = part * RPT2;
       const bool owner = g < N2;
       bool active = owner;
+      T mc[RPT2];
       T cn = 0;
-      if (owner) {
-        for (int i = part; i < N2; i += TPC) cn += Tw[g * LDT + i] * Tw[g * LDT + i];
+      {
+        T cp[4] = {T(0), T(0), T(0), T(0)};
+#pragma unroll
+        for (int t = 0; t < RPT2; ++t) {
+          const int rho = row0 + t;
+          mc[t] = (owner && rho < N2) ? Tw[g * LDT + rho] : T(0);
+          cp[t & 3] += mc[t] * mc[t];
+        }
+        cn = group_sum<TPC>((cp[0] + cp[1]) + (cp[2] + cp[3]));
       }
-      cn = group_sum<TPC>(cn);
       {
         T bv = owner ? cn : T(-1);
         int bi = owner ? g : N2;
@@ -557,59 +566,60 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       int rank = N2;
       for (int j = 0; j < N2; ++j) {
         const int buf = j & 1;
-        T best = candv[buf * NW];
-        int piv = candi[buf * NW];
+        // arg-max of the per-wave candidates (ties -> smaller column), without branches
+        T cv[NW];
+        int ci[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          cv[w] = candv[buf * NW + w];
+          ci[w] = candi[buf * NW + w];
+        }
+        T best = cv[0];
+        int piv = ci[0];
 #pragma unroll
         for (int w = 1; w < NW; ++w) {
-          const T ob = candv[buf * NW + w];
-          const int oi = candi[buf * NW + w];
-          if (ob > best || (ob == best && oi < piv)) { best = ob; piv = oi; }
+          const bool better = (cv[w] > best) | ((cv[w] == best) & (ci[w] < piv));
+          best = better ? cv[w] : best;
+          piv = better ? ci[w] : piv;
         }
         if (!(best > tolr2)) { rank = j; break; }
-        const T alpha = Tw[piv * LDT + j];
+        const T* pc = Tw + piv * LDT;
+        const T alpha = pc[j];
         const T ss = fmax(best - alpha * alpha, T(0));
         T tau = 0, beta = alpha, scal = 0;
         if (ss > T(0)) hh_params(alpha, ss, beta, tau, scal);
         if (tid == 0) { diag[j] = beta; perm[j] = piv; }
         if (g == piv) active = false;
-        T cand = T(-1);
-        T w = T(0), nn = T(0);
-        T v[ER2], m[ER2];
-        if (active) {
-          const T a0 = Tw[g * LDT + j];
-          if (part == 0) w = a0;
+        T v[RPT2];
+        T wp[4] = {T(0), T(0), T(0), T(0)};
+        // loads first and unconditional (a select on the loaded value would let the compiler
+        // move each load under its own branch and wait for it there)
+        T u[RPT2];
 #pragma unroll
-          for (int e = 0; e < ER2; ++e) {
-            const int i = j + 1 + part + TPC * e;   // may run past N2: read in bounds, value masked
-            const T vi = Tw[piv * LDT + i], mi = Tw[g * LDT + i];
-            const bool ok = i < N2;
-            v[e] = ok ? vi * scal : T(0);
-            m[e] = ok ? mi : T(0);
-          }
+        for (int t = 0; t < RPT2; ++t) u[t] = pc[(N2 % TPC == 0 || row0 + t < N2) ? row0 + t : 0];
 #pragma unroll
-          for (int e = 0; e < ER2; ++e) w += v[e] * m[e];
+        for (int t = 0; t < RPT2; ++t) {
+          const int rho = row0 + t;
+          const T sg = (rho > j && rho < N2) ? scal : T(0);
+          const T one = (rho == j) ? T(1) : T(0);
+          v[t] = u[t] * sg + one;
+          wp[t & 3] += v[t] * mc[t];
         }
-        w = group_sum<TPC>(w);
+        const T w = group_sum<TPC>((wp[0] + wp[1]) + (wp[2] + wp[3]));
+        T np[4] = {T(0), T(0), T(0), T(0)};
         if (active) {
           const T tw = tau * w;
-          if (part == 0) Tw[g * LDT + j] -= tw;
 #pragma unroll
-          for (int e = 0; e < ER2; ++e) {
-            const int i = j + 1 + part + TPC * e;
-            if (i < N2) {
-              const T nv = m[e] - tw * v[e];
-              Tw[g * LDT + i] = nv;
-              nn += nv * nv;
-            }
+          for (int t = 0; t < RPT2; ++t) {
+            const int rho = row0 + t;
+            mc[t] -= tw * v[t];
+            np[t & 3] += (rho > j) ? mc[t] * mc[t] : T(0);
+            if (N2 % TPC == 0 || rho < N2) Tw[g * LDT + rho] = mc[t];
           }
         }
-        nn = group_sum<TPC>(nn);
-        if (active) {
-          cn = nn;
-          cand = nn;
-        }
+        const T nn = group_sum<TPC>((np[0] + np[1]) + (np[2] + np[3]));
         {
-          T bv = cand;
+          T bv = active ? nn : T(-1);
           int bi = active ? g : N2;
           wave_argmax(bv, bi);
           if ((tid & (WAVE - 1)) == 0) {
@@ -660,8 +670,15 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
 #pragma unroll
               for (int e = 0; e < EPT; ++e) {
                 const int k = l + TPP * e;
-                xp[e] = (k < N2) ? bufR[p * LDT + k] : T(0);
-                xq[e] = (k < N2) ? bufR[q * LDT + k] : T(0);
+                const int kc = (N2 % TPP == 0 || k < N2) ? k : 0;   // in bounds; masked below
+                xp[e] = bufR[p * LDT + kc];
+                xq[e] = bufR[q * LDT + kc];
+              }
+#pragma unroll
+              for (int e = 0; e < EPT; ++e) {
+                const T mk = (N2 % TPP == 0 || l + TPP * e < N2) ? T(1) : T(0);
+                xp[e] *= mk;
+                xq[e] *= mk;
                 a += xp[e] * xp[e];
                 b += xq[e] * xq[e];
                 cc += xp[e] * xq[e];

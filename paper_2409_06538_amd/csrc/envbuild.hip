@@ -44,6 +44,16 @@ struct JacobiTol<float> {
   static constexpr float eta = 1e-5f;
 };
 
+// Tolerances follow the storage precision of the environments.
+template <typename E>
+struct TolOf {
+  using type = E;
+};
+template <>
+struct TolOf<bf16_t> {
+  using type = float;
+};
+
 constexpr int MAX_SWEEPS = 40;
 // 32 threads per unit of CHI, at most 512 (8 waves, two per SIMD, so that LDS and barrier latency
 // of one wave overlaps with the other's work while each keeps 256 registers).
@@ -100,6 +110,35 @@ __device__ __forceinline__ T bond_weight(const uint64_t* row_bits, int c, int sa
   const bool af = (row_bits[c >> 6] >> (c & 63)) & 1ull;
   const bool parallel = (sa == sb);
   return (parallel != af) ? ep : em;
+}
+
+// C (M x N) = A (M x K) B (K x N) in FP64 on 16x16x4 matrix-core tiles (M, N multiples of 16,
+// K of 4).  Each wavefront takes whole 16 x 16 output tiles; lane (i, q) = (lane % 16, lane / 16)
+// feeds A(i, k0 + q) and B(k0 + q, j) and receives rows q + 4 r of column i of its tile.
+// fa(i, k) and fb(k, j) read the operands, fc(i, j, v) stores.
+template <int M, int N, int K, int NT, typename FA, typename FB, typename FC>
+__device__ __forceinline__ void mfma_gemm_f64(FA fa, FB fb, FC fc) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  static_assert(M % 16 == 0 && N % 16 == 0 && K % 16 == 0, "matrix-core tile shapes");
+  constexpr int TM = M / 16, TN = N / 16, NWV = NT / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i16 = lane & 15, q = lane >> 4;
+  for (int t = wv; t < TM * TN; t += NWV) {
+    const int r0 = (t % TM) * 16, c0 = (t / TM) * 16;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = fa(r0 + i16, k0 + 4 * u + q);
+        b[u] = fb(k0 + 4 * u + q, c0 + i16);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fc(r0 + q + 4 * r, c0 + i16, acc[r]);
+  }
 }
 
 // Householder reflector parameters for a column with pivot entry a and sub-pivot norm^2 s:
@@ -302,10 +341,14 @@ __device__ void mgs2_rows(T* V, int k, T eta) {
   }
 }
 
-// T: arithmetic type; E: storage type of the environments (T, or bf16_t with T = float).
-template <typename T, typename E, int CHI>
+// T: arithmetic type; E: storage type of the environments.  GRAM selects the Gram form of both
+// sweeps (FP64 arithmetic for FP32 / BF16 environments): the QR sweep carries G_c = R_c^T R_c,
+// and the SVD step factors Z_c^T G_{c-1} Z_c = (R_{c-1} Z_c)^T (R_{c-1} Z_c) by pivoted Cholesky,
+// whose factor is the R of the pivoted QR of R_{c-1} Z_c (same pivots, same rows up to sign).
+template <typename T, typename E, int CHI, bool GRAM>
 __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevReal* reals,
                                                                      double* lnZ_out) {
+  using Tol = JacobiTol<typename TolOf<E>::type>;
   using S = EnvSmem<T, CHI>;
   constexpr int N2 = S::N2, MQ = S::MQ, LDT = S::LDT, LDZ = S::LDZ;
   constexpr int NT = S::NT, NW = S::NW, TL = S::TILE;
@@ -356,7 +399,156 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     const uint64_t* jv = R.Jv + size_t(r - 1) * W;    // vertical bonds between rows r-1 and r
     long long log2acc = 0;
 
-    // ---------------- left to right: R factors ----------------
+    if constexpr (GRAM) {
+      // ---------------- left to right: Gram matrices ----------------
+      // With At_c = wh(a,b) wv(x,b) A_c[b]:
+      //   G_c[(b,.),(b',.)] = kx(b,b') A_c[b]^T P_bb' A_c[b'],  kx(b,b') = sum_x wv(x,b) wv(x,b'),
+      //   P_bb' = sum_{a,a'} wh(a,b) wh(a',b') G_{c-1}[(a,.),(a',.)];  G_0 = kx A_0[b][0]^T A_0[b'][0].
+      // G_c is rescaled by 4^-e_c (R_c by 2^-e_c) and kept for the second sweep.
+      constexpr int LDC = CHI + 2;
+      static_assert(4 * CHI * LDC <= N2 * LDT, "P and Q blocks fit a Gram buffer");
+      static_assert(size_t(N2) * LDT + size_t(2) * CHI * LDC <= S::bufA, "left-sweep buffers");
+      T* gX = bufA;                        // G_{c-1} (N2 x LDT), then Q
+      T* gY = bufR;                        // P, then G_c
+      T* As2 = bufA + size_t(N2) * LDT;    // A_c[b][al][ap], ld LDC
+      constexpr int tmb = CHI / TL;
+      for (int c = 0; c < L - 1; ++c) {
+        __syncthreads();
+        for (int e = tid; e < int(site); e += NT) {
+          const int b = e / (CHI * CHI), al = (e / CHI) % CHI, ap = e % CHI;
+          As2[(b * CHI + al) * LDC + ap] = widen(Ain[size_t(c) * site + e]);
+        }
+        T kx[2][2];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int b2 = 0; b2 < 2; ++b2)
+            kx[b][b2] = bond_weight<T>(jv, c, 0, b, ep, em) * bond_weight<T>(jv, c, 0, b2, ep, em) +
+                        bond_weight<T>(jv, c, 1, b, ep, em) * bond_weight<T>(jv, c, 1, b2, ep, em);
+        __syncthreads();
+        if (c == 0) {
+          for (int o = tid; o < N2 * N2; o += NT) {
+            const int i = o / N2, k = o % N2;
+            const int b = i / CHI, ap = i % CHI, b2 = k / CHI, ap2 = k % CHI;
+            const T f = b ? (b2 ? kx[1][1] : kx[1][0]) : (b2 ? kx[0][1] : kx[0][0]);
+            gY[i * LDT + k] = f * As2[(b * CHI) * LDC + ap] * As2[(b2 * CHI) * LDC + ap2];
+          }
+        } else {
+          T wh2[2][2];
+#pragma unroll
+          for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b) wh2[a][b] = bond_weight<T>(jh, c - 1, a, b, ep, em);
+          for (int o = tid; o < 4 * CHI * CHI; o += NT) {
+            const int blk = o / (CHI * CHI), al = (o / CHI) % CHI, al2 = o % CHI;
+            const int b = blk >> 1, b2 = blk & 1;
+            // (selects, not indexing with the runtime b: that would put the table in scratch)
+            const T w0b = b ? wh2[0][1] : wh2[0][0], w1b = b ? wh2[1][1] : wh2[1][0];
+            const T w0c = b2 ? wh2[0][1] : wh2[0][0], w1c = b2 ? wh2[1][1] : wh2[1][0];
+            T p = w0b * w0c * gX[al * LDT + al2];
+            p += w0b * w1c * gX[al * LDT + CHI + al2];
+            p += w1b * w0c * gX[(CHI + al) * LDT + al2];
+            p += w1b * w1c * gX[(CHI + al) * LDT + CHI + al2];
+            gY[(blk * CHI + al) * LDC + al2] = p;
+          }
+          __syncthreads();
+          if constexpr (CHI % 16 == 0) {
+            // Q_bb' = P_bb' A_c[b'] (into gX), then G_c = kx A_c[b]^T Q_bb' (into gY)
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk) {
+              const int b2 = blk & 1;
+              mfma_gemm_f64<CHI, CHI, CHI, NT>(
+                  [&](int i, int k) { return gY[(blk * CHI + i) * LDC + k]; },
+                  [&](int k, int j) { return As2[(b2 * CHI + k) * LDC + j]; },
+                  [&](int i, int j, T v) { gX[(blk * CHI + i) * LDC + j] = v; });
+            }
+            __syncthreads();
+#pragma unroll
+            for (int blk = 0; blk < 4; ++blk) {
+              const int b = blk >> 1, b2 = blk & 1;
+              const T f = kx[b][b2];
+              mfma_gemm_f64<CHI, CHI, CHI, NT>(
+                  [&](int i, int k) { return As2[(b * CHI + k) * LDC + i]; },
+                  [&](int k, int j) { return gX[(blk * CHI + k) * LDC + j]; },
+                  [&](int i, int j, T v) { gY[(b * CHI + i) * LDT + b2 * CHI + j] = f * v; });
+            }
+          } else {
+            // Q_bb' = P_bb' A_c[b'] (into gX)
+            for (int t = tid; t < 4 * tmb * tmb; t += NT) {
+              const int blk = t / (tmb * tmb), tt = t % (tmb * tmb);
+              const int i0 = (tt % tmb) * TL, j0 = (tt / tmb) * TL, b2 = blk & 1;
+              T acc[TL][TL];
+  #pragma unroll
+              for (int u = 0; u < TL; ++u)
+  #pragma unroll
+                for (int v = 0; v < TL; ++v) acc[u][v] = T(0);
+  #pragma unroll 8
+              for (int k = 0; k < CHI; ++k) {
+                T av[TL], bv[TL];
+  #pragma unroll
+                for (int u = 0; u < TL; ++u) av[u] = gY[(blk * CHI + i0 + u) * LDC + k];
+  #pragma unroll
+                for (int v = 0; v < TL; ++v) bv[v] = As2[(b2 * CHI + k) * LDC + j0 + v];
+  #pragma unroll
+                for (int u = 0; u < TL; ++u)
+  #pragma unroll
+                  for (int v = 0; v < TL; ++v) acc[u][v] += av[u] * bv[v];
+              }
+  #pragma unroll
+              for (int u = 0; u < TL; ++u)
+  #pragma unroll
+                for (int v = 0; v < TL; ++v) gX[(blk * CHI + i0 + u) * LDC + j0 + v] = acc[u][v];
+            }
+            __syncthreads();
+            // G_c = kx A_c[b]^T Q_bb' (into gY)
+            for (int t = tid; t < 4 * tmb * tmb; t += NT) {
+              const int blk = t / (tmb * tmb), tt = t % (tmb * tmb);
+              const int i0 = (tt % tmb) * TL, j0 = (tt / tmb) * TL, b = blk >> 1, b2 = blk & 1;
+              T acc[TL][TL];
+  #pragma unroll
+              for (int u = 0; u < TL; ++u)
+  #pragma unroll
+                for (int v = 0; v < TL; ++v) acc[u][v] = T(0);
+  #pragma unroll 8
+              for (int k = 0; k < CHI; ++k) {
+                T av[TL], bv[TL];
+  #pragma unroll
+                for (int u = 0; u < TL; ++u) av[u] = As2[(b * CHI + k) * LDC + i0 + u];
+  #pragma unroll
+                for (int v = 0; v < TL; ++v) bv[v] = gX[(blk * CHI + k) * LDC + j0 + v];
+  #pragma unroll
+                for (int u = 0; u < TL; ++u)
+  #pragma unroll
+                  for (int v = 0; v < TL; ++v) acc[u][v] += av[u] * bv[v];
+              }
+              const T f = b ? (b2 ? kx[1][1] : kx[1][0]) : (b2 ? kx[0][1] : kx[0][0]);
+  #pragma unroll
+              for (int u = 0; u < TL; ++u)
+  #pragma unroll
+                for (int v = 0; v < TL; ++v)
+                  gY[(b * CHI + i0 + u) * LDT + b2 * CHI + j0 + v] = f * acc[u][v];
+            }
+          }
+          }
+        __syncthreads();
+        T mx = 0;
+        for (int o = tid; o < N2 * N2; o += NT) mx = fmax(mx, fabs(gY[(o / N2) * LDT + o % N2]));
+        mx = block_max<NT>(mx, red);
+        const int e = (pow2_exponent(mx) + 1) / 2;
+        log2acc += e;
+        if (tid == 0) rexp[c] = e;
+        T* gdst = rs + size_t(c) * N2 * N2;
+        for (int o = tid; o < N2 * N2; o += NT) {
+          const int i = o / N2, k = o % N2;
+          const T v = T(ldexp(gY[i * LDT + k], -2 * e));
+          gY[i * LDT + k] = v;
+          gdst[o] = v;
+        }
+        T* tmp = gX;
+        gX = gY;
+        gY = tmp;
+      }
+    } else // ---------------- left to right: R factors ----------------
     {
       using C = LeftCfg<CHI>;
       constexpr int TPC = C::TPC, RPT = C::RPT, LDAT = C::LDAT, LDRT = C::LDRT;
@@ -525,137 +717,252 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         if (tid == 0) R.lognorm[r - 1] = lambda;
         break;
       }
-      // R_{c-1} into bufR, then T = R_{c-1} Z
-      const T* rsrc = rs + size_t(c - 1) * N2 * N2;
-      for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = rsrc[o];
-      __syncthreads();
-      gemm_tiles<TL, TL, N2, NT, T>(
-          N2, N2, [&](int i, int a) { return bufR[a * LDT + i]; },
-          [&](int a, int col) { return Zr[a * LDZ + col]; },
-          [&](int i, int col, T v) { Tw[col * LDT + i] = v; });
-      __syncthreads();
-
-      // ---- QR with column pivoting, stopping at the numerical rank ----
-      // Group g (TPC threads) owns physical column g; thread part keeps rows [part * RPT2, +RPT2)
-      // in registers and republishes them in Tw after each update, so that every thread reads the
-      // next pivot column from LDS and forms its reflector itself (one barrier per column).
-      constexpr int RPT2 = (N2 + TPC - 1) / TPC;
-      const int g = tid / TPC, part = tid % TPC, row0 = part * RPT2;
-      const bool owner = g < N2;
-      bool active = owner;
-      T mc[RPT2];
-      T cn = 0;
-      {
-        T cp[4] = {T(0), T(0), T(0), T(0)};
-#pragma unroll
-        for (int t = 0; t < RPT2; ++t) {
-          const int rho = row0 + t;
-          mc[t] = (owner && rho < N2) ? Tw[g * LDT + rho] : T(0);
-          cp[t & 3] += mc[t] * mc[t];
-        }
-        cn = group_sum<TPC>((cp[0] + cp[1]) + (cp[2] + cp[3]));
-      }
-      {
-        T bv = owner ? cn : T(-1);
-        int bi = owner ? g : N2;
-        wave_argmax(bv, bi);
-        if ((tid & (WAVE - 1)) == 0) { candv[tid / WAVE] = bv; candi[tid / WAVE] = bi; }
-      }
-      const T fro2 = block_sum<NT>((owner && part == 0) ? cn : T(0), red);
-      const T tolr2 = JacobiTol<T>::rank * JacobiTol<T>::rank * fro2;
       int rank = N2;
-      for (int j = 0; j < N2; ++j) {
-        const int buf = j & 1;
-        // arg-max of the per-wave candidates (ties -> smaller column), without branches
-        T cv[NW];
-        int ci[NW];
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          cv[w] = candv[buf * NW + w];
-          ci[w] = candi[buf * NW + w];
-        }
-        T best = cv[0];
-        int piv = ci[0];
-#pragma unroll
-        for (int w = 1; w < NW; ++w) {
-          const bool better = (cv[w] > best) | ((cv[w] == best) & (ci[w] < piv));
-          best = better ? cv[w] : best;
-          piv = better ? ci[w] : piv;
-        }
-        if (!(best > tolr2)) { rank = j; break; }
-        const T* pc = Tw + piv * LDT;
-        const T alpha = pc[j];
-        const T ss = fmax(best - alpha * alpha, T(0));
-        T tau = 0, beta = alpha, scal = 0;
-        if (ss > T(0)) hh_params(alpha, ss, beta, tau, scal);
-        if (tid == 0) { diag[j] = beta; perm[j] = piv; }
-        if (g == piv) active = false;
-        T v[RPT2];
-        T wp[4] = {T(0), T(0), T(0), T(0)};
-        // loads first and unconditional (a select on the loaded value would let the compiler
-        // move each load under its own branch and wait for it there)
-        T u[RPT2];
-#pragma unroll
-        for (int t = 0; t < RPT2; ++t) u[t] = pc[(N2 % TPC == 0 || row0 + t < N2) ? row0 + t : 0];
-#pragma unroll
-        for (int t = 0; t < RPT2; ++t) {
-          const int rho = row0 + t;
-          const T sg = (rho > j && rho < N2) ? scal : T(0);
-          const T one = (rho == j) ? T(1) : T(0);
-          v[t] = u[t] * sg + one;
-          wp[t & 3] += v[t] * mc[t];
-        }
-        const T w = group_sum<TPC>((wp[0] + wp[1]) + (wp[2] + wp[3]));
-        T np[4] = {T(0), T(0), T(0), T(0)};
-        if (active) {
-          const T tw = tau * w;
-#pragma unroll
-          for (int t = 0; t < RPT2; ++t) {
-            const int rho = row0 + t;
-            mc[t] -= tw * v[t];
-            np[t & 3] += (rho > j) ? mc[t] * mc[t] : T(0);
-            if (N2 % TPC == 0 || rho < N2) Tw[g * LDT + rho] = mc[t];
-          }
-        }
-        const T nn = group_sum<TPC>((np[0] + np[1]) + (np[2] + np[3]));
-        {
-          T bv = active ? nn : T(-1);
-          int bi = active ? g : N2;
-          wave_argmax(bv, bi);
-          if ((tid & (WAVE - 1)) == 0) {
-            candv[(buf ^ 1) * NW + tid / WAVE] = bv;
-            candi[(buf ^ 1) * NW + tid / WAVE] = bi;
+      T fro2 = 0;
+      if constexpr (GRAM) {
+        // H = Z^T G_{c-1} Z (row-major in bufR, symmetrised), via W = G_{c-1} Z (in Tw)
+        const T* gsrc = rs + size_t(c - 1) * N2 * N2;
+        for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = gsrc[o];
+        __syncthreads();
+        auto ga = [&](int i, int k) { return bufR[i * LDT + k]; };
+        auto gb = [&](int k, int col) { return Zr[k * LDZ + col]; };
+        auto gc = [&](int i, int col, T v) { Tw[i * LDT + col] = v; };
+        auto ha = [&](int c1, int i) { return Zr[i * LDZ + c1]; };
+        auto hb = [&](int i, int c2) { return Tw[i * LDT + c2]; };
+        auto hc = [&](int c1, int c2, T v) { bufR[c1 * LDT + c2] = v; };
+        if constexpr (CHI % 16 == 0) mfma_gemm_f64<N2, N2, N2, NT>(ga, gb, gc);
+        else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ga, gb, gc);
+        __syncthreads();
+        if constexpr (CHI % 16 == 0) mfma_gemm_f64<N2, N2, N2, NT>(ha, hb, hc);
+        else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ha, hb, hc);
+        __syncthreads();
+        for (int o = tid; o < N2 * N2; o += NT) {
+          const int c1 = o / N2, c2 = o % N2;
+          if (c1 < c2) {
+            const T h = T(0.5) * (bufR[c1 * LDT + c2] + bufR[c2 * LDT + c1]);
+            bufR[c1 * LDT + c2] = h;
+            bufR[c2 * LDT + c1] = h;
           }
         }
         __syncthreads();
-      }
-      // columns never picked follow the pivots in ascending order
-      if (owner && part == 0) unpk[g] = active ? 1 : 0;
-      __syncthreads();
-      {
-        static_assert(2 * CHI <= WAVE, "one wave ranks the unused columns");
-        if (tid < WAVE) {
-          const bool un = tid < N2 && unpk[tid];
-          const unsigned long long mask = __ballot(un);
-          if (un) perm[rank + __popcll(mask & ((1ull << tid) - 1ull))] = tid;
+        // ---- pivoted Cholesky of H, stopping at the numerical rank: H[p, p] = L L^T ----
+        // Left-looking: with p_j the pivot of step j (largest remaining diagonal d),
+        //   L[a][j] = (H[a][p_j] - sum_{i<j} L[a][i] L[p_j][i]) / sqrt(d[p_j]),  d[a] -= L[a][j]^2.
+        // The TPR threads of row a split the sum; row j of L^T (natural column order) goes to Tw.
+        constexpr int TPR = NT / N2;
+        constexpr int PW = (N2 + 63) / 64;
+        const int ra = tid / TPR, cpart = tid % TPR;
+        uint64_t pk[PW];
+#pragma unroll
+        for (int w = 0; w < PW; ++w) pk[w] = 0ull;
+        // (a one-word mask is indexed statically: a dynamic index would put pk in scratch memory)
+        auto picked = [&](int i) {
+          if constexpr (PW == 1) return ((pk[0] >> (i & 63)) & 1ull) != 0ull;
+          else return ((pk[i >> 6] >> (i & 63)) & 1ull) != 0ull;
+        };
+        T dreg = bufR[ra * LDT + ra];
+        fro2 = block_sum<NT>(cpart == 0 ? fmax(dreg, T(0)) : T(0), red);
+        {
+          T bv = cpart == 0 ? dreg : T(-1);
+          int bi = cpart == 0 ? ra : N2;
+          wave_argmax(bv, bi);
+          if ((tid & (WAVE - 1)) == 0) { candv[tid / WAVE] = bv; candi[tid / WAVE] = bi; }
         }
+        __syncthreads();
+        const T tolr2 = T(Tol::rank) * T(Tol::rank) * fro2;
+        for (int j = 0; j < N2; ++j) {
+          const int buf = j & 1;
+          T cv[NW];
+          int ci[NW];
+#pragma unroll
+          for (int w = 0; w < NW; ++w) {
+            cv[w] = candv[buf * NW + w];
+            ci[w] = candi[buf * NW + w];
+          }
+          T best = cv[0];
+          int piv = ci[0];
+#pragma unroll
+          for (int w = 1; w < NW; ++w) {
+            const bool better = (cv[w] > best) | ((cv[w] == best) & (ci[w] < piv));
+            best = better ? cv[w] : best;
+            piv = better ? ci[w] : piv;
+          }
+          if (!(best > tolr2)) { rank = j; break; }
+          const T sq = sqrt(best), inv = T(1) / sq;
+          T dot = 0;
+          for (int i = cpart; i < j; i += TPR) dot += Tw[i * LDT + ra] * Tw[i * LDT + piv];
+          dot = group_sum<TPR>(dot);
+          const bool arow = !picked(ra) && ra != piv;
+          const T La = (ra == piv) ? sq : (arow ? (bufR[ra * LDT + piv] - dot) * inv : T(0));
+          if (cpart == 0) Tw[j * LDT + ra] = La;
+          dreg -= arow ? La * La : T(0);
+          if constexpr (PW == 1) pk[0] |= 1ull << (piv & 63);
+          else pk[piv >> 6] |= 1ull << (piv & 63);
+          if (tid == 0) perm[j] = piv;
+          {
+            T bv = (cpart == 0 && arow) ? dreg : T(-1);
+            int bi = (cpart == 0 && arow) ? ra : N2;
+            wave_argmax(bv, bi);
+            if ((tid & (WAVE - 1)) == 0) {
+              candv[(buf ^ 1) * NW + tid / WAVE] = bv;
+              candi[(buf ^ 1) * NW + tid / WAVE] = bi;
+            }
+          }
+          __syncthreads();
+        }
+        // columns never picked follow the pivots in ascending order
+        if (tid < N2) unpk[tid] = picked(tid) ? 0 : 1;
+        __syncthreads();
+        {
+          static_assert(2 * CHI <= WAVE, "one wave ranks the unused columns");
+          if (tid < WAVE) {
+            const bool un = tid < N2 && unpk[tid];
+            const unsigned long long mask = __ballot(un);
+            if (un) perm[rank + __popcll(mask & ((1ull << tid) - 1ull))] = tid;
+          }
+        }
+        __syncthreads();
+        // J = rows 0..rank-1 of L^T in pivoted column order (row-major in bufR, ld LDT)
+        const int nr = rank + (rank & 1);
+        for (int o = tid; o < nr * N2; o += NT) {
+          const int i = o / N2, kk = o % N2;
+          bufR[i * LDT + kk] = (i < rank) ? Tw[i * LDT + perm[kk]] : T(0);
+        }
+        __syncthreads();
+      } else {
+        // R_{c-1} into bufR, then T = R_{c-1} Z
+        const T* rsrc = rs + size_t(c - 1) * N2 * N2;
+        for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = rsrc[o];
+        __syncthreads();
+        gemm_tiles<TL, TL, N2, NT, T>(
+            N2, N2, [&](int i, int a) { return bufR[a * LDT + i]; },
+            [&](int a, int col) { return Zr[a * LDZ + col]; },
+            [&](int i, int col, T v) { Tw[col * LDT + i] = v; });
+        __syncthreads();
+
+        // ---- QR with column pivoting, stopping at the numerical rank ----
+        // Group g (TPC threads) owns physical column g; thread part keeps rows [part * RPT2, +RPT2)
+        // in registers and republishes them in Tw after each update, so that every thread reads the
+        // next pivot column from LDS and forms its reflector itself (one barrier per column).
+        constexpr int RPT2 = (N2 + TPC - 1) / TPC;
+        const int g = tid / TPC, part = tid % TPC, row0 = part * RPT2;
+        const bool owner = g < N2;
+        bool active = owner;
+        T mc[RPT2];
+        T cn = 0;
+        {
+          T cp[4] = {T(0), T(0), T(0), T(0)};
+  #pragma unroll
+          for (int t = 0; t < RPT2; ++t) {
+            const int rho = row0 + t;
+            mc[t] = (owner && rho < N2) ? Tw[g * LDT + rho] : T(0);
+            cp[t & 3] += mc[t] * mc[t];
+          }
+          cn = group_sum<TPC>((cp[0] + cp[1]) + (cp[2] + cp[3]));
+        }
+        {
+          T bv = owner ? cn : T(-1);
+          int bi = owner ? g : N2;
+          wave_argmax(bv, bi);
+          if ((tid & (WAVE - 1)) == 0) { candv[tid / WAVE] = bv; candi[tid / WAVE] = bi; }
+        }
+        fro2 = block_sum<NT>((owner && part == 0) ? cn : T(0), red);
+        const T tolr2 = T(Tol::rank) * T(Tol::rank) * fro2;
+        rank = N2;
+        for (int j = 0; j < N2; ++j) {
+          const int buf = j & 1;
+          // arg-max of the per-wave candidates (ties -> smaller column), without branches
+          T cv[NW];
+          int ci[NW];
+  #pragma unroll
+          for (int w = 0; w < NW; ++w) {
+            cv[w] = candv[buf * NW + w];
+            ci[w] = candi[buf * NW + w];
+          }
+          T best = cv[0];
+          int piv = ci[0];
+  #pragma unroll
+          for (int w = 1; w < NW; ++w) {
+            const bool better = (cv[w] > best) | ((cv[w] == best) & (ci[w] < piv));
+            best = better ? cv[w] : best;
+            piv = better ? ci[w] : piv;
+          }
+          if (!(best > tolr2)) { rank = j; break; }
+          const T* pc = Tw + piv * LDT;
+          const T alpha = pc[j];
+          const T ss = fmax(best - alpha * alpha, T(0));
+          T tau = 0, beta = alpha, scal = 0;
+          if (ss > T(0)) hh_params(alpha, ss, beta, tau, scal);
+          if (tid == 0) { diag[j] = beta; perm[j] = piv; }
+          if (g == piv) active = false;
+          T v[RPT2];
+          T wp[4] = {T(0), T(0), T(0), T(0)};
+          // loads first and unconditional (a select on the loaded value would let the compiler
+          // move each load under its own branch and wait for it there)
+          T u[RPT2];
+  #pragma unroll
+          for (int t = 0; t < RPT2; ++t) u[t] = pc[(N2 % TPC == 0 || row0 + t < N2) ? row0 + t : 0];
+  #pragma unroll
+          for (int t = 0; t < RPT2; ++t) {
+            const int rho = row0 + t;
+            const T sg = (rho > j && rho < N2) ? scal : T(0);
+            const T one = (rho == j) ? T(1) : T(0);
+            v[t] = u[t] * sg + one;
+            wp[t & 3] += v[t] * mc[t];
+          }
+          const T w = group_sum<TPC>((wp[0] + wp[1]) + (wp[2] + wp[3]));
+          T np[4] = {T(0), T(0), T(0), T(0)};
+          if (active) {
+            const T tw = tau * w;
+  #pragma unroll
+            for (int t = 0; t < RPT2; ++t) {
+              const int rho = row0 + t;
+              mc[t] -= tw * v[t];
+              np[t & 3] += (rho > j) ? mc[t] * mc[t] : T(0);
+              if (N2 % TPC == 0 || rho < N2) Tw[g * LDT + rho] = mc[t];
+            }
+          }
+          const T nn = group_sum<TPC>((np[0] + np[1]) + (np[2] + np[3]));
+          {
+            T bv = active ? nn : T(-1);
+            int bi = active ? g : N2;
+            wave_argmax(bv, bi);
+            if ((tid & (WAVE - 1)) == 0) {
+              candv[(buf ^ 1) * NW + tid / WAVE] = bv;
+              candi[(buf ^ 1) * NW + tid / WAVE] = bi;
+            }
+          }
+          __syncthreads();
+        }
+        // columns never picked follow the pivots in ascending order
+        if (owner && part == 0) unpk[g] = active ? 1 : 0;
+        __syncthreads();
+        {
+          static_assert(2 * CHI <= WAVE, "one wave ranks the unused columns");
+          if (tid < WAVE) {
+            const bool un = tid < N2 && unpk[tid];
+            const unsigned long long mask = __ballot(un);
+            if (un) perm[rank + __popcll(mask & ((1ull << tid) - 1ull))] = tid;
+          }
+        }
+        __syncthreads();
+        // J = rows 0..rank-1 of R in pivoted column order (row-major in bufR, ld LDT)
+        const int nr = rank + (rank & 1);
+        for (int o = tid; o < nr * N2; o += NT) {
+          const int i = o / N2, kk = o % N2;
+          T val = T(0);
+          if (i < rank) val = (kk > i) ? Tw[perm[kk] * LDT + i] : (kk == i ? diag[i] : T(0));
+          bufR[i * LDT + kk] = val;
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      // J = rows 0..rank-1 of R in pivoted column order (row-major in bufR, ld LDT)
       const int nr = rank + (rank & 1);
-      for (int o = tid; o < nr * N2; o += NT) {
-        const int i = o / N2, kk = o % N2;
-        T val = T(0);
-        if (i < rank) val = (kk > i) ? Tw[perm[kk] * LDT + i] : (kk == i ? diag[i] : T(0));
-        bufR[i * LDT + kk] = val;
-      }
-      __syncthreads();
 
       // ---- one-sided Jacobi on the rows of J, parallel round-robin ordering ----
       // Needed only when the numerical rank exceeds CHI: otherwise every direction is kept, and
       // the span of the rows of J (what site c of E_{r-1} depends on) is already final.
       if (nr >= 2 && rank > CHI) {
-        const T tol = JacobiTol<T>::rot * sqrt(fro2);
+        const T tol = T(Tol::rot) * sqrt(fro2);
         const int gj = tid / TPP, l = tid % TPP;
         const int npair = nr / 2;
         for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
@@ -744,7 +1051,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       }
       // small kept rows are orthogonal to the large ones only up to rot ||T|| / sigma: make the
       // kept rows orthonormal (span unchanged)
-      mgs2_rows<T, CHI, NT>(bufS, kept, T(JacobiTol<T>::eta));
+      mgs2_rows<T, CHI, NT>(bufS, kept, T(Tol::eta));
       E* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
       for (int o = tid; o < int(site); o += NT) {
         const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
@@ -806,7 +1113,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   }
 }
 
-template <typename T, typename E, int CHI>
+template <typename T, typename E, int CHI, bool GRAM>
 hipError_t launch_env_build(const DevReal* d_reals, int n, double* d_lnZ, hipStream_t stream) {
   using S = EnvSmem<T, CHI>;
   static_assert(S::NT == env_tpc(CHI) * S::N2, "one group of TPC threads per column");
@@ -815,27 +1122,29 @@ hipError_t launch_env_build(const DevReal* d_reals, int n, double* d_lnZ, hipStr
   static_assert(S::NT % 64 == 0, "");
   static_assert(LeftCfg<CHI>::lds <= S::bufA, "left-sweep buffers fit in bufA");
   static_assert(LeftCfg<CHI>::TPC * LeftCfg<CHI>::RPT >= LeftCfg<CHI>::MQ, "rows covered");
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_kernel<T, E, CHI>),
+  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_kernel<T, E, CHI, GRAM>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(S::bytes));
   if (err != hipSuccess) return err;
-  hipLaunchKernelGGL((env_build_kernel<T, E, CHI>), dim3(n), dim3(S::NT), S::bytes, stream, d_reals,
+  hipLaunchKernelGGL((env_build_kernel<T, E, CHI, GRAM>), dim3(n), dim3(S::NT), S::bytes, stream, d_reals,
                      d_lnZ);
   return hipGetLastError();
 }
 
 hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n, double* d_lnZ,
                      hipStream_t stream) {
-#define TNMC_ENV_CASE(TY, EY, C) \
-  case C: return launch_env_build<TY, EY, C>(d_reals, n, d_lnZ, stream);
-#define TNMC_ENV_CHIS(TY, EY) \
-  TNMC_ENV_CASE(TY, EY, 2) TNMC_ENV_CASE(TY, EY, 4) TNMC_ENV_CASE(TY, EY, 8) \
-  TNMC_ENV_CASE(TY, EY, 16) TNMC_ENV_CASE(TY, EY, 32)
+#define TNMC_ENV_CASE(TY, EY, C, G) \
+  case C: return launch_env_build<TY, EY, C, G>(d_reals, n, d_lnZ, stream);
+#define TNMC_ENV_CHIS(TY, EY, G) \
+  TNMC_ENV_CASE(TY, EY, 2, G) TNMC_ENV_CASE(TY, EY, 4, G) TNMC_ENV_CASE(TY, EY, 8, G) \
+  TNMC_ENV_CASE(TY, EY, 16, G) TNMC_ENV_CASE(TY, EY, 32, G)
+  // FP64 environments: Householder / pivoted-QR form in FP64.  FP32 and BF16 environments: Gram
+  // form in FP64 arithmetic, results rounded to the storage type.
   if (prec == TNMC_FP64) {
-    switch (chi) { TNMC_ENV_CHIS(double, double) }
+    switch (chi) { TNMC_ENV_CHIS(double, double, false) }
   } else if (prec == TNMC_FP32) {
-    switch (chi) { TNMC_ENV_CHIS(float, float) }
+    switch (chi) { TNMC_ENV_CHIS(double, float, true) }
   } else if (prec == TNMC_BF16) {
-    switch (chi) { TNMC_ENV_CHIS(float, bf16_t) }
+    switch (chi) { TNMC_ENV_CHIS(double, bf16_t, true) }
   }
 #undef TNMC_ENV_CHIS
 #undef TNMC_ENV_CASE
@@ -843,8 +1152,8 @@ hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n
 }
 
 size_t env_build_scratch_bytes(tnmc_precision prec, int chi, int L) {
-  const size_t elem = (prec == TNMC_FP64) ? 8 : 4;
-  return size_t(L) * 2 * chi * 2 * chi * elem;   // the carried R factor of every site
+  (void)prec;   // every form keeps FP64: the carried R factor or Gram matrix of every site
+  return size_t(L) * 2 * chi * 2 * chi * sizeof(double);
 }
 
 }  // namespace tnmc

@@ -21,6 +21,8 @@
 // workgroup barrier per column.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -349,6 +351,8 @@ template <typename T, typename E, int CHI, bool GRAM>
 __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevReal* reals,
                                                                      double* lnZ_out) {
   using Tol = JacobiTol<typename TolOf<E>::type>;
+  // FP64 products on matrix-core tiles where the shapes allow
+  constexpr bool MF64 = std::is_same<T, double>::value && CHI % 16 == 0;
   using S = EnvSmem<T, CHI>;
   constexpr int N2 = S::N2, MQ = S::MQ, LDT = S::LDT, LDZ = S::LDZ;
   constexpr int NT = S::NT, NW = S::NW, TL = S::TILE;
@@ -452,7 +456,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
             gY[(blk * CHI + al) * LDC + al2] = p;
           }
           __syncthreads();
-          if constexpr (CHI % 16 == 0) {
+          if constexpr (MF64) {
             // Q_bb' = P_bb' A_c[b'] (into gX), then G_c = kx A_c[b]^T Q_bb' (into gY)
 #pragma unroll
             for (int blk = 0; blk < 4; ++blk) {
@@ -658,6 +662,34 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         for (int b = 0; b < 2; ++b)
           wh[a][b] = (c > 0) ? bond_weight<T>(jh, c - 1, a, b, ep, em) : (a == 0 ? T(1) : T(0));
       // Z[(a,al)][(x,be)] = sum_b wh(a,b) wv(x,b) (A_c[b] Xt_b)[al][be]
+      if constexpr (MF64) {
+        // both products of an output tile on 16x16x4 FP64 matrix-core tiles, combined in registers
+        typedef double v4d __attribute__((ext_vector_type(4)));
+        constexpr int TT = CHI / 16;
+        const int lane = tid & 63, wvi = tid >> 6, i16 = lane & 15, qg = lane >> 4;
+        for (int t = wvi; t < TT * TT; t += NW) {
+          const int r0 = (t % TT) * 16, c0 = (t / TT) * 16;
+          v4d p0 = {0.0, 0.0, 0.0, 0.0}, p1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int k0 = 0; k0 < CHI; k0 += 4) {
+            const int k = k0 + qg;
+            const double a0 = bufS[(r0 + i16) * CHI + k], a1 = bufS[(CHI + r0 + i16) * CHI + k];
+            const double x0 = bufR[(c0 + i16) * LDT + k], x1 = bufR[(c0 + i16) * LDT + CHI + k];
+            p0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, p0, 0, 0, 0);
+            p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, p1, 0, 0, 0);
+          }
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int al = r0 + qg + 4 * rr, be = c0 + i16;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+              for (int x = 0; x < 2; ++x)
+                Zr[(a * CHI + al) * LDZ + x * CHI + be] =
+                    wh[a][0] * wv[x][0] * p0[rr] + wh[a][1] * wv[x][1] * p1[rr];
+          }
+        }
+      } else
       {
         constexpr int tm = CHI / TL;
         for (int t = tid; t < tm * tm; t += NT) {
@@ -730,10 +762,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         auto ha = [&](int c1, int i) { return Zr[i * LDZ + c1]; };
         auto hb = [&](int i, int c2) { return Tw[i * LDT + c2]; };
         auto hc = [&](int c1, int c2, T v) { bufR[c1 * LDT + c2] = v; };
-        if constexpr (CHI % 16 == 0) mfma_gemm_f64<N2, N2, N2, NT>(ga, gb, gc);
+        if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ga, gb, gc);
         else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ga, gb, gc);
         __syncthreads();
-        if constexpr (CHI % 16 == 0) mfma_gemm_f64<N2, N2, N2, NT>(ha, hb, hc);
+        if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ha, hb, hc);
         else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ha, hb, hc);
         __syncthreads();
         for (int o = tid; o < N2 * N2; o += NT) {
@@ -834,10 +866,11 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         const T* rsrc = rs + size_t(c - 1) * N2 * N2;
         for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = rsrc[o];
         __syncthreads();
-        gemm_tiles<TL, TL, N2, NT, T>(
-            N2, N2, [&](int i, int a) { return bufR[a * LDT + i]; },
-            [&](int a, int col) { return Zr[a * LDZ + col]; },
-            [&](int i, int col, T v) { Tw[col * LDT + i] = v; });
+        auto ta = [&](int i, int a) { return bufR[a * LDT + i]; };
+        auto tb = [&](int a, int col) { return Zr[a * LDZ + col]; };
+        auto tc = [&](int i, int col, T v) { Tw[col * LDT + i] = v; };
+        if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ta, tb, tc);
+        else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ta, tb, tc);
         __syncthreads();
 
         // ---- QR with column pivoting, stopping at the numerical rank ----
@@ -1060,14 +1093,17 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       // Xt_c = 2^-e_{c-1} Z V^T (N2 x CHI, column-major in bufR), then a power-of-two rescale
       const int ec = rexp[c - 1];
       T mx = 0;
-      gemm_tiles<TL, TL, N2, NT, T>(
-          N2, CHI, [&](int j, int col) { return Zr[j * LDZ + col]; },
-          [&](int col, int al) { return bufS[al * N2 + col]; },
-          [&](int j, int al, T val) {
-            const T d = T(ldexp(val, -ec));
-            bufR[al * LDT + j] = d;
-            mx = fmax(mx, fabs(d));
-          });
+      {
+        auto xa = [&](int j, int col) { return Zr[j * LDZ + col]; };
+        auto xb = [&](int col, int al) { return bufS[al * N2 + col]; };
+        auto xc = [&](int j, int al, T val) {
+          const T d = T(ldexp(val, -ec));
+          bufR[al * LDT + j] = d;
+          mx = fmax(mx, fabs(d));
+        };
+        if constexpr (MF64) mfma_gemm_f64<N2, CHI, N2, NT>(xa, xb, xc);
+        else gemm_tiles<TL, TL, N2, NT, T>(N2, CHI, xa, xb, xc);
+      }
       mx = block_max<NT>(mx, red);
       const int e = pow2_exponent(mx);
       log2acc += e;

@@ -144,6 +144,17 @@ __device__ __forceinline__ void wave_argmax(T& v, int& i) {
   i = bi;
 }
 
+// Unsigned maximum over a whole wavefront; every lane gets the result.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  auto mx = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+  v = mx(v, uint32_t(dpp<0xB1>(int(v))));
+  v = mx(v, uint32_t(dpp<0x4E>(int(v))));
+  v = mx(v, uint32_t(dpp<0x141>(int(v))));
+  v = mx(v, uint32_t(dpp<0x140>(int(v))));
+  return mx(mx(uint32_t(readlane_i(int(v), 0)), uint32_t(readlane_i(int(v), 16))),
+            mx(uint32_t(readlane_i(int(v), 32)), uint32_t(readlane_i(int(v), 48))));
+}
+
 // Block-wide sum for NT threads (NT a multiple of 64); `red` holds NT/64 entries of LDS.
 // Contains the barriers it needs; every thread returns the total.
 template <int NT, typename T>

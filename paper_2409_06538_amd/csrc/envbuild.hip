@@ -100,7 +100,8 @@ struct EnvSmem {
   static constexpr size_t bufA = (bufA_left > bufA_right ? bufA_left : bufA_right) + MQ + N2;
   static constexpr size_t bufR = size_t(N2) * LDT;
   static constexpr size_t bufS = size_t(2) * CHI * CHI;
-  static constexpr size_t reals = bufA + bufR + bufS + 4 * N2 + 2 * NW + NT / 64 + 8;
+  static constexpr size_t stage = size_t(2) * CHI * CHI;   // next site of E_r
+  static constexpr size_t reals = bufA + bufR + bufS + stage + 4 * N2 + 2 * NW + NT / 64 + 8;
   static constexpr size_t ints = 3 * N2 + 2 * NW + 8 + 1024;
   static constexpr size_t bytes = reals * sizeof(T) + ints * sizeof(int);
 };
@@ -363,7 +364,8 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   T* bufA = reinterpret_cast<T*>(smem_raw);
   T* bufR = bufA + S::bufA;
   T* bufS = bufR + S::bufR;
-  T* diag = bufS + S::bufS;         // N2
+  T* Astage = bufS + S::bufS;       // 2 CHI^2: next site of E_r
+  T* diag = Astage + S::stage;      // N2
   T* sc = diag + N2;                // 2 N2 scalars scratch
   T* cnv = sc + 2 * N2;             // N2 (ss double buffer lives in its first 2 entries too)
   T* candv = cnv + N2;              // 2 x NW argmax candidates
@@ -647,9 +649,43 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     for (int o = tid; o < N2 * LDT; o += NT) bufR[o] = T(0);
     __syncthreads();
     if (tid == 0) { bufR[0] = T(1); bufR[CHI] = T(1); }
+    // Site c-1 of E_r is fetched while site c is processed: its loads are issued at the start
+    // of site c and parked in LDS (Astage) once the products of site c have used bufS; in the Gram
+    // form G_{c-1} is fetched at the start of site c into registers.
+    constexpr int SPT = (2 * CHI * CHI + NT - 1) / NT;
+    constexpr int GPT = GRAM ? (N2 * N2 + NT - 1) / NT : 1;
+    E apf[SPT];
+    T gpf[GPT];
+    auto fetch_site = [&](int cc) {
+#pragma unroll
+      for (int t = 0; t < SPT; ++t) {
+        const int e = tid + NT * t;
+        if ((2 * CHI * CHI) % NT == 0 || e < int(site)) apf[t] = Ain[size_t(cc) * site + e];
+      }
+    };
+    auto park_site = [&]() {
+#pragma unroll
+      for (int t = 0; t < SPT; ++t) {
+        const int e = tid + NT * t;
+        if ((2 * CHI * CHI) % NT == 0 || e < int(site)) Astage[e] = widen(apf[t]);
+      }
+    };
+    fetch_site(L - 1);
+    park_site();
     for (int c = L - 1; c >= 0; --c) {
       __syncthreads();
-      for (int e = tid; e < int(site); e += NT) bufS[e] = widen(Ain[size_t(c) * site + e]);
+      for (int e = tid; e < int(site); e += NT) bufS[e] = Astage[e];
+      if (c > 0) fetch_site(c - 1);
+      if constexpr (GRAM) {
+        if (c > 0) {
+          const T* gsrc = rs + size_t(c - 1) * N2 * N2;
+#pragma unroll
+          for (int t = 0; t < GPT; ++t) {
+            const int o = tid + NT * t;
+            if ((N2 * N2) % NT == 0 || o < N2 * N2) gpf[t] = gsrc[o];
+          }
+        }
+      }
       __syncthreads();
       T wv[2][2], wh[2][2];
 #pragma unroll
@@ -731,6 +767,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         }
       }
       __syncthreads();
+      if (c > 0) park_site();   // bufS and Astage are not read again during site c
       if (c == 0) {
         // site 0: left bond (a = 0, alpha = 0): A_0[x][0][be] = Z[(0,0)][(x,be)]
         T part = 0;
@@ -752,9 +789,13 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       int rank = N2;
       T fro2 = 0;
       if constexpr (GRAM) {
-        // H = Z^T G_{c-1} Z (row-major in bufR, symmetrised), via W = G_{c-1} Z (in Tw)
-        const T* gsrc = rs + size_t(c - 1) * N2 * N2;
-        for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = gsrc[o];
+        // H = Z^T G_{c-1} Z (row-major in bufR), via W = G_{c-1} Z (in Tw).  Rounding leaves H
+        // slightly asymmetric; the factorisation reads its columns only.
+#pragma unroll
+        for (int t = 0; t < GPT; ++t) {
+          const int o = tid + NT * t;
+          if ((N2 * N2) % NT == 0 || o < N2 * N2) bufR[(o / N2) * LDT + (o % N2)] = gpf[t];
+        }
         __syncthreads();
         auto ga = [&](int i, int k) { return bufR[i * LDT + k]; };
         auto gb = [&](int k, int col) { return Zr[k * LDZ + col]; };
@@ -767,15 +808,6 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         __syncthreads();
         if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ha, hb, hc);
         else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ha, hb, hc);
-        __syncthreads();
-        for (int o = tid; o < N2 * N2; o += NT) {
-          const int c1 = o / N2, c2 = o % N2;
-          if (c1 < c2) {
-            const T h = T(0.5) * (bufR[c1 * LDT + c2] + bufR[c2 * LDT + c1]);
-            bufR[c1 * LDT + c2] = h;
-            bufR[c2 * LDT + c1] = h;
-          }
-        }
         __syncthreads();
         // ---- pivoted Cholesky of H, stopping at the numerical rank: H[p, p] = L L^T ----
         // Left-looking: with p_j the pivot of step j (largest remaining diagonal d),
@@ -792,35 +824,39 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           if constexpr (PW == 1) return ((pk[0] >> (i & 63)) & 1ull) != 0ull;
           else return ((pk[i >> 6] >> (i & 63)) & 1ull) != 0ull;
         };
+        // Pivot choice by one unsigned maximum: key = float bits of d with the low IB bits
+        // replaced by N2-1-row (larger d first, to 2^(IB-23) relative; ties to the smaller row).
+        // The exact d of every row is published in dv[] for the pivot's square root.
+        constexpr int IB = (N2 <= 64) ? 6 : 7;
+        static_assert(N2 <= (1 << IB), "row index fits the key");
+        auto key_of = [&](T d, int row) -> uint32_t {
+          const uint32_t fb = __float_as_uint(float(fmax(d, T(0))));
+          return (fb & ~((1u << IB) - 1u)) | uint32_t(N2 - 1 - row);
+        };
+        uint32_t* candk = reinterpret_cast<uint32_t*>(candi);   // 2 x NW keys
+        T* dv = sc;                                             // N2 exact diagonals
         T dreg = bufR[ra * LDT + ra];
+        if (cpart == 0) dv[ra] = dreg;
         fro2 = block_sum<NT>(cpart == 0 ? fmax(dreg, T(0)) : T(0), red);
         {
-          T bv = cpart == 0 ? dreg : T(-1);
-          int bi = cpart == 0 ? ra : N2;
-          wave_argmax(bv, bi);
-          if ((tid & (WAVE - 1)) == 0) { candv[tid / WAVE] = bv; candi[tid / WAVE] = bi; }
+          const uint32_t k = wave_max_u32(cpart == 0 ? key_of(dreg, ra) : 0u);
+          if ((tid & (WAVE - 1)) == 0) candk[tid / WAVE] = k;
         }
         __syncthreads();
         const T tolr2 = T(Tol::rank) * T(Tol::rank) * fro2;
         for (int j = 0; j < N2; ++j) {
           const int buf = j & 1;
-          T cv[NW];
-          int ci[NW];
+          uint32_t bk = candk[buf * NW];
 #pragma unroll
-          for (int w = 0; w < NW; ++w) {
-            cv[w] = candv[buf * NW + w];
-            ci[w] = candi[buf * NW + w];
-          }
-          T best = cv[0];
-          int piv = ci[0];
-#pragma unroll
-          for (int w = 1; w < NW; ++w) {
-            const bool better = (cv[w] > best) | ((cv[w] == best) & (ci[w] < piv));
-            best = better ? cv[w] : best;
-            piv = better ? ci[w] : piv;
-          }
-          if (!(best > tolr2)) { rank = j; break; }
-          const T sq = sqrt(best), inv = T(1) / sq;
+          for (int w = 1; w < NW; ++w) bk = max(bk, candk[buf * NW + w]);
+          const int piv = N2 - 1 - int(bk & ((1u << IB) - 1u));
+          const T best = dv[piv];
+          if (bk == 0u || !(best > tolr2)) { rank = j; break; }
+          // 1/sqrt(d) from the hardware estimate refined by two Newton steps, sqrt(d) = d / sqrt(d)
+          T inv = T(__builtin_amdgcn_rsq(double(best)));
+          inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
+          inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
+          const T sq = best * inv;
           T dot = 0;
           for (int i = cpart; i < j; i += TPR) dot += Tw[i * LDT + ra] * Tw[i * LDT + piv];
           dot = group_sum<TPR>(dot);
@@ -828,17 +864,13 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           const T La = (ra == piv) ? sq : (arow ? (bufR[ra * LDT + piv] - dot) * inv : T(0));
           if (cpart == 0) Tw[j * LDT + ra] = La;
           dreg -= arow ? La * La : T(0);
+          if (cpart == 0 && arow) dv[ra] = dreg;
           if constexpr (PW == 1) pk[0] |= 1ull << (piv & 63);
           else pk[piv >> 6] |= 1ull << (piv & 63);
           if (tid == 0) perm[j] = piv;
           {
-            T bv = (cpart == 0 && arow) ? dreg : T(-1);
-            int bi = (cpart == 0 && arow) ? ra : N2;
-            wave_argmax(bv, bi);
-            if ((tid & (WAVE - 1)) == 0) {
-              candv[(buf ^ 1) * NW + tid / WAVE] = bv;
-              candi[(buf ^ 1) * NW + tid / WAVE] = bi;
-            }
+            const uint32_t k = wave_max_u32((cpart == 0 && arow) ? key_of(dreg, ra) : 0u);
+            if ((tid & (WAVE - 1)) == 0) candk[(buf ^ 1) * NW + tid / WAVE] = k;
           }
           __syncthreads();
         }

@@ -217,6 +217,15 @@ __device__ __forceinline__ E narrow(T v) {
   return Narrow<E>::from(v);
 }
 
+// Reciprocal: the hardware estimate (FP32: about 1 ulp; FP64: refined by two Newton steps to
+// a few ulp), for scale factors where a correctly rounded quotient is not needed.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * (2.0 - x * r);
+  return r * (2.0 - x * r);
+}
+
 // Exponent e with 2^(e-1) <= |x| < 2^e (0 for x == 0 or non-finite); scaling by 2^-e is exact.
 template <typename T>
 __device__ __forceinline__ int pow2_exponent(T x) {

@@ -100,7 +100,7 @@ struct EnvSmem {
   static constexpr size_t bufA = (bufA_left > bufA_right ? bufA_left : bufA_right) + MQ + N2;
   static constexpr size_t bufR = size_t(N2) * LDT;
   static constexpr size_t bufS = size_t(2) * CHI * CHI;
-  static constexpr size_t stage = size_t(2) * CHI * CHI;   // next site of E_r
+  static constexpr size_t stage = size_t(2) * CHI * (CHI + 2);   // next site of E_r
   static constexpr size_t reals = bufA + bufR + bufS + stage + 4 * N2 + 2 * NW + NT / 64 + 8;
   static constexpr size_t ints = 3 * N2 + 2 * NW + 8 + 1024;
   static constexpr size_t bytes = reals * sizeof(T) + ints * sizeof(int);
@@ -285,10 +285,10 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
 }
 
 // Orthonormalise rows 0..k-1 of V (CHI x N2, row-major, ld N2) in place by modified Gram-Schmidt
-// applied twice, one barrier per row.  A group of TPP threads owns one row.  A row whose residual
+// applied PASSES times, one barrier per row.  A group of TPP threads owns one row.  A row whose residual
 // norm^2 falls below eta (the rows start with unit norm) lies in the span of the earlier rows to
 // rounding and is set to zero; the span of the others is unchanged.
-template <typename T, int CHI, int NT>
+template <typename T, int CHI, int NT, int PASSES>
 __device__ void mgs2_rows(T* V, int k, T eta) {
   constexpr int N2 = 2 * CHI, TPP = env_tpp(CHI), EPR = (N2 + TPP - 1) / TPP;
   const int grp = threadIdx.x / TPP, l = threadIdx.x % TPP;
@@ -300,7 +300,7 @@ __device__ void mgs2_rows(T* V, int k, T eta) {
     const int j = l + TPP * e;
     vb[e] = (mine && j < N2) ? V[grp * N2 + j] : T(0);
   }
-  for (int pass = 0; pass < 2; ++pass) {
+  for (int pass = 0; pass < PASSES; ++pass) {
     for (int a = 0; a < k; ++a) {
       T va[EPR];
       T n2 = 0, d = 0;
@@ -315,7 +315,7 @@ __device__ void mgs2_rows(T* V, int k, T eta) {
       n2 = group_sum<TPP>(n2);
       d = group_sum<TPP>(d);
       if (mine && grp > a && n2 > eta) {
-        const T f = d / n2;
+        const T f = d * fast_rcp(n2);
 #pragma unroll
         for (int e = 0; e < EPR; ++e) {
           const int j = l + TPP * e;
@@ -416,14 +416,51 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       static_assert(size_t(N2) * LDT + size_t(2) * CHI * LDC <= S::bufA, "left-sweep buffers");
       T* gX = bufA;                        // G_{c-1} (N2 x LDT), then Q
       T* gY = bufR;                        // P, then G_c
-      T* As2 = bufA + size_t(N2) * LDT;    // A_c[b][al][ap], ld LDC
+      T* As2 = bufA + size_t(N2) * LDT;    // A_c[b][al][ap], ld LDC (alternates with Astage)
+      T* Anx = Astage;                     // site c+1 while site c is processed
       constexpr int tmb = CHI / TL;
+      // Site c+1 of E_r is fetched while site c is processed and parked in As2 at its end.  The
+      // rescale of G_c (per-wave maxima in red[]) is applied by the next site's P pass, which
+      // also stores the rescaled G_c for the second sweep.
+      constexpr int SPT = (2 * CHI * CHI + NT - 1) / NT;
+      E lpf[SPT];
+      auto lfetch = [&](int cc) {
+#pragma unroll
+        for (int t = 0; t < SPT; ++t) {
+          const int e = tid + NT * t;
+          if ((2 * CHI * CHI) % NT == 0 || e < int(site)) lpf[t] = Ain[size_t(cc) * site + e];
+        }
+      };
+      auto lpark = [&]() {
+#pragma unroll
+        for (int t = 0; t < SPT; ++t) {
+          const int e = tid + NT * t;
+          if ((2 * CHI * CHI) % NT == 0 || e < int(site)) {
+            const int b = e / (CHI * CHI), al = (e / CHI) % CHI, ap = e % CHI;
+            Anx[(b * CHI + al) * LDC + ap] = widen(lpf[t]);
+          }
+        }
+      };
+      auto take_exponent = [&](int cc) {   // exponent of G_cc from the per-wave maxima
+        T m = red[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) m = fmax(m, red[w]);
+        const int e = (pow2_exponent(m) + 1) / 2;
+        log2acc += e;
+        if (tid == 0) rexp[cc] = e;
+        return e;
+      };
+      __syncthreads();
+      lfetch(0);
+      lpark();
+      {
+        T* tmp = As2;
+        As2 = Anx;
+        Anx = tmp;
+      }
       for (int c = 0; c < L - 1; ++c) {
         __syncthreads();
-        for (int e = tid; e < int(site); e += NT) {
-          const int b = e / (CHI * CHI), al = (e / CHI) % CHI, ap = e % CHI;
-          As2[(b * CHI + al) * LDC + ap] = widen(Ain[size_t(c) * site + e]);
-        }
+        if (c + 1 < L - 1) lfetch(c + 1);
         T kx[2][2];
 #pragma unroll
         for (int b = 0; b < 2; ++b)
@@ -431,15 +468,19 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           for (int b2 = 0; b2 < 2; ++b2)
             kx[b][b2] = bond_weight<T>(jv, c, 0, b, ep, em) * bond_weight<T>(jv, c, 0, b2, ep, em) +
                         bond_weight<T>(jv, c, 1, b, ep, em) * bond_weight<T>(jv, c, 1, b2, ep, em);
-        __syncthreads();
+        T mx = 0;
         if (c == 0) {
           for (int o = tid; o < N2 * N2; o += NT) {
             const int i = o / N2, k = o % N2;
             const int b = i / CHI, ap = i % CHI, b2 = k / CHI, ap2 = k % CHI;
             const T f = b ? (b2 ? kx[1][1] : kx[1][0]) : (b2 ? kx[0][1] : kx[0][0]);
-            gY[i * LDT + k] = f * As2[(b * CHI) * LDC + ap] * As2[(b2 * CHI) * LDC + ap2];
+            const T g = f * As2[(b * CHI) * LDC + ap] * As2[(b2 * CHI) * LDC + ap2];
+            gY[i * LDT + k] = g;
+            mx = fmax(mx, fabs(g));
           }
         } else {
+          const T gs = T(ldexp(T(1), -2 * take_exponent(c - 1)));
+          T* gdst = rs + size_t(c - 1) * N2 * N2;
           T wh2[2][2];
 #pragma unroll
           for (int a = 0; a < 2; ++a)
@@ -449,15 +490,21 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
             const int blk = o / (CHI * CHI), al = (o / CHI) % CHI, al2 = o % CHI;
             const int b = blk >> 1, b2 = blk & 1;
             // (selects, not indexing with the runtime b: that would put the table in scratch)
-            const T w0b = b ? wh2[0][1] : wh2[0][0], w1b = b ? wh2[1][1] : wh2[1][0];
+            const T w0b = gs * (b ? wh2[0][1] : wh2[0][0]), w1b = gs * (b ? wh2[1][1] : wh2[1][0]);
             const T w0c = b2 ? wh2[0][1] : wh2[0][0], w1c = b2 ? wh2[1][1] : wh2[1][0];
-            T p = w0b * w0c * gX[al * LDT + al2];
-            p += w0b * w1c * gX[al * LDT + CHI + al2];
-            p += w1b * w0c * gX[(CHI + al) * LDT + al2];
-            p += w1b * w1c * gX[(CHI + al) * LDT + CHI + al2];
-            gY[(blk * CHI + al) * LDC + al2] = p;
+            const T g00 = gX[al * LDT + al2], g01 = gX[al * LDT + CHI + al2];
+            const T g10 = gX[(CHI + al) * LDT + al2], g11 = gX[(CHI + al) * LDT + CHI + al2];
+            gY[(blk * CHI + al) * LDC + al2] =
+                w0b * (w0c * g00 + w1c * g01) + w1b * (w0c * g10 + w1c * g11);
+            if (blk == 0) {   // the rescaled G_{c-1}, once per entry, for the second sweep
+              gdst[al * N2 + al2] = gs * g00;
+              gdst[al * N2 + CHI + al2] = gs * g01;
+              gdst[(CHI + al) * N2 + al2] = gs * g10;
+              gdst[(CHI + al) * N2 + CHI + al2] = gs * g11;
+            }
           }
           __syncthreads();
+          if (c + 1 < L - 1) lpark();   // into the other buffer: As2 is read until the end of site c
           if constexpr (MF64) {
             // Q_bb' = P_bb' A_c[b'] (into gX), then G_c = kx A_c[b]^T Q_bb' (into gY)
 #pragma unroll
@@ -476,7 +523,11 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
               mfma_gemm_f64<CHI, CHI, CHI, NT>(
                   [&](int i, int k) { return As2[(b * CHI + k) * LDC + i]; },
                   [&](int k, int j) { return gX[(blk * CHI + k) * LDC + j]; },
-                  [&](int i, int j, T v) { gY[(b * CHI + i) * LDT + b2 * CHI + j] = f * v; });
+                  [&](int i, int j, T v) {
+                    const T g = f * v;
+                    gY[(b * CHI + i) * LDT + b2 * CHI + j] = g;
+                    mx = fmax(mx, fabs(g));
+                  });
             }
           } else {
             // Q_bb' = P_bb' A_c[b'] (into gX)
@@ -532,27 +583,30 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
               for (int u = 0; u < TL; ++u)
   #pragma unroll
                 for (int v = 0; v < TL; ++v)
-                  gY[(b * CHI + i0 + u) * LDT + b2 * CHI + j0 + v] = f * acc[u][v];
+                {
+                  const T g = f * acc[u][v];
+                  gY[(b * CHI + i0 + u) * LDT + b2 * CHI + j0 + v] = g;
+                  mx = fmax(mx, fabs(g));
+                }
             }
           }
           }
-        __syncthreads();
-        T mx = 0;
-        for (int o = tid; o < N2 * N2; o += NT) mx = fmax(mx, fabs(gY[(o / N2) * LDT + o % N2]));
-        mx = block_max<NT>(mx, red);
-        const int e = (pow2_exponent(mx) + 1) / 2;
-        log2acc += e;
-        if (tid == 0) rexp[c] = e;
-        T* gdst = rs + size_t(c) * N2 * N2;
-        for (int o = tid; o < N2 * N2; o += NT) {
-          const int i = o / N2, k = o % N2;
-          const T v = T(ldexp(gY[i * LDT + k], -2 * e));
-          gY[i * LDT + k] = v;
-          gdst[o] = v;
-        }
+        if (c == 0 && L > 2) lpark();
+        mx = wave_max(mx);
+        if ((tid & (WAVE - 1)) == 0) red[tid / WAVE] = mx;
         T* tmp = gX;
         gX = gY;
         gY = tmp;
+        tmp = As2;
+        As2 = Anx;
+        Anx = tmp;
+      }
+      // the last Gram matrix of the row: rescale and store
+      __syncthreads();
+      {
+        const T gs = T(ldexp(T(1), -2 * take_exponent(L - 2)));
+        T* gdst = rs + size_t(L - 2) * N2 * N2;
+        for (int o = tid; o < N2 * N2; o += NT) gdst[o] = gs * gX[(o / N2) * LDT + o % N2];
       }
     } else // ---------------- left to right: R factors ----------------
     {
@@ -692,11 +746,21 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int b = 0; b < 2; ++b) wv[x][b] = bond_weight<T>(jv, c, x, b, ep, em);
+      // 2^-e rescale of Xt_{c+1} (from the maxima its product left in red[]), folded into wh
+      T xsc = T(1);
+      if (c < L - 1) {
+        T m = red[0];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) m = fmax(m, red[w]);
+        const int xe = pow2_exponent(m);
+        log2acc += xe;
+        xsc = T(ldexp(T(1), -xe));
+      }
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
-          wh[a][b] = (c > 0) ? bond_weight<T>(jh, c - 1, a, b, ep, em) : (a == 0 ? T(1) : T(0));
+          wh[a][b] = xsc * ((c > 0) ? bond_weight<T>(jh, c - 1, a, b, ep, em) : (a == 0 ? T(1) : T(0)));
       // Z[(a,al)][(x,be)] = sum_b wh(a,b) wv(x,b) (A_c[b] Xt_b)[al][be]
       if constexpr (MF64) {
         // both products of an output tile on 16x16x4 FP64 matrix-core tiles, combined in registers
@@ -1116,7 +1180,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       }
       // small kept rows are orthogonal to the large ones only up to rot ||T|| / sigma: make the
       // kept rows orthonormal (span unchanged)
-      mgs2_rows<T, CHI, NT>(bufS, kept, T(Tol::eta));
+      // One pass suffices in the Gram form: the rows come from a pivoted Cholesky factor whose
+      // conditioning is bounded by the FP32 rank tolerance, so FP64 Gram-Schmidt leaves them
+      // orthonormal to ~1e-10; FP64 environments need the second pass.
+      mgs2_rows<T, CHI, NT, GRAM ? 1 : 2>(bufS, kept, T(Tol::eta));
       E* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
       for (int o = tid; o < int(site); o += NT) {
         const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
@@ -1136,13 +1203,9 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         if constexpr (MF64) mfma_gemm_f64<N2, CHI, N2, NT>(xa, xb, xc);
         else gemm_tiles<TL, TL, N2, NT, T>(N2, CHI, xa, xb, xc);
       }
-      mx = block_max<NT>(mx, red);
-      const int e = pow2_exponent(mx);
-      log2acc += e;
-      for (int o = tid; o < N2 * CHI; o += NT) {
-        const int j = o % N2, al = o / N2;
-        bufR[al * LDT + j] = T(ldexp(bufR[al * LDT + j], -e));
-      }
+      // the power-of-two rescale of Xt_c is applied to Z_{c-1} (per-wave maxima in red[])
+      mx = wave_max(mx);
+      if ((tid & (WAVE - 1)) == 0) red[tid / WAVE] = mx;
     }
     __syncthreads();
   }

@@ -23,26 +23,35 @@ sys.path.insert(0, ROOT)
 METRIC = "accepted spin-updates/s + acceptance rate, BF16/FP32 batched vs FP64 plain"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
 
 
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE counters, each
 # scaled by the same counter on a plain 1 GiB copy (profiles/rbim64_fp32_hbm_traffic.md).  Valid
 # only for the kernel sources they were taken on: reported as null once those change.
 COUNTED_TRAFFIC = {
-    ("rbim64", "fp32"): {
-        "fetch_kib": 3846582.9375, "fetch_factor": 1048576.0 / 524306.1875,
-        "write_kib": 6160537.5, "write_factor": 1.0,
+    ("rbim64", "fp32", "env_build"): {
+        "fetch_kib": 5951877.25, "fetch_factor": 1048576.0 / 524306.8125,
+        "write_kib": 10225012.625, "write_factor": 1.0,
         "sources_sha256": {
-            "envbuild.hip": "c2342458c6e82fdc783a1e9875d1be705b46e65822f35fd345f834eeabfa3c34",
-            "common.hpp": "2efa25530392e8807d613e9aabe42d3afcfa73e766988131a0dca016b25208c3",
+            "envbuild.hip": "11070b5cd462942eb0adb494e137a1e47fa4192be434f8fcf6210d6b3c9ed565",
+            "common.hpp": "d3d203ac7e1f0d0435cb5dfe9b83b18a8e2489c363933aa5b163e724c48f17b5",
+        },
+    },
+    ("rbim64", "fp32", "propose"): {
+        "fetch_kib": 63815979.5, "fetch_factor": 1048576.0 / 524306.8125,
+        "write_kib": 67237614.0, "write_factor": 1.0,
+        "sources_sha256": {
+            "sampler.hip": "11bc15fd7edc0a92f52a2f818daccafd01f76dd57beea330dede4ab20da297a3",
+            "common.hpp": "d3d203ac7e1f0d0435cb5dfe9b83b18a8e2489c363933aa5b163e724c48f17b5",
         },
     },
 }
 
 
-def counted_traffic(workload, precision):
+def counted_traffic(workload, precision, kernel):
     import hashlib
-    rec = COUNTED_TRAFFIC.get((workload, precision))
+    rec = COUNTED_TRAFFIC.get((workload, precision, kernel))
     if rec is None:
         return None
     csrc = os.path.join(ROOT, "paper_2409_06538_amd", "csrc")
@@ -120,9 +129,23 @@ def run_gpu(args):
     achieved = flops / (build_ms * 1e-3) / 1e12
     res["roofline"] = {"kernel": "env_build_kernel", "bound": "alu", "achieved": achieved,
                        "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                       "traffic": counted_traffic(args.workload, args.precision),
+                       "traffic": counted_traffic(args.workload, args.precision, "env_build"),
                        "launch_ms": build_ms,
                        "algorithmic_flops_per_launch": flops}
+    # proposals: HBM-bound; algorithmic bytes = the per-row V store written and read back, plus
+    # each workgroup of 64 proposals streaming its realization's environments once per sweep
+    elem = 8 if args.precision == "fp64" else 4
+    esize = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
+    kpad = (K + 63) // 64 * 64
+    vbytes = 2.0 * L * L * 2 * chi * kpad * n * elem
+    ebytes = 2.0 * L * L * 2 * chi * chi * esize * (kpad // 64) * n
+    pbytes = vbytes + ebytes
+    pach = pbytes / (prop_ms * 1e-3) / 1e9
+    res["roofline_propose"] = {"kernel": "propose_mfma_kernel" if chi % 16 == 0 else "propose_kernel",
+                               "bound": "hbm", "achieved": pach, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": pach / HBM_PEAK_GBS,
+                               "traffic": counted_traffic(args.workload, args.precision, "propose"),
+                               "launch_ms": prop_ms, "algorithmic_bytes_per_launch": pbytes}
     return res
 
 
@@ -245,6 +268,7 @@ def main():
         "propose_ms": res["propose_ms"],
         "fp64_plain": plain,
         "roofline": res["roofline"],
+        "roofline_propose": res["roofline_propose"],
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -19,8 +19,11 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 // bytes of one stored environment element
 inline size_t elem_bytes(tnmc_precision p) { return p == TNMC_FP64 ? 8 : (p == TNMC_FP32 ? 4 : 2); }
 
-bool chi_ok(int32_t chi) { return chi == 2 || chi == 4 || chi == 8 || chi == 16 || chi == 32; }
 bool prec_ok(tnmc_precision p) { return p == TNMC_FP64 || p == TNMC_FP32 || p == TNMC_BF16; }
+// chi = 48 exists for FP32 and BF16 environments only
+bool chi_ok(int32_t chi, tnmc_precision p) {
+  return chi == 2 || chi == 4 || chi == 8 || chi == 16 || chi == 32 || (chi == 48 && p != TNMC_FP64);
+}
 
 // Basic per-instance checks; returns Lmax or -1.
 int check_instances(const tnmc_instance* inst, int32_t n, bool need_env, bool need_J) {
@@ -86,16 +89,16 @@ inline tnmc_status hip_status(hipError_t e) { return e == hipSuccess ? TNMC_OK :
 
 extern "C" {
 
-int tnmc_chi_supported(int32_t chi, tnmc_precision prec) { return chi_ok(chi) && prec_ok(prec); }
+int tnmc_chi_supported(int32_t chi, tnmc_precision prec) { return prec_ok(prec) && chi_ok(chi, prec); }
 
 size_t tnmc_env_bytes(int32_t L, int32_t chi, tnmc_precision prec) {
-  if (L < 2 || L > 1024 || !chi_ok(chi) || !prec_ok(prec)) return 0;
+  if (L < 2 || L > 1024 || !prec_ok(prec) || !chi_ok(chi, prec)) return 0;
   return size_t(L) * L * 2 * chi * chi * elem_bytes(prec);
 }
 
 size_t tnmc_workspace_bytes(const tnmc_instance* inst, int32_t n, int32_t chi, int32_t K,
                             tnmc_precision prec) {
-  if (check_instances(inst, n, false, false) < 0 || !chi_ok(chi) || !prec_ok(prec) || K < 1)
+  if (check_instances(inst, n, false, false) < 0 || !prec_ok(prec) || !chi_ok(chi, prec) || K < 1)
     return 0;
   const size_t r = std::max({build_region(inst, n, chi, prec), propose_region(inst, n, chi, K, prec),
                              accept_region(n, K), align_up(sizeof(uint64_t) * n)});
@@ -123,7 +126,7 @@ tnmc_status tnmc_make_couplings(const tnmc_instance* inst, int32_t n, const uint
 tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,
                            void* d_workspace, size_t workspace_bytes, double* d_lnZ,
                            hipStream_t stream) {
-  if (check_instances(inst, n, true, true) < 0 || !chi_ok(chi) || !prec_ok(prec) ||
+  if (check_instances(inst, n, true, true) < 0 || !prec_ok(prec) || !chi_ok(chi, prec) ||
       d_workspace == nullptr)
     return TNMC_EINVAL;
   if (workspace_bytes < desc_bytes(n) + build_region(inst, n, chi, prec)) return TNMC_ENOMEM;
@@ -139,7 +142,7 @@ static tnmc_status propose_common(const tnmc_instance* inst, int32_t n, int32_t 
                                   double* d_logq, int32_t* d_E, uint32_t* d_fallbacks,
                                   hipStream_t stream) {
   const int Lmax = check_instances(inst, n, true, true);
-  if (Lmax < 0 || !chi_ok(chi) || !prec_ok(prec) || K < 1 || d_workspace == nullptr ||
+  if (Lmax < 0 || !prec_ok(prec) || !chi_ok(chi, prec) || K < 1 || d_workspace == nullptr ||
       d_logq == nullptr)
     return TNMC_EINVAL;
   if (d_teacher == nullptr && (d_spins == nullptr || d_E == nullptr)) return TNMC_EINVAL;

@@ -59,8 +59,12 @@ struct TolOf<bf16_t> {
 constexpr int MAX_SWEEPS = 40;
 // 32 threads per unit of CHI, at most 512 (8 waves, two per SIMD, so that LDS and barrier latency
 // of one wave overlaps with the other's work while each keeps 256 registers).
+// (the largest multiple of both 64 and 2 CHI not above 512 when 32 CHI exceeds 512: 384 at CHI = 48)
+__host__ __device__ constexpr int env_gcd(int a, int b) { return b == 0 ? a : env_gcd(b, a % b); }
 __host__ __device__ constexpr int env_threads(int chi) {
-  return (32 * chi < 64) ? 64 : (32 * chi > 512 ? 512 : 32 * chi);
+  return (32 * chi < 64) ? 64
+         : (32 * chi <= 512) ? 32 * chi
+         : 512 / (64 * 2 * chi / env_gcd(64, 2 * chi)) * (64 * 2 * chi / env_gcd(64, 2 * chi));
 }
 // threads per column in the Householder updates (a power of two; NT = TPC * 2 CHI)
 __host__ __device__ constexpr int env_tpc(int chi) { return env_threads(chi) / (2 * chi); }
@@ -264,18 +268,24 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
     const T* vj = vbuf + (j & 1) * VLD;
     const T tau = taub[j & 1];
     if (g > j) {
-      T vv[RPT];
+      // long slices re-read the reflector for the update instead of holding it in registers
+      constexpr bool HOLD = RPT <= 32;
+      T vv[HOLD ? RPT : 1];
       T wp[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int t = 0; t < RPT; ++t) {
-        vv[t] = vj[row0 + t];
-        wp[t & 3] += vv[t] * m[t];
+        const T x = vj[row0 + t];
+        if constexpr (HOLD) vv[t] = x;
+        wp[t & 3] += x * m[t];
       }
       T w = (wp[0] + wp[1]) + (wp[2] + wp[3]);
       w = group_sum<TPC>(w);
       const T tw = tau * w;
 #pragma unroll
-      for (int t = 0; t < RPT; ++t) m[t] -= tw * vv[t];
+      for (int t = 0; t < RPT; ++t) {
+        if constexpr (HOLD) m[t] -= tw * vv[t];
+        else m[t] -= tw * vj[row0 + t];
+      }
       if (g == j + 1)
         make_reflector<T, TPC, RPT>(m, j + 1, row0, MQ, vbuf + ((j + 1) & 1) * VLD,
                                     taub + ((j + 1) & 1), diag, part);
@@ -377,6 +387,23 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   int* candi = unpk + N2;                         // 2 x NW
   int* imisc = candi + 2 * NW;                    // 8
   int* rexp = imisc + 8;                          // exponents of the carried R_c (L <= 1024)
+  // perm[rank ..] = the columns never picked as pivots (unpk[col] = 1), ascending; wave w ranks
+  // columns 64 w .. 64 w + 63 by ballot, offset by the counts of the waves before it.
+  auto rank_unpicked = [&](int rk) {
+    constexpr int NWC = (2 * CHI + WAVE - 1) / WAVE;
+    static_assert(NWC <= 8, "column-count slots");
+    const int t = threadIdx.x, wi = t / WAVE, li = t % WAVE;
+    const bool un = t < 2 * CHI && unpk[t];
+    const unsigned long long mask = __ballot(un);
+    if (li == 0 && wi < NWC) imisc[wi] = __popcll(mask);
+    __syncthreads();
+    if (un) {
+      int base = rk;
+      for (int w = 0; w < wi; ++w) base += imisc[w];
+      perm[base + __popcll(mask & ((1ull << li) - 1ull))] = t;
+    }
+    __syncthreads();
+  };
 
   const int tid = threadIdx.x;
   const DevReal R = reals[blockIdx.x];
@@ -941,15 +968,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         // columns never picked follow the pivots in ascending order
         if (tid < N2) unpk[tid] = picked(tid) ? 0 : 1;
         __syncthreads();
-        {
-          static_assert(2 * CHI <= WAVE, "one wave ranks the unused columns");
-          if (tid < WAVE) {
-            const bool un = tid < N2 && unpk[tid];
-            const unsigned long long mask = __ballot(un);
-            if (un) perm[rank + __popcll(mask & ((1ull << tid) - 1ull))] = tid;
-          }
-        }
-        __syncthreads();
+        rank_unpicked(rank);
         // J = rows 0..rank-1 of L^T in pivoted column order (row-major in bufR, ld LDT)
         const int nr = rank + (rank & 1);
         for (int o = tid; o < nr * N2; o += NT) {
@@ -1028,15 +1047,14 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           T wp[4] = {T(0), T(0), T(0), T(0)};
           // loads first and unconditional (a select on the loaded value would let the compiler
           // move each load under its own branch and wait for it there)
-          T u[RPT2];
   #pragma unroll
-          for (int t = 0; t < RPT2; ++t) u[t] = pc[(N2 % TPC == 0 || row0 + t < N2) ? row0 + t : 0];
+          for (int t = 0; t < RPT2; ++t) v[t] = pc[(N2 % TPC == 0 || row0 + t < N2) ? row0 + t : 0];
   #pragma unroll
           for (int t = 0; t < RPT2; ++t) {
             const int rho = row0 + t;
             const T sg = (rho > j && rho < N2) ? scal : T(0);
             const T one = (rho == j) ? T(1) : T(0);
-            v[t] = u[t] * sg + one;
+            v[t] = v[t] * sg + one;
             wp[t & 3] += v[t] * mc[t];
           }
           const T w = group_sum<TPC>((wp[0] + wp[1]) + (wp[2] + wp[3]));
@@ -1066,15 +1084,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         // columns never picked follow the pivots in ascending order
         if (owner && part == 0) unpk[g] = active ? 1 : 0;
         __syncthreads();
-        {
-          static_assert(2 * CHI <= WAVE, "one wave ranks the unused columns");
-          if (tid < WAVE) {
-            const bool un = tid < N2 && unpk[tid];
-            const unsigned long long mask = __ballot(un);
-            if (un) perm[rank + __popcll(mask & ((1ull << tid) - 1ull))] = tid;
-          }
-        }
-        __syncthreads();
+        rank_unpicked(rank);
         // J = rows 0..rank-1 of R in pivoted column order (row-major in bufR, ld LDT)
         const int nr = rank + (rank & 1);
         for (int o = tid; o < nr * N2; o += NT) {
@@ -1269,13 +1279,20 @@ hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n
   TNMC_ENV_CASE(TY, EY, 2, G) TNMC_ENV_CASE(TY, EY, 4, G) TNMC_ENV_CASE(TY, EY, 8, G) \
   TNMC_ENV_CASE(TY, EY, 16, G) TNMC_ENV_CASE(TY, EY, 32, G)
   // FP64 environments: Householder / pivoted-QR form in FP64.  FP32 and BF16 environments: Gram
-  // form in FP64 arithmetic, results rounded to the storage type.
+  // form in FP64 arithmetic, results rounded to the storage type; at chi = 48 (where FP64 Gram
+  // matrices do not fit the LDS) the QR form in FP32.
   if (prec == TNMC_FP64) {
     switch (chi) { TNMC_ENV_CHIS(double, double, false) }
   } else if (prec == TNMC_FP32) {
-    switch (chi) { TNMC_ENV_CHIS(double, float, true) }
+    switch (chi) {
+      TNMC_ENV_CHIS(double, float, true)
+      TNMC_ENV_CASE(float, float, 48, false)
+    }
   } else if (prec == TNMC_BF16) {
-    switch (chi) { TNMC_ENV_CHIS(double, bf16_t, true) }
+    switch (chi) {
+      TNMC_ENV_CHIS(double, bf16_t, true)
+      TNMC_ENV_CASE(float, bf16_t, 48, false)
+    }
   }
 #undef TNMC_ENV_CHIS
 #undef TNMC_ENV_CASE

@@ -596,9 +596,9 @@ hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, 
   if (prec == TNMC_FP64) {
     switch (chi) { TNMC_PROP_CHIS(double, double) }
   } else if (prec == TNMC_FP32) {
-    switch (chi) { TNMC_PROP_CHIS(float, float) }
+    switch (chi) { TNMC_PROP_CHIS(float, float) TNMC_PROP_CASE(float, float, 48) }
   } else if (prec == TNMC_BF16) {
-    switch (chi) { TNMC_PROP_CHIS(float, bf16_t) }
+    switch (chi) { TNMC_PROP_CHIS(float, bf16_t) TNMC_PROP_CASE(float, bf16_t, 48) }
   }
 #undef TNMC_PROP_CHIS
 #undef TNMC_PROP_CASE

@@ -103,7 +103,12 @@ struct EnvSmem {
   // + MQ + N2: rows read past the end of the last column (values masked) stay in bounds
   static constexpr size_t bufA = (bufA_left > bufA_right ? bufA_left : bufA_right) + MQ + N2;
   static constexpr size_t bufR = size_t(N2) * LDT;
-  static constexpr size_t bufS = size_t(2) * CHI * CHI;
+  // site of E_r (row stride LDA_S) or V (row stride LDV) in bufS: the odd strides keep the rows
+  // that one matrix-core operand load touches in distinct LDS banks
+  static constexpr int LDA_S = CHI + 1;
+  static constexpr int LDV = N2 + 1;
+  static constexpr size_t bufS = (size_t(2) * CHI * LDA_S > size_t(CHI) * LDV)
+                                     ? size_t(2) * CHI * LDA_S : size_t(CHI) * LDV;
   static constexpr size_t stage = size_t(2) * CHI * (CHI + 2);   // next site of E_r
   static constexpr size_t reals = bufA + bufR + bufS + stage + 4 * N2 + 2 * NW + NT / 64 + 8;
   static constexpr size_t ints = 3 * N2 + 2 * NW + 8 + 1024;
@@ -294,11 +299,11 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
   }
 }
 
-// Orthonormalise rows 0..k-1 of V (CHI x N2, row-major, ld N2) in place by modified Gram-Schmidt
+// Orthonormalise rows 0..k-1 of V (CHI x N2, row-major, ld LDVR) in place by modified Gram-Schmidt
 // applied PASSES times, one barrier per row.  A group of TPP threads owns one row.  A row whose residual
 // norm^2 falls below eta (the rows start with unit norm) lies in the span of the earlier rows to
 // rounding and is set to zero; the span of the others is unchanged.
-template <typename T, int CHI, int NT, int PASSES>
+template <typename T, int CHI, int NT, int PASSES, int LDVR>
 __device__ void mgs2_rows(T* V, int k, T eta) {
   constexpr int N2 = 2 * CHI, TPP = env_tpp(CHI), EPR = (N2 + TPP - 1) / TPP;
   const int grp = threadIdx.x / TPP, l = threadIdx.x % TPP;
@@ -308,7 +313,7 @@ __device__ void mgs2_rows(T* V, int k, T eta) {
 #pragma unroll
   for (int e = 0; e < EPR; ++e) {
     const int j = l + TPP * e;
-    vb[e] = (mine && j < N2) ? V[grp * N2 + j] : T(0);
+    vb[e] = (mine && j < N2) ? V[grp * LDVR + j] : T(0);
   }
   for (int pass = 0; pass < PASSES; ++pass) {
     for (int a = 0; a < k; ++a) {
@@ -317,7 +322,7 @@ __device__ void mgs2_rows(T* V, int k, T eta) {
 #pragma unroll
       for (int e = 0; e < EPR; ++e) {
         const int j = l + TPP * e;
-        const T ra = V[a * N2 + (j < N2 ? j : 0)];
+        const T ra = V[a * LDVR + (j < N2 ? j : 0)];
         va[e] = (mine && grp >= a && j < N2) ? (grp == a ? vb[e] : ra) : T(0);
         n2 += va[e] * va[e];
         d += va[e] * vb[e];
@@ -330,7 +335,7 @@ __device__ void mgs2_rows(T* V, int k, T eta) {
         for (int e = 0; e < EPR; ++e) {
           const int j = l + TPP * e;
           vb[e] -= f * va[e];
-          if (j < N2) V[grp * N2 + j] = vb[e];
+          if (j < N2) V[grp * LDVR + j] = vb[e];
         }
       }
       if (mine && grp == a && !(n2 > eta)) {
@@ -348,7 +353,7 @@ __device__ void mgs2_rows(T* V, int k, T eta) {
     for (int e = 0; e < EPR; ++e) {
       const int j = l + TPP * e;
       vb[e] *= f;
-      if (mine && j < N2) V[grp * N2 + j] = vb[e];
+      if (mine && j < N2) V[grp * LDVR + j] = vb[e];
     }
     __syncthreads();
   }
@@ -366,6 +371,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   constexpr bool MF64 = std::is_same<T, double>::value && CHI % 16 == 0;
   using S = EnvSmem<T, CHI>;
   constexpr int N2 = S::N2, MQ = S::MQ, LDT = S::LDT, LDZ = S::LDZ;
+  constexpr int LDA_S = S::LDA_S, LDV = S::LDV;
   constexpr int NT = S::NT, NW = S::NW, TL = S::TILE;
   constexpr int TPP = env_tpp(CHI);   // threads per Jacobi row pair
   constexpr int TPC = env_tpc(CHI);   // threads per column in the QR updates
@@ -755,7 +761,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     park_site();
     for (int c = L - 1; c >= 0; --c) {
       __syncthreads();
-      for (int e = tid; e < int(site); e += NT) bufS[e] = Astage[e];
+      for (int e = tid; e < int(site); e += NT) bufS[(e / CHI) * LDA_S + e % CHI] = Astage[e];
       if (c > 0) fetch_site(c - 1);
       if constexpr (GRAM) {
         if (c > 0) {
@@ -800,7 +806,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
 #pragma unroll
           for (int k0 = 0; k0 < CHI; k0 += 4) {
             const int k = k0 + qg;
-            const double a0 = bufS[(r0 + i16) * CHI + k], a1 = bufS[(CHI + r0 + i16) * CHI + k];
+            const double a0 = bufS[(r0 + i16) * LDA_S + k], a1 = bufS[(CHI + r0 + i16) * LDA_S + k];
             const double x0 = bufR[(c0 + i16) * LDT + k], x1 = bufR[(c0 + i16) * LDT + CHI + k];
             p0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, p0, 0, 0, 0);
             p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, p1, 0, 0, 0);
@@ -831,8 +837,8 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
             T a0[TL], a1[TL], x0[TL], x1[TL];
 #pragma unroll
             for (int u = 0; u < TL; ++u) {
-              a0[u] = bufS[(al0 + u) * CHI + ap];
-              a1[u] = bufS[(CHI + al0 + u) * CHI + ap];
+              a0[u] = bufS[(al0 + u) * LDA_S + ap];
+              a1[u] = bufS[(CHI + al0 + u) * LDA_S + ap];
               x0[u] = bufR[(be0 + u) * LDT + ap];
               x1[u] = bufR[(be0 + u) * LDT + CHI + ap];
             }
@@ -1186,25 +1192,25 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           const T s2 = sc[row];
           if (s2 > T(0)) val = bufR[row * LDT + kk] / sqrt(s2);
         }
-        bufS[al * N2 + perm[kk]] = val;
+        bufS[al * LDV + perm[kk]] = val;
       }
       // small kept rows are orthogonal to the large ones only up to rot ||T|| / sigma: make the
       // kept rows orthonormal (span unchanged)
       // One pass suffices in the Gram form: the rows come from a pivoted Cholesky factor whose
       // conditioning is bounded by the FP32 rank tolerance, so FP64 Gram-Schmidt leaves them
       // orthonormal to ~1e-10; FP64 environments need the second pass.
-      mgs2_rows<T, CHI, NT, GRAM ? 1 : 2>(bufS, kept, T(Tol::eta));
+      mgs2_rows<T, CHI, NT, GRAM ? 1 : 2, LDV>(bufS, kept, T(Tol::eta));
       E* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
       for (int o = tid; o < int(site); o += NT) {
         const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
-        bout[o] = narrow<E>(bufS[al * N2 + x * CHI + be]);
+        bout[o] = narrow<E>(bufS[al * LDV + x * CHI + be]);
       }
       // Xt_c = 2^-e_{c-1} Z V^T (N2 x CHI, column-major in bufR), then a power-of-two rescale
       const int ec = rexp[c - 1];
       T mx = 0;
       {
         auto xa = [&](int j, int col) { return Zr[j * LDZ + col]; };
-        auto xb = [&](int col, int al) { return bufS[al * N2 + col]; };
+        auto xb = [&](int col, int al) { return bufS[al * LDV + col]; };
         auto xc = [&](int j, int al, T val) {
           const T d = T(ldexp(val, -ec));
           bufR[al * LDT + j] = d;

@@ -153,6 +153,34 @@ __device__ __forceinline__ void mfma_gemm_f64(FA fa, FB fb, FC fc) {
   }
 }
 
+// BATCH independent products C_b = A_b B_b of the shapes above in one tile loop, so that all
+// wavefronts share the tiles of all products.  fa(b, i, k), fb(b, k, j), fc(b, i, j, v).
+template <int BATCH, int M, int N, int K, int NT, typename FA, typename FB, typename FC>
+__device__ __forceinline__ void mfma_gemm_f64_batched(FA fa, FB fb, FC fc) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  static_assert(M % 16 == 0 && N % 16 == 0 && K % 16 == 0, "matrix-core tile shapes");
+  constexpr int TM = M / 16, TN = N / 16, NWV = NT / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i16 = lane & 15, q = lane >> 4;
+  for (int t = wv; t < BATCH * TM * TN; t += NWV) {
+    const int bt = t / (TM * TN), tt = t % (TM * TN);
+    const int r0 = (tt % TM) * 16, c0 = (tt / TM) * 16;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = fa(bt, r0 + i16, k0 + 4 * u + q);
+        b[u] = fb(bt, k0 + 4 * u + q, c0 + i16);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fc(bt, r0 + q + 4 * r, c0 + i16, acc[r]);
+  }
+}
+
 // Householder reflector parameters for a column with pivot entry a and sub-pivot norm^2 s:
 // beta = -sign(a) sqrt(a^2 + s), tau = (beta - a) / beta, scal = 1 / (a - beta) (the scale that
 // makes v_pivot = 1).  FP32 uses the hardware reciprocal square root and reciprocal (about 1 ulp
@@ -494,19 +522,16 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       for (int c = 0; c < L - 1; ++c) {
         __syncthreads();
         if (c + 1 < L - 1) lfetch(c + 1);
-        T kx[2][2];
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int b2 = 0; b2 < 2; ++b2)
-            kx[b][b2] = bond_weight<T>(jv, c, 0, b, ep, em) * bond_weight<T>(jv, c, 0, b2, ep, em) +
-                        bond_weight<T>(jv, c, 1, b, ep, em) * bond_weight<T>(jv, c, 1, b2, ep, em);
+        // kx(b,b') = sum_x wv(x,b) wv(x,b') = ep^2 + em^2 if b == b', 2 ep em otherwise, whatever
+        // the sign of the vertical coupling (kept as two scalars: a 2x2 table indexed by the
+        // runtime b would be placed in scratch memory)
+        const T kxd = ep * ep + em * em, kxo = T(2) * ep * em;
         T mx = 0;
         if (c == 0) {
           for (int o = tid; o < N2 * N2; o += NT) {
             const int i = o / N2, k = o % N2;
             const int b = i / CHI, ap = i % CHI, b2 = k / CHI, ap2 = k % CHI;
-            const T f = b ? (b2 ? kx[1][1] : kx[1][0]) : (b2 ? kx[0][1] : kx[0][0]);
+            const T f = (b == b2) ? kxd : kxo;
             const T g = f * As2[(b * CHI) * LDC + ap] * As2[(b2 * CHI) * LDC + ap2];
             gY[i * LDT + k] = g;
             mx = fmax(mx, fabs(g));
@@ -540,28 +565,20 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           if (c + 1 < L - 1) lpark();   // into the other buffer: As2 is read until the end of site c
           if constexpr (MF64) {
             // Q_bb' = P_bb' A_c[b'] (into gX), then G_c = kx A_c[b]^T Q_bb' (into gY)
-#pragma unroll
-            for (int blk = 0; blk < 4; ++blk) {
-              const int b2 = blk & 1;
-              mfma_gemm_f64<CHI, CHI, CHI, NT>(
-                  [&](int i, int k) { return gY[(blk * CHI + i) * LDC + k]; },
-                  [&](int k, int j) { return As2[(b2 * CHI + k) * LDC + j]; },
-                  [&](int i, int j, T v) { gX[(blk * CHI + i) * LDC + j] = v; });
-            }
+            mfma_gemm_f64_batched<4, CHI, CHI, CHI, NT>(
+                [&](int blk, int i, int k) { return gY[(blk * CHI + i) * LDC + k]; },
+                [&](int blk, int k, int j) { return As2[((blk & 1) * CHI + k) * LDC + j]; },
+                [&](int blk, int i, int j, T v) { gX[(blk * CHI + i) * LDC + j] = v; });
             __syncthreads();
-#pragma unroll
-            for (int blk = 0; blk < 4; ++blk) {
-              const int b = blk >> 1, b2 = blk & 1;
-              const T f = kx[b][b2];
-              mfma_gemm_f64<CHI, CHI, CHI, NT>(
-                  [&](int i, int k) { return As2[(b * CHI + k) * LDC + i]; },
-                  [&](int k, int j) { return gX[(blk * CHI + k) * LDC + j]; },
-                  [&](int i, int j, T v) {
-                    const T g = f * v;
-                    gY[(b * CHI + i) * LDT + b2 * CHI + j] = g;
-                    mx = fmax(mx, fabs(g));
-                  });
-            }
+            mfma_gemm_f64_batched<4, CHI, CHI, CHI, NT>(
+                [&](int blk, int i, int k) { return As2[((blk >> 1) * CHI + k) * LDC + i]; },
+                [&](int blk, int k, int j) { return gX[(blk * CHI + k) * LDC + j]; },
+                [&](int blk, int i, int j, T v) {
+                  const int b = blk >> 1, b2 = blk & 1;
+                  const T g = ((b == b2) ? kxd : kxo) * v;
+                  gY[(b * CHI + i) * LDT + b2 * CHI + j] = g;
+                  mx = fmax(mx, fabs(g));
+                });
           } else {
             // Q_bb' = P_bb' A_c[b'] (into gX)
             for (int t = tid; t < 4 * tmb * tmb; t += NT) {
@@ -611,7 +628,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   #pragma unroll
                   for (int v = 0; v < TL; ++v) acc[u][v] += av[u] * bv[v];
               }
-              const T f = b ? (b2 ? kx[1][1] : kx[1][0]) : (b2 ? kx[0][1] : kx[0][0]);
+              const T f = (b == b2) ? kxd : kxo;
   #pragma unroll
               for (int u = 0; u < TL; ++u)
   #pragma unroll
@@ -903,77 +920,88 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ga, gb, gc);
         else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ga, gb, gc);
         __syncthreads();
-        if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ha, hb, hc);
-        else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ha, hb, hc);
+        if constexpr (MF64) {
+          // H is symmetric: the tiles on and above the diagonal, each mirrored below
+          typedef double v4d __attribute__((ext_vector_type(4)));
+          constexpr int TH = N2 / 16, NTILE = TH * (TH + 1) / 2;
+          const int lane = tid & 63, wvi = tid >> 6, i16 = lane & 15, qg = lane >> 4;
+          for (int t = wvi; t < NTILE; t += NW) {
+            int ti = 0, rem = t;
+            while (rem >= TH - ti) { rem -= TH - ti; ++ti; }
+            const int tj = ti + rem;
+            const int r0 = ti * 16, c0 = tj * 16;
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < N2; k0 += 16) {
+              double a[4], b[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                a[u] = ha(r0 + i16, k0 + 4 * u + qg);
+                b[u] = hb(k0 + 4 * u + qg, c0 + i16);
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+              const int i = r0 + qg + 4 * rr, j = c0 + i16;
+              bufR[i * LDT + j] = acc[rr];
+              if (ti != tj) bufR[j * LDT + i] = acc[rr];
+            }
+          }
+        } else {
+          gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ha, hb, hc);
+        }
         __syncthreads();
         // ---- pivoted Cholesky of H, stopping at the numerical rank: H[p, p] = L L^T ----
-        // Left-looking: with p_j the pivot of step j (largest remaining diagonal d),
-        //   L[a][j] = (H[a][p_j] - sum_{i<j} L[a][i] L[p_j][i]) / sqrt(d[p_j]),  d[a] -= L[a][j]^2.
-        // The TPR threads of row a split the sum; row j of L^T (natural column order) goes to Tw.
-        constexpr int TPR = NT / N2;
-        constexpr int PW = (N2 + 63) / 64;
-        const int ra = tid / TPR, cpart = tid % TPR;
-        uint64_t pk[PW];
-#pragma unroll
-        for (int w = 0; w < PW; ++w) pk[w] = 0ull;
-        // (a one-word mask is indexed statically: a dynamic index would put pk in scratch memory)
-        auto picked = [&](int i) {
-          if constexpr (PW == 1) return ((pk[0] >> (i & 63)) & 1ull) != 0ull;
-          else return ((pk[i >> 6] >> (i & 63)) & 1ull) != 0ull;
-        };
-        // Pivot choice by one unsigned maximum: key = float bits of d with the low IB bits
-        // replaced by N2-1-row (larger d first, to 2^(IB-23) relative; ties to the smaller row).
-        // The exact d of every row is published in dv[] for the pivot's square root.
-        constexpr int IB = (N2 <= 64) ? 6 : 7;
-        static_assert(N2 <= (1 << IB), "row index fits the key");
-        auto key_of = [&](T d, int row) -> uint32_t {
-          const uint32_t fb = __float_as_uint(float(fmax(d, T(0))));
-          return (fb & ~((1u << IB) - 1u)) | uint32_t(N2 - 1 - row);
-        };
-        uint32_t* candk = reinterpret_cast<uint32_t*>(candi);   // 2 x NW keys
-        T* dv = sc;                                             // N2 exact diagonals
-        T dreg = bufR[ra * LDT + ra];
-        if (cpart == 0) dv[ra] = dreg;
-        fro2 = block_sum<NT>(cpart == 0 ? fmax(dreg, T(0)) : T(0), red);
-        {
-          const uint32_t k = wave_max_u32(cpart == 0 ? key_of(dreg, ra) : 0u);
-          if ((tid & (WAVE - 1)) == 0) candk[tid / WAVE] = k;
-        }
-        __syncthreads();
-        const T tolr2 = T(Tol::rank) * T(Tol::rank) * fro2;
-        for (int j = 0; j < N2; ++j) {
-          const int buf = j & 1;
-          uint32_t bk = candk[buf * NW];
-#pragma unroll
-          for (int w = 1; w < NW; ++w) bk = max(bk, candk[buf * NW + w]);
-          const int piv = N2 - 1 - int(bk & ((1u << IB) - 1u));
-          const T best = dv[piv];
-          if (bk == 0u || !(best > tolr2)) { rank = j; break; }
-          // 1/sqrt(d) from the hardware estimate refined by two Newton steps, sqrt(d) = d / sqrt(d)
-          T inv = T(__builtin_amdgcn_rsq(double(best)));
-          inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
-          inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
-          const T sq = best * inv;
-          T dot = 0;
-          for (int i = cpart; i < j; i += TPR) dot += Tw[i * LDT + ra] * Tw[i * LDT + piv];
-          dot = group_sum<TPR>(dot);
-          const bool arow = !picked(ra) && ra != piv;
-          const T La = (ra == piv) ? sq : (arow ? (bufR[ra * LDT + piv] - dot) * inv : T(0));
-          if (cpart == 0) Tw[j * LDT + ra] = La;
-          dreg -= arow ? La * La : T(0);
-          if (cpart == 0 && arow) dv[ra] = dreg;
-          if constexpr (PW == 1) pk[0] |= 1ull << (piv & 63);
-          else pk[piv >> 6] |= 1ull << (piv & 63);
-          if (tid == 0) perm[j] = piv;
-          {
-            const uint32_t k = wave_max_u32((cpart == 0 && arow) ? key_of(dreg, ra) : 0u);
-            if ((tid & (WAVE - 1)) == 0) candk[(buf ^ 1) * NW + tid / WAVE] = k;
+        // One wavefront, lane a = row a (2 CHI <= 64), so the loop needs no workgroup barrier.
+        // Left-looking: with p_j the row of largest remaining diagonal d,
+        //   L[a][j] = (H[a][p_j] - sum_{i<j} L[a][i] L[p_j][i]) / sqrt(d[p_j]),  d[a] -= L[a][j]^2;
+        // row j of L^T (natural column order) goes to Tw.  The pivot comes from one unsigned wave
+        // maximum over keys (float bits of d with the low 6 bits = 63 - row: larger d first, to
+        // 2^-17 relative, ties to the smaller row); its exact d by readlane.  Within one wavefront
+        // LDS operations complete in order, so the rows of L^T written at step i are visible to
+        // every lane at later steps.
+        static_assert(N2 <= WAVE, "one wavefront holds every row");
+        if (tid < WAVE) {
+          const int a = tid;
+          const bool live = a < N2;
+          T d = live ? bufR[a * LDT + a] : T(0);
+          const T f2 = wave_sum(live ? fmax(d, T(0)) : T(0));
+          const T tol2 = T(Tol::rank) * T(Tol::rank) * f2;
+          bool pkd = !live;
+          int rk = N2;
+          for (int j = 0; j < N2; ++j) {
+            const uint32_t key =
+                pkd ? 0u : ((__float_as_uint(float(fmax(d, T(0)))) & ~63u) | uint32_t(63 - a));
+            const uint32_t bk = wave_max_u32(key);
+            const int piv = 63 - int(bk & 63u);
+            const T best = readlane_v(d, piv);
+            if (bk == 0u || !(best > tol2)) { rk = j; break; }
+            // 1/sqrt(d) from the hardware estimate refined by two Newton steps
+            T inv = T(__builtin_amdgcn_rsq(double(best)));
+            inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
+            inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
+            const T sq = best * inv;
+            const T hap = bufR[a * LDT + piv];
+            T dot = 0;
+            for (int i = 0; i < j; ++i) dot += Tw[i * LDT + a] * Tw[i * LDT + piv];
+            const bool arow = !pkd && a != piv;
+            const T La = (a == piv) ? sq : (arow ? (hap - dot) * inv : T(0));
+            if (live) Tw[j * LDT + a] = La;
+            d -= arow ? La * La : T(0);
+            if (a == piv) pkd = true;
+            if (a == 0) perm[j] = piv;
           }
-          __syncthreads();
+          if (live) unpk[a] = pkd ? 0 : 1;
+          if (a == 0) {
+            imisc[7] = rk;
+            misc[0] = f2;
+          }
         }
-        // columns never picked follow the pivots in ascending order
-        if (tid < N2) unpk[tid] = picked(tid) ? 0 : 1;
         __syncthreads();
+        rank = imisc[7];
+        fro2 = misc[0];
         rank_unpicked(rank);
         // J = rows 0..rank-1 of L^T in pivoted column order (row-major in bufR, ld LDT)
         const int nr = rank + (rank & 1);

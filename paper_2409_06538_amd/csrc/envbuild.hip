@@ -331,6 +331,90 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
 // applied PASSES times, one barrier per row.  A group of TPP threads owns one row.  A row whose residual
 // norm^2 falls below eta (the rows start with unit norm) lies in the span of the earlier rows to
 // rounding and is set to zero; the span of the others is unchanged.
+// One pass of modified Gram-Schmidt on rows 0..k-1 of V taking the rows two at a time, one
+// barrier per pair: with rows a and c = a+1 as they stand at the start of the step,
+// c' = c - (<c,a>/<a,a>) a, and every later row b subtracts its projections on a and c', formed
+// from <b,a>, <b,c>, <a,a>, <c,a>, <c,c>.  Rows whose residual norm^2 falls below eta are set to
+// zero; the rows are normalised at the end.
+template <typename T, int CHI, int NT, int LDVR>
+__device__ void mgs_pairs_rows(T* V, int k, T eta) {
+  constexpr int N2 = 2 * CHI, TPP = env_tpp(CHI), EPR = (N2 + TPP - 1) / TPP;
+  const int grp = threadIdx.x / TPP, l = threadIdx.x % TPP;
+  const bool mine = grp < k;
+  T vb[EPR];
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < EPR; ++e) {
+    const int j = l + TPP * e;
+    vb[e] = (mine && j < N2) ? V[grp * LDVR + j] : T(0);
+  }
+  for (int a = 0; a < k; a += 2) {
+    const int c = a + 1;
+    const bool pair = c < k;
+    T va[EPR], vc[EPR];
+    T naa = 0, nca = 0, ncc = 0, dba = 0, dbc = 0;
+#pragma unroll
+    for (int e = 0; e < EPR; ++e) {
+      const int j = l + TPP * e;
+      const int jj = j < N2 ? j : 0;
+      const T ra = V[a * LDVR + jj], rc = V[(pair ? c : a) * LDVR + jj];
+      va[e] = (j < N2) ? ra : T(0);
+      vc[e] = (pair && j < N2) ? rc : T(0);
+      naa += va[e] * va[e];
+      nca += vc[e] * va[e];
+      ncc += vc[e] * vc[e];
+      dba += vb[e] * va[e];
+      dbc += vb[e] * vc[e];
+    }
+    naa = group_sum<TPP>(naa);
+    nca = group_sum<TPP>(nca);
+    ncc = group_sum<TPP>(ncc);
+    dba = group_sum<TPP>(dba);
+    dbc = group_sum<TPP>(dbc);
+    const bool aok = naa > eta;
+    const T ria = aok ? fast_rcp(naa) : T(0);
+    const T g = nca * ria;                  // c' = c - g a
+    const T ncp = ncc - g * nca;            // <c', c'>
+    const bool cok = pair && ncp > eta;
+    if (mine && grp > c) {
+      const T fa = dba * ria;
+      const T fc = cok ? (dbc - g * dba) * fast_rcp(ncp) : T(0);
+      const T ca = fa - fc * g;             // b -= fa a + fc c' = (fa - fc g) a + fc c
+#pragma unroll
+      for (int e = 0; e < EPR; ++e) {
+        const int j = l + TPP * e;
+        vb[e] -= ca * va[e] + fc * vc[e];
+        if (j < N2) V[grp * LDVR + j] = vb[e];
+      }
+    }
+    if (mine && grp == c) {
+#pragma unroll
+      for (int e = 0; e < EPR; ++e) {
+        const int j = l + TPP * e;
+        vb[e] = cok ? vb[e] - g * va[e] : T(0);
+        if (j < N2) V[grp * LDVR + j] = vb[e];
+      }
+    }
+    if (mine && grp == a && !aok) {
+#pragma unroll
+      for (int e = 0; e < EPR; ++e) vb[e] = T(0);
+    }
+    __syncthreads();
+  }
+  T n2 = 0;
+#pragma unroll
+  for (int e = 0; e < EPR; ++e) n2 += vb[e] * vb[e];
+  n2 = group_sum<TPP>(n2);
+  const T f = (n2 > T(0)) ? T(1) / sqrt(n2) : T(0);
+#pragma unroll
+  for (int e = 0; e < EPR; ++e) {
+    const int j = l + TPP * e;
+    vb[e] *= f;
+    if (mine && j < N2) V[grp * LDVR + j] = vb[e];
+  }
+  __syncthreads();
+}
+
 template <typename T, int CHI, int NT, int PASSES, int LDVR>
 __device__ void mgs2_rows(T* V, int k, T eta) {
   constexpr int N2 = 2 * CHI, TPP = env_tpp(CHI), EPR = (N2 + TPP - 1) / TPP;
@@ -984,8 +1068,19 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
             inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
             const T sq = best * inv;
             const T hap = bufR[a * LDT + piv];
+            // four rows per round, loads issued together (rows past j are clamped and masked)
             T dot = 0;
-            for (int i = 0; i < j; ++i) dot += Tw[i * LDT + a] * Tw[i * LDT + piv];
+            for (int i0 = 0; i0 < j; i0 += 4) {
+              T x[4], y[4];
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int ii = (i0 + u < N2) ? i0 + u : N2 - 1;
+                x[u] = Tw[ii * LDT + a];
+                y[u] = Tw[ii * LDT + piv];
+              }
+#pragma unroll
+              for (int u = 0; u < 4; ++u) dot += (i0 + u < j) ? x[u] * y[u] : T(0);
+            }
             const bool arow = !pkd && a != piv;
             const T La = (a == piv) ? sq : (arow ? (hap - dot) * inv : T(0));
             if (live) Tw[j * LDT + a] = La;
@@ -1227,7 +1322,8 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       // One pass suffices in the Gram form: the rows come from a pivoted Cholesky factor whose
       // conditioning is bounded by the FP32 rank tolerance, so FP64 Gram-Schmidt leaves them
       // orthonormal to ~1e-10; FP64 environments need the second pass.
-      mgs2_rows<T, CHI, NT, GRAM ? 1 : 2, LDV>(bufS, kept, T(Tol::eta));
+      if constexpr (GRAM) mgs_pairs_rows<T, CHI, NT, LDV>(bufS, kept, T(Tol::eta));
+      else mgs2_rows<T, CHI, NT, 2, LDV>(bufS, kept, T(Tol::eta));
       E* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
       for (int o = tid; o < int(site); o += NT) {
         const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;

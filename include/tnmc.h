@@ -76,7 +76,8 @@ typedef struct {
 /* Number of observable accumulators per realization (see tnmc_accept). */
 #define TNMC_OBS_COUNT 9
 
-/* Supported bond dimensions: chi in {2, 4, 8, 16, 32}; L in [2, 1024]. */
+/* Supported bond dimensions: chi in {2, 4, 8, 16, 32} for every precision, and chi = 48 for
+ * TNMC_FP32 and TNMC_BF16; L in [2, 1024].  Returns 1 if supported, else 0. */
 int tnmc_chi_supported(int32_t chi, tnmc_precision prec);
 
 /* Bytes of one realization's environments: L rows x L sites x 2 x chi x chi elements of the

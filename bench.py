@@ -68,63 +68,98 @@ def build_flops_per_site(chi):
     return 270.0 * chi ** 3
 
 
+def workload_sizes(w):
+    """Lattice size of every realization of a workload (uniform L, or L cycling through Ls)."""
+    seeds = list(w["seeds"])
+    if "Ls" in w:
+        return [w["Ls"][i % len(w["Ls"])] for i in range(len(seeds))], seeds
+    return [w["L"]] * len(seeds), seeds
+
+
 def run_gpu(args):
     import torch
     from paper_2409_06538_amd import binding
     import synth
 
     w = synth.WORKLOADS[args.workload]
-    L, chi, p, K = w["L"], w["chi"], w["p"], args.proposals or w["proposals"]
-    seeds = list(w["seeds"])
+    Ls, seeds = workload_sizes(w)
+    chi, p, K = w["chi"], w["p"], args.proposals or w["proposals"]
     n = len(seeds)
     beta = binding.nishimori_beta(p)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    b = binding.Batch([L] * n, [beta] * n, seeds, chi, args.precision, K=K, device=dev)
+    b = binding.Batch(Ls, [beta] * n, seeds, chi, args.precision, K=K, device=dev)
     out = (torch.empty(b.spins_shape(K), dtype=torch.int64, device=dev),
            torch.empty((n, K), dtype=torch.float64, device=dev),
            torch.empty((n, K), dtype=torch.int32, device=dev))
     accum = torch.zeros((n, binding.OBS_COUNT), dtype=torch.float64, device=dev)
+    chains = b.new_chains(1)
     ev = []
 
-    def step(timed):
+    def step(events):
         b.make_couplings(seeds, p)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e2 = torch.cuda.Event(enable_timing=True)
-        e0.record()
+        if events is not None:
+            events[0].record()
         b.build_env(want_lnZ=False)
-        e1.record()
+        if events is not None:
+            events[1].record()
         b.propose(K, args.seed, first_proposal=0, out=out)
-        e2.record()
-        chains = b.new_chains(1)
+        if events is not None:
+            events[2].record()
+        for t in (chains["spins"], chains["E"], chains["logq"], chains["init"]):
+            t.zero_()
         acc, _ = b.accept(out, chains, seed=args.seed, accum=accum)
-        if timed:
-            ev.append((e0, e1, e2))
         return acc
 
-    for _ in range(args.warmup):
-        step(False)
+    def new_events():
+        return [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+    for _ in range(max(1, args.warmup) if args.graph else args.warmup):
+        e = new_events()
+        step(e)
+        ev.append(e)          # graph mode: phase times come from the eager warm-up steps
     torch.cuda.synchronize()
+    if not args.graph:
+        ev = []
+    graph = None
+    if args.graph:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            gacc = step(None)
+        torch.cuda.synchronize()
+    # accepted spin-updates of one step: per realization, accepted proposals x L^2
+    L2 = torch.tensor([L * L for L in Ls], dtype=torch.float64, device=dev)
     accs = []
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        accs.append(step(True))
+        if graph is not None:
+            graph.replay()
+            acc = gacc
+        else:
+            e = new_events()
+            acc = step(e)
+            ev.append(e)
+        per_real = acc.sum(dim=1, dtype=torch.float64)
+        accs.append(torch.stack([per_real.sum(), (per_real * L2).sum()]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    accepted = int(sum(int(a.sum().item()) for a in accs))
+    tot = torch.stack(accs).sum(dim=0).tolist()
+    accepted, updates = int(tot[0]), tot[1]
     attempted = args.steps * n * (K - 1)
-    build_ms = sum(a.elapsed_time(bb) for a, bb, _ in ev) / len(ev)
-    prop_ms = sum(bb.elapsed_time(c) for _, bb, c in ev) / len(ev)
+    build_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / len(ev)
+    prop_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / len(ev)
     wall = t1 - t0
     res = {
-        "L": L, "chi": chi, "n": n, "K": K, "p": p, "beta": beta,
+        "Ls": sorted(set(Ls)), "chi": chi, "n": n, "K": K, "p": p, "beta": beta,
         "wall_s": wall, "ms_per_step": 1e3 * wall / args.steps,
+        "value": updates / wall,
         "accepted": accepted, "attempted": attempted,
-        "value": accepted * L * L / wall,
         "acceptance": accepted / attempted,
         "build_ms": build_ms, "propose_ms": prop_ms,
+        "graph": bool(args.graph),
     }
-    flops = build_flops_per_site(chi) * (L - 1) * L * n
+    flops = sum(build_flops_per_site(chi) * (L - 1) * L for L in Ls)
     peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
     achieved = flops / (build_ms * 1e-3) / 1e12
     res["roofline"] = {"kernel": "env_build_kernel", "bound": "alu", "achieved": achieved,
@@ -137,8 +172,8 @@ def run_gpu(args):
     elem = 8 if args.precision == "fp64" else 4
     esize = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
     kpad = (K + 63) // 64 * 64
-    vbytes = 2.0 * L * L * 2 * chi * kpad * n * elem
-    ebytes = 2.0 * L * L * 2 * chi * chi * esize * (kpad // 64) * n
+    vbytes = sum(2.0 * L * L * 2 * chi * kpad * elem for L in Ls)
+    ebytes = sum(2.0 * L * L * 2 * chi * chi * esize * (kpad // 64) for L in Ls)
     pbytes = vbytes + ebytes
     pach = pbytes / (prop_ms * 1e-3) / 1e9
     res["roofline_propose"] = {"kernel": "propose_mfma_kernel" if chi % 16 == 0 else "propose_kernel",
@@ -236,6 +271,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture the whole step in one HIP graph and time its replays (phase "
+                         "times then come from the eager warm-up steps)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy one buffer of this many MiB once (a plain copy "
                          "kernel of known size, the reference for hardware byte counters)")
@@ -248,8 +286,14 @@ def main():
     res = run_gpu(args)
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
-    plain = None if args.no_plain else run_fp64_plain(args, res["L"], res["chi"], res["p"], res["K"])
-    cpu = None if args.no_cpu else run_cpu_baseline(res["L"], res["chi"], res["p"], res["K"], args.seed)
+    uniform = len(res["Ls"]) == 1
+    L0 = res["Ls"][0]
+    # the FP64 plain form and the CPU oracle are measured on uniform-L workloads
+    plain = None if args.no_plain or not uniform else run_fp64_plain(args, L0, res["chi"], res["p"],
+                                                                     res["K"])
+    cpu = None if args.no_cpu or not uniform else run_cpu_baseline(L0, res["chi"], res["p"],
+                                                                   res["K"], args.seed)
+    size = f"{L0}x{L0}" if uniform else "L x L (L in " + ", ".join(map(str, res["Ls"])) + ")"
     line = {
         "metric": METRIC,
         "value": res["value"],
@@ -263,12 +307,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {res['n']} realizations of the {res['L']}x"
-                               f"{res['L']} open +-J lattice, p={res['p']}, Nishimori beta, "
-                               f"chi={res['chi']}, {res['K']} proposals each, "
-                               f"{args.precision} batched",
-                   "L": res["L"], "chi": res["chi"], "realizations": res["n"],
-                   "proposals": res["K"], "p": res["p"], "precision": args.precision},
+        "config": {"workload": f"{args.workload}: {res['n']} realizations of the {size} open "
+                               f"+-J lattice, p={res['p']}, Nishimori beta, chi={res['chi']}, "
+                               f"{res['K']} proposals each, {args.precision} batched"
+                               + (", one HIP graph per step" if res["graph"] else ""),
+                   "L": L0 if uniform else res["Ls"], "chi": res["chi"], "realizations": res["n"],
+                   "proposals": res["K"], "p": res["p"], "precision": args.precision,
+                   "graph": res["graph"]},
         "acceptance": res["acceptance"],
         "accepted": res["accepted"],
         "attempted": res["attempted"],

@@ -30,6 +30,11 @@
  *    keyed (k0, k1) with counter words (c1, c2, c3) is word (i & 3) of the block at counter
  *    (i >> 2, c1, c2, c3), turned into u = (w >> 11) * 2^-53 in [0, 1).
  *  - Concurrent calls that share a workspace race; use one workspace per stream.
+ *  - Every call enqueues kernel launches only (host tables and seeds travel as kernel
+ *    arguments; no copies from host memory, no memsets), so a sequence of calls can be captured
+ *    into a HIP graph and replayed: each replay uses the host values of the capture and the
+ *    device buffers they name.  The first call of each (precision, chi) on a device should be
+ *    made outside a capture (it raises the kernel's LDS limit once).
  */
 #ifndef TNMC_H
 #define TNMC_H

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 #include "common.hpp"
@@ -59,9 +60,34 @@ size_t accept_region(int32_t n, int32_t K) { return 2 * align_up(size_t(n) * K *
 
 enum class Use { build, propose, none };
 
+// Host data (the descriptor table, the coupling seeds) reaches the device as kernel arguments,
+// not as a copy from pageable host memory: a kernel node of a captured HIP graph keeps its
+// argument values, so a sequence of calls captured into a graph replays correctly.
+constexpr int ARG_WORDS = 384;   // 3 KiB per launch, inside the 4 KiB kernel-argument block
+struct ArgWords {
+  uint64_t w[ARG_WORDS];
+};
+
+__global__ void __launch_bounds__(128) store_words_kernel(ArgWords a, uint64_t* dst, int count) {
+  for (int i = threadIdx.x; i < count; i += blockDim.x) dst[i] = a.w[i];
+}
+
+hipError_t store_words(const uint64_t* src, size_t count, uint64_t* dst, hipStream_t stream) {
+  for (size_t o = 0; o < count; o += ARG_WORDS) {
+    ArgWords a;
+    const size_t c = std::min<size_t>(ARG_WORDS, count - o);
+    std::memcpy(a.w, src + o, c * sizeof(uint64_t));
+    hipLaunchKernelGGL(store_words_kernel, dim3(1), dim3(128), 0, stream, a, dst + o, int(c));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 // Build the device descriptor table in the workspace; per-realization slices for `use`.
 hipError_t upload_desc(const tnmc_instance* inst, int32_t n, int32_t chi, int32_t K,
                        tnmc_precision p, Use use, void* ws, hipStream_t stream) {
+  static_assert(sizeof(DevReal) % sizeof(uint64_t) == 0, "descriptor is whole words");
   std::vector<DevReal> h(n);
   char* base = static_cast<char*>(ws) + desc_bytes(n);
   size_t off = 0;
@@ -79,8 +105,8 @@ hipError_t upload_desc(const tnmc_instance* inst, int32_t n, int32_t chi, int32_
     if (use == Use::build) off += align_up(env_build_scratch_bytes(p, chi, inst[i].L));
     else if (use == Use::propose) off += align_up(propose_scratch_bytes(p, chi, inst[i].L, K));
   }
-  // Pageable source: the runtime stages it before returning, so `h` may go out of scope.
-  return hipMemcpyAsync(ws, h.data(), sizeof(DevReal) * n, hipMemcpyHostToDevice, stream);
+  return store_words(reinterpret_cast<const uint64_t*>(h.data()),
+                     sizeof(DevReal) * n / sizeof(uint64_t), static_cast<uint64_t*>(ws), stream);
 }
 
 inline tnmc_status hip_status(hipError_t e) { return e == hipSuccess ? TNMC_OK : TNMC_EHIP; }
@@ -115,8 +141,7 @@ tnmc_status tnmc_make_couplings(const tnmc_instance* inst, int32_t n, const uint
   char* d = static_cast<char*>(d_workspace);
   hipError_t e = upload_desc(inst, n, 4, 1, TNMC_FP32, Use::none, d, stream);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(d + desc_bytes(n), seeds, sizeof(uint64_t) * n, hipMemcpyHostToDevice,
-                       stream);
+    e = store_words(seeds, size_t(n), reinterpret_cast<uint64_t*>(d + desc_bytes(n)), stream);
   if (e == hipSuccess)
     e = couplings_launch(reinterpret_cast<const DevReal*>(d), n,
                          reinterpret_cast<const uint64_t*>(d + desc_bytes(n)), p, Lmax, stream);

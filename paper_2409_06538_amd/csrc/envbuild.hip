@@ -21,6 +21,8 @@
 // workgroup barrier per column.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <type_traits>
 
 #include "common.hpp"
@@ -1393,9 +1395,20 @@ hipError_t launch_env_build(const DevReal* d_reals, int n, double* d_lnZ, hipStr
   static_assert(S::NT % 64 == 0, "");
   static_assert(LeftCfg<CHI>::lds <= S::bufA, "left-sweep buffers fit in bufA");
   static_assert(LeftCfg<CHI>::TPC * LeftCfg<CHI>::RPT >= LeftCfg<CHI>::MQ, "rows covered");
-  hipError_t err = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_kernel<T, E, CHI, GRAM>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(S::bytes));
+  // Raise the dynamic-LDS limit once per device (not on every call, so that calls captured
+  // into a HIP graph enqueue nothing but the launch).
+  constexpr int MAX_DEVICES = 64;
+  static std::once_flag once[MAX_DEVICES];
+  static hipError_t attr[MAX_DEVICES];
+  int dev = 0;
+  hipError_t err = hipGetDevice(&dev);
   if (err != hipSuccess) return err;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::call_once(once[dev], [dev] {
+    attr[dev] = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_kernel<T, E, CHI, GRAM>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(S::bytes));
+  });
+  if (attr[dev] != hipSuccess) return attr[dev];
   hipLaunchKernelGGL((env_build_kernel<T, E, CHI, GRAM>), dim3(n), dim3(S::NT), S::bytes, stream, d_reals,
                      d_lnZ);
   return hipGetLastError();

@@ -4,11 +4,17 @@ One step = one pass of the whole hot path over one batch: couplings (a1) -> envi
 a3) -> K proposals per realization with log q and exact energies (a4, a5) -> independence
 Metropolis over them (a6).  Default workload: 64 realizations of the 64 x 64 open +-J lattice at
 p = 0.109 on the Nishimori line, chi = 32, 1000 proposals each, FP32 batched (one launch per
-stage for the whole batch).  Also measured: the FP64 plain form (FP64 environments, one
+stage for the whole batch).
+
+Consecutive steps overlap on two streams: the build of step t+1 (one workgroup per realization,
+on CUs kept free of proposal work by a CU mask) runs during the proposals and accepts of step t
+(on the other CUs); two sets of environments alternate.  The timed region starts with an empty
+pipeline and ends when the last step's accepts are done.  `serial` reports the same steps one
+after the other on one stream.  Also measured: the FP64 plain form (FP64 environments, one
 realization per call, one proposal per call) on a bounded sample, and the CPU FP64 oracle on the
 host (bounded sample, extrapolated; labelled).
 
-Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1]
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 1] [--serial]
 """
 import argparse
 import json
@@ -31,16 +37,16 @@ HBM_PEAK_GBS = 8000.0
 # only for the kernel sources they were taken on: reported as null once those change.
 COUNTED_TRAFFIC = {
     ("rbim64", "fp32", "env_build"): {
-        "fetch_kib": 5957411.6, "fetch_factor": 1048576.0 / 524306.625,
-        "write_kib": 10225272.5, "write_factor": 1.0,
+        "fetch_kib": 5958406.4, "fetch_factor": 1048576.0 / 524299.5,
+        "write_kib": 10225280.1, "write_factor": 1.0,
         "sources_sha256": {
-            "envbuild.hip": "45ce8c1325b473ea1978155f3da6fdbb9cb71c539620b82c22d80b39562996c3",
+            "envbuild.hip": "58ef749acd1734e03416e2c7ad02897ea99924c43025f47e7c9000434013dcb7",
             "common.hpp": "d3d203ac7e1f0d0435cb5dfe9b83b18a8e2489c363933aa5b163e724c48f17b5",
         },
     },
     ("rbim64", "fp32", "propose"): {
-        "fetch_kib": 63694703.3, "fetch_factor": 1048576.0 / 524306.625,
-        "write_kib": 67237614.0, "write_factor": 1.0,
+        "fetch_kib": 63672803.0, "fetch_factor": 1048576.0 / 524299.5,
+        "write_kib": 67237444.3, "write_factor": 1.0,
         "sources_sha256": {
             "sampler.hip": "36e477df883f9a1863bafa2e69bfcd168aa700f756c771cfdb0dc71be2dd0f25",
             "common.hpp": "d3d203ac7e1f0d0435cb5dfe9b83b18a8e2489c363933aa5b163e724c48f17b5",
@@ -74,6 +80,34 @@ def workload_sizes(w):
     if "Ls" in w:
         return [w["Ls"][i % len(w["Ls"])] for i in range(len(seeds))], seeds
     return [w["L"]] * len(seeds), seeds
+
+
+def add_rooflines(res, args, Ls):
+    """Dominant-kernel rooflines from the HIP-event launch times in `res`."""
+    chi, K, build_ms, prop_ms = res["chi"], res["K"], res["build_ms"], res["propose_ms"]
+    flops = sum(build_flops_per_site(chi) * (L - 1) * L for L in Ls)
+    peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+    achieved = flops / (build_ms * 1e-3) / 1e12
+    res["roofline"] = {"kernel": "env_build_kernel", "bound": "alu", "achieved": achieved,
+                       "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                       "traffic": counted_traffic(args.workload, args.precision, "env_build"),
+                       "launch_ms": build_ms,
+                       "algorithmic_flops_per_launch": flops}
+    # proposals: HBM-bound; algorithmic bytes = the per-row V store written and read back, plus
+    # each workgroup of 64 proposals streaming its realization's environments once per sweep
+    elem = 8 if args.precision == "fp64" else 4
+    esize = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
+    kpad = (K + 63) // 64 * 64
+    vbytes = sum(2.0 * L * L * 2 * chi * kpad * elem for L in Ls)
+    ebytes = sum(2.0 * L * L * 2 * chi * chi * esize * (kpad // 64) for L in Ls)
+    pbytes = vbytes + ebytes
+    pach = pbytes / (prop_ms * 1e-3) / 1e9
+    res["roofline_propose"] = {"kernel": "propose_mfma_kernel" if chi % 16 == 0 else "propose_kernel",
+                               "bound": "hbm", "achieved": pach, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": pach / HBM_PEAK_GBS,
+                               "traffic": counted_traffic(args.workload, args.precision, "propose"),
+                               "launch_ms": prop_ms, "algorithmic_bytes_per_launch": pbytes}
+    return res
 
 
 def run_gpu(args):
@@ -159,29 +193,131 @@ def run_gpu(args):
         "build_ms": build_ms, "propose_ms": prop_ms,
         "graph": bool(args.graph),
     }
-    flops = sum(build_flops_per_site(chi) * (L - 1) * L for L in Ls)
-    peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
-    achieved = flops / (build_ms * 1e-3) / 1e12
-    res["roofline"] = {"kernel": "env_build_kernel", "bound": "alu", "achieved": achieved,
-                       "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                       "traffic": counted_traffic(args.workload, args.precision, "env_build"),
-                       "launch_ms": build_ms,
-                       "algorithmic_flops_per_launch": flops}
-    # proposals: HBM-bound; algorithmic bytes = the per-row V store written and read back, plus
-    # each workgroup of 64 proposals streaming its realization's environments once per sweep
-    elem = 8 if args.precision == "fp64" else 4
-    esize = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
-    kpad = (K + 63) // 64 * 64
-    vbytes = sum(2.0 * L * L * 2 * chi * kpad * elem for L in Ls)
-    ebytes = sum(2.0 * L * L * 2 * chi * chi * esize * (kpad // 64) for L in Ls)
-    pbytes = vbytes + ebytes
-    pach = pbytes / (prop_ms * 1e-3) / 1e9
-    res["roofline_propose"] = {"kernel": "propose_mfma_kernel" if chi % 16 == 0 else "propose_kernel",
-                               "bound": "hbm", "achieved": pach, "peak": HBM_PEAK_GBS,
-                               "unit": "GB/s", "frac": pach / HBM_PEAK_GBS,
-                               "traffic": counted_traffic(args.workload, args.precision, "propose"),
-                               "launch_ms": prop_ms, "algorithmic_bytes_per_launch": pbytes}
-    return res
+    return add_rooflines(res, args, Ls)
+
+
+def reserved_cu_bits(word):
+    """Bit positions cleared in 32-bit word `word` of the CU mask: 8 per word, one per residue
+    mod 8 and two per byte, rotated by the word index.  Whether the mask enumerates CUs XCD by
+    XCD (32 per XCD, shader engines by byte or interleaved mod 4) or interleaved across the 8
+    XCDs with shader engines by byte, every XCD then keeps 8 CUs free, 2 in each shader engine."""
+    return [8 * ((x // 2 + word) % 4) + x for x in range(8)]
+
+
+def cu_masked_stream(reserve):
+    """A stream (default priority) whose kernels avoid 8 CUs of every XCD, so that the 64
+    workgroups of a concurrent build always find free CUs.  Returns (stream, mask words), or
+    (None, None) when no mask is asked for or the call fails."""
+    import ctypes
+    import torch
+    if not reserve:
+        return None, None
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    words = (n_cu + 31) // 32
+    vals = []
+    for w in range(words):
+        v = 0xFFFFFFFF
+        for bit in reserved_cu_bits(w):
+            v &= ~(1 << bit)
+        vals.append(v)
+    mask = (ctypes.c_uint32 * words)(*vals)
+    try:
+        hip = ctypes.CDLL("libamdhip64.so")
+    except OSError:
+        return None, None
+    stream = ctypes.c_void_p()
+    err = hip.hipExtStreamCreateWithCUMask(ctypes.byref(stream), ctypes.c_uint32(words), mask)
+    if err != 0 or not stream.value:
+        return None, None
+    ext = torch.cuda.ExternalStream(stream.value)
+    ext.destroy = lambda: hip.hipStreamDestroy(stream)    # the library owns it, not torch
+    return ext, [hex(v) for v in vals]
+
+
+def run_gpu_pipelined(args):
+    """Consecutive steps overlapped on two streams: the build of step t+1 (one workgroup per
+    realization, so a fraction of the CUs) runs while the proposals and accepts of step t use
+    the rest.  Two batches with their own environments and workspaces alternate, so a build never
+    overwrites environments that proposals still read."""
+    import torch
+    from paper_2409_06538_amd import binding
+    import synth
+
+    w = synth.WORKLOADS[args.workload]
+    Ls, seeds = workload_sizes(w)
+    chi, p, K = w["chi"], w["p"], args.proposals or w["proposals"]
+    n = len(seeds)
+    beta = binding.nishimori_beta(p)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s_build = torch.cuda.Stream()
+    s_prop, cu_mask = cu_masked_stream(args.reserve_cus)
+    if s_prop is None:
+        s_prop = torch.cuda.Stream()
+    sets = []
+    for _ in range(2):
+        b = binding.Batch(Ls, [beta] * n, seeds, chi, args.precision, K=K, device=dev)
+        out = (torch.empty(b.spins_shape(K), dtype=torch.int64, device=dev),
+               torch.empty((n, K), dtype=torch.float64, device=dev),
+               torch.empty((n, K), dtype=torch.int32, device=dev))
+        sets.append({"b": b, "out": out, "chains": b.new_chains(1),
+                     "accum": torch.zeros((n, binding.OBS_COUNT), dtype=torch.float64, device=dev),
+                     "acc": torch.empty((n, K), dtype=torch.uint8, device=dev),
+                     "done": None})
+    L2 = torch.tensor([L * L for L in Ls], dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def run(steps, record):
+        sums, ev = [], []
+        for t in range(steps):
+            st = sets[t % 2]
+            b = st["b"]
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            with torch.cuda.stream(s_build):
+                if st["done"] is not None:
+                    s_build.wait_event(st["done"])     # proposals of step t-2 have read this env
+                b.make_couplings(seeds, p)
+                e[0].record(s_build)
+                b.build_env(want_lnZ=False)
+                e[1].record(s_build)
+            with torch.cuda.stream(s_prop):
+                s_prop.wait_event(e[1])
+                e[2].record(s_prop)
+                b.propose(K, args.seed, first_proposal=0, out=st["out"])
+                e[3].record(s_prop)
+                ch = st["chains"]
+                for x in (ch["spins"], ch["E"], ch["logq"], ch["init"]):
+                    x.zero_()
+                acc, _ = b.accept(st["out"], ch, seed=args.seed, accum=st["accum"])
+                per_real = acc.sum(dim=1, dtype=torch.float64)
+                sums.append(torch.stack([per_real.sum(), (per_real * L2).sum()]))
+                done = torch.cuda.Event()
+                done.record(s_prop)
+                st["done"] = done
+            ev.append(e)
+        return sums, ev
+
+    run(max(1, args.warmup), False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sums, ev = run(args.steps, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    tot = torch.stack(sums).sum(dim=0).tolist()
+    accepted, updates = int(tot[0]), tot[1]
+    attempted = args.steps * n * (K - 1)
+    build_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / len(ev)
+    prop_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / len(ev)
+    wall = t1 - t0
+    del sets, sums, ev
+    torch.cuda.synchronize()
+    if cu_mask is not None:
+        s_prop.destroy()
+    return add_rooflines({"Ls": sorted(set(Ls)), "chi": chi, "n": n, "K": K, "p": p, "beta": beta,
+            "wall_s": wall, "ms_per_step": 1e3 * wall / args.steps,
+            "value": updates / wall, "accepted": accepted, "attempted": attempted,
+            "acceptance": accepted / attempted, "build_ms": build_ms, "propose_ms": prop_ms,
+            "graph": False, "pipelined": True, "propose_cu_mask": cu_mask}, args, Ls)
 
 
 def run_fp64_plain(args, L, chi, p, K_full, n_prop=20):
@@ -215,7 +351,7 @@ def run_fp64_plain(args, L, chi, p, K_full, n_prop=20):
                       f"extrapolated to {K_full} proposals"}
 
 
-def run_cpu_baseline(L, chi, p, K_full, seed, n_real=4, n_prop=100):
+def run_cpu_baseline(L, chi, p, K_full, seed, n_real=6, n_prop=150):
     """The oracle on one host core: n_real realizations (coupling seeds 0..n_real-1), each a full
     build + n_prop proposals (vectorised) + the chain, extrapolated to K_full proposals per
     realization."""
@@ -263,7 +399,7 @@ def calib_copy(mib):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rbim64")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
@@ -271,6 +407,15 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serial", action="store_true",
+                    help="run the steps one after the other on one stream (default: consecutive "
+                         "steps overlap on two streams, the build of step t+1 during the "
+                         "proposals of step t, with double-buffered environments)")
+    ap.add_argument("--no-serial", action="store_true",
+                    help="skip the serial comparison run")
+    ap.add_argument("--reserve-cus", type=int, default=1, choices=[0, 1],
+                    help="overlapped steps: keep 8 CUs of every XCD free of proposal work for the "
+                         "concurrent build (0: no CU mask)")
     ap.add_argument("--graph", action="store_true",
                     help="capture the whole step in one HIP graph and time its replays (phase "
                          "times then come from the eager warm-up steps)")
@@ -283,7 +428,16 @@ def main():
               "batch are independent, so N GPUs would each run their own share; this "
               "benchmark measures one GPU's share.", file=sys.stderr)
         sys.exit(2)
-    res = run_gpu(args)
+    serial = args.serial or args.graph
+    res = run_gpu(args) if serial else run_gpu_pipelined(args)
+    if not serial and not args.no_serial:
+        # the same steps one after the other on one stream, for comparison
+        import copy
+        a2 = copy.copy(args)
+        a2.steps, a2.warmup = 3, 1
+        r2 = run_gpu(a2)
+        res["serial"] = {"value": r2["value"], "ms_per_step": r2["ms_per_step"], "steps": 3,
+                         "build_ms": r2["build_ms"], "propose_ms": r2["propose_ms"]}
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
     uniform = len(res["Ls"]) == 1
@@ -310,15 +464,20 @@ def main():
         "config": {"workload": f"{args.workload}: {res['n']} realizations of the {size} open "
                                f"+-J lattice, p={res['p']}, Nishimori beta, chi={res['chi']}, "
                                f"{res['K']} proposals each, {args.precision} batched"
-                               + (", one HIP graph per step" if res["graph"] else ""),
+                               + (", one HIP graph per step" if res["graph"] else "")
+                               + (", consecutive steps overlapped on two streams (build of step "
+                                  "t+1 during the proposals of step t)" if res.get("pipelined")
+                                  else ""),
                    "L": L0 if uniform else res["Ls"], "chi": res["chi"], "realizations": res["n"],
                    "proposals": res["K"], "p": res["p"], "precision": args.precision,
-                   "graph": res["graph"]},
+                   "graph": res["graph"], "pipelined": bool(res.get("pipelined")),
+                   "propose_cu_mask": res.get("propose_cu_mask")},
         "acceptance": res["acceptance"],
         "accepted": res["accepted"],
         "attempted": res["attempted"],
         "build_ms": res["build_ms"],
         "propose_ms": res["propose_ms"],
+        "serial": res.get("serial"),
         "fp64_plain": plain,
         "roofline": res["roofline"],
         "roofline_propose": res["roofline_propose"],

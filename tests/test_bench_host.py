@@ -1,0 +1,26 @@
+"""Host logic of bench.py: workload sizes and the CU mask that keeps CUs free for the build."""
+from collections import Counter
+
+import bench
+import synth
+
+
+def test_reserved_cu_bits_spread_under_each_layout():
+    words = 8                                  # 256 CUs
+    bits = [32 * w + b for w in range(words) for b in bench.reserved_cu_bits(w)]
+    assert len(bits) == len(set(bits)) == 64
+    # CUs enumerated XCD by XCD (32 each), shader engines by byte or interleaved mod 4
+    assert Counter(i // 32 for i in bits) == Counter({x: 8 for x in range(8)})
+    assert set(Counter((i // 32, (i % 32) // 8) for i in bits).values()) == {2}
+    assert set(Counter((i // 32, (i % 32) % 4) for i in bits).values()) == {2}
+    # CUs interleaved across the 8 XCDs, shader engines by byte of the per-XCD index
+    assert Counter(i % 8 for i in bits) == Counter({x: 8 for x in range(8)})
+    assert set(Counter((i % 8, (i // 8) % 4) for i in bits).values()) == {2}
+
+
+def test_workload_sizes():
+    Ls, seeds = bench.workload_sizes(synth.WORKLOADS["mixed"])
+    assert len(Ls) == len(seeds) == 256
+    assert Ls[:5] == [32, 64, 128, 256, 32]
+    Ls, seeds = bench.workload_sizes(synth.WORKLOADS["rbim64"])
+    assert Ls == [64] * 64 and seeds == list(range(64))

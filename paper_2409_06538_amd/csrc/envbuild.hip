@@ -113,7 +113,8 @@ struct EnvSmem {
                                      ? size_t(2) * CHI * LDA_S : size_t(CHI) * LDV;
   static constexpr size_t stage = size_t(2) * CHI * (CHI + 2);   // next site of E_r
   static constexpr size_t reals = bufA + bufR + bufS + stage + 4 * N2 + 2 * NW + NT / 64 + 8;
-  static constexpr size_t ints = 3 * N2 + 2 * NW + 8 + 1024;
+  // + 1024 exponents of the carried factors, + 2 x 1028 bytes of bond dimensions
+  static constexpr size_t ints = 3 * N2 + 2 * NW + 8 + 1024 + 2 * 1028 / 4;
   static constexpr size_t bytes = reals * sizeof(T) + ints * sizeof(int);
 };
 
@@ -337,10 +338,12 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
 // barrier per pair: with rows a and c = a+1 as they stand at the start of the step,
 // c' = c - (<c,a>/<a,a>) a, and every later row b subtracts its projections on a and c', formed
 // from <b,a>, <b,c>, <a,a>, <c,a>, <c,c>.  Rows whose residual norm^2 falls below eta are set to
-// zero; the rows are normalised at the end.
-template <typename T, int CHI, int NT, int LDVR>
+// zero; the rows are normalised at the end.  Only the 2 KW columns (x, be < KW), at x CHI + be,
+// take part (the others are zero).
+template <typename T, int CHI, int NT, int LDVR, int KW = CHI>
 __device__ void mgs_pairs_rows(T* V, int k, T eta) {
-  constexpr int N2 = 2 * CHI, TPP = env_tpp(CHI), EPR = (N2 + TPP - 1) / TPP;
+  constexpr int N2 = 2 * KW, TPP = env_tpp(CHI), EPR = (N2 + TPP - 1) / TPP;
+  auto col = [](int j) { return (j / KW) * CHI + j % KW; };
   const int grp = threadIdx.x / TPP, l = threadIdx.x % TPP;
   const bool mine = grp < k;
   T vb[EPR];
@@ -348,7 +351,7 @@ __device__ void mgs_pairs_rows(T* V, int k, T eta) {
 #pragma unroll
   for (int e = 0; e < EPR; ++e) {
     const int j = l + TPP * e;
-    vb[e] = (mine && j < N2) ? V[grp * LDVR + j] : T(0);
+    vb[e] = (mine && j < N2) ? V[grp * LDVR + col(j)] : T(0);
   }
   for (int a = 0; a < k; a += 2) {
     const int c = a + 1;
@@ -358,7 +361,7 @@ __device__ void mgs_pairs_rows(T* V, int k, T eta) {
 #pragma unroll
     for (int e = 0; e < EPR; ++e) {
       const int j = l + TPP * e;
-      const int jj = j < N2 ? j : 0;
+      const int jj = col(j < N2 ? j : 0);
       const T ra = V[a * LDVR + jj], rc = V[(pair ? c : a) * LDVR + jj];
       va[e] = (j < N2) ? ra : T(0);
       vc[e] = (pair && j < N2) ? rc : T(0);
@@ -386,7 +389,7 @@ __device__ void mgs_pairs_rows(T* V, int k, T eta) {
       for (int e = 0; e < EPR; ++e) {
         const int j = l + TPP * e;
         vb[e] -= ca * va[e] + fc * vc[e];
-        if (j < N2) V[grp * LDVR + j] = vb[e];
+        if (j < N2) V[grp * LDVR + col(j)] = vb[e];
       }
     }
     if (mine && grp == c) {
@@ -394,7 +397,7 @@ __device__ void mgs_pairs_rows(T* V, int k, T eta) {
       for (int e = 0; e < EPR; ++e) {
         const int j = l + TPP * e;
         vb[e] = cok ? vb[e] - g * va[e] : T(0);
-        if (j < N2) V[grp * LDVR + j] = vb[e];
+        if (j < N2) V[grp * LDVR + col(j)] = vb[e];
       }
     }
     if (mine && grp == a && !aok) {
@@ -412,7 +415,7 @@ __device__ void mgs_pairs_rows(T* V, int k, T eta) {
   for (int e = 0; e < EPR; ++e) {
     const int j = l + TPP * e;
     vb[e] *= f;
-    if (mine && j < N2) V[grp * LDVR + j] = vb[e];
+    if (mine && j < N2) V[grp * LDVR + col(j)] = vb[e];
   }
   __syncthreads();
 }
@@ -507,13 +510,23 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   int* candi = unpk + N2;                         // 2 x NW
   int* imisc = candi + 2 * NW;                    // 8
   int* rexp = imisc + 8;                          // exponents of the carried R_c (L <= 1024)
-  // perm[rank ..] = the columns never picked as pivots (unpk[col] = 1), ascending; wave w ranks
+  // bond dimensions of E_r (bdin) and of E_{r-1} (bdout, filled by the second sweep): entry c is
+  // the bond between sites c-1 and c; entries 0 and L are 1
+  unsigned char* bdin = reinterpret_cast<unsigned char*>(rexp + 1024);
+  unsigned char* bdout = bdin + 1028;
+  // Sites whose bonds are all at most KWS are processed on the KWS-wide part of every block
+  // (the rest is zero): the same arithmetic on a quarter of the entries and an eighth of the
+  // products.  The numerical-rank truncation keeps most bonds of the random-bond lattices well
+  // below chi.
+  constexpr int KWS = 16;
+  constexpr bool ADAPT = GRAM && MF64 && CHI > KWS && CHI <= 2 * KWS;
+  // perm[rank .. nk) = the columns < nk never picked as pivots (unpk[col] = 1), ascending; wave w ranks
   // columns 64 w .. 64 w + 63 by ballot, offset by the counts of the waves before it.
-  auto rank_unpicked = [&](int rk) {
+  auto rank_unpicked = [&](int rk, int nk) {
     constexpr int NWC = (2 * CHI + WAVE - 1) / WAVE;
     static_assert(NWC <= 8, "column-count slots");
     const int t = threadIdx.x, wi = t / WAVE, li = t % WAVE;
-    const bool un = t < 2 * CHI && unpk[t];
+    const bool un = t < nk && unpk[t];
     const unsigned long long mask = __ballot(un);
     if (li == 0 && wi < NWC) imisc[wi] = __popcll(mask);
     __syncthreads();
@@ -544,6 +557,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   }
   double lambda = 0.5 * double(L) * 0.69314718055994530942;
   if (tid == 0) R.lognorm[L - 1] = lambda;
+  for (int c = tid; c <= L; c += NT) {
+    bdin[c] = 1;
+    bdout[c] = 1;
+  }
 
   for (int r = L - 1; r >= 1; --r) {
     const E* Ain = env + size_t(r) * rowst;
@@ -630,42 +647,58 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) wh2[a][b] = bond_weight<T>(jh, c - 1, a, b, ep, em);
-          for (int o = tid; o < 4 * CHI * CHI; o += NT) {
-            const int blk = o / (CHI * CHI), al = (o / CHI) % CHI, al2 = o % CHI;
-            const int b = blk >> 1, b2 = blk & 1;
-            // (selects, not indexing with the runtime b: that would put the table in scratch)
-            const T w0b = gs * (b ? wh2[0][1] : wh2[0][0]), w1b = gs * (b ? wh2[1][1] : wh2[1][0]);
-            const T w0c = b2 ? wh2[0][1] : wh2[0][0], w1c = b2 ? wh2[1][1] : wh2[1][0];
-            const T g00 = gX[al * LDT + al2], g01 = gX[al * LDT + CHI + al2];
-            const T g10 = gX[(CHI + al) * LDT + al2], g11 = gX[(CHI + al) * LDT + CHI + al2];
-            gY[(blk * CHI + al) * LDC + al2] =
-                w0b * (w0c * g00 + w1c * g01) + w1b * (w0c * g10 + w1c * g11);
-            if (blk == 0) {   // the rescaled G_{c-1}, once per entry, for the second sweep
-              gdst[al * N2 + al2] = gs * g00;
-              gdst[al * N2 + CHI + al2] = gs * g01;
-              gdst[(CHI + al) * N2 + al2] = gs * g10;
-              gdst[(CHI + al) * N2 + CHI + al2] = gs * g11;
+          auto left_site = [&](auto kwc) {
+            constexpr int KW = decltype(kwc)::value;
+            for (int o = tid; o < 4 * KW * KW; o += NT) {
+              const int blk = o / (KW * KW), al = (o / KW) % KW, al2 = o % KW;
+              const int b = blk >> 1, b2 = blk & 1;
+              // (selects, not indexing with the runtime b: that would put the table in scratch)
+              const T w0b = gs * (b ? wh2[0][1] : wh2[0][0]), w1b = gs * (b ? wh2[1][1] : wh2[1][0]);
+              const T w0c = b2 ? wh2[0][1] : wh2[0][0], w1c = b2 ? wh2[1][1] : wh2[1][0];
+              const T g00 = gX[al * LDT + al2], g01 = gX[al * LDT + CHI + al2];
+              const T g10 = gX[(CHI + al) * LDT + al2], g11 = gX[(CHI + al) * LDT + CHI + al2];
+              gY[(blk * CHI + al) * LDC + al2] =
+                  w0b * (w0c * g00 + w1c * g01) + w1b * (w0c * g10 + w1c * g11);
+              if constexpr (KW == CHI) {
+                if (blk == 0) {   // the rescaled G_{c-1}, once per entry, for the second sweep
+                  gdst[al * N2 + al2] = gs * g00;
+                  gdst[al * N2 + CHI + al2] = gs * g01;
+                  gdst[(CHI + al) * N2 + al2] = gs * g10;
+                  gdst[(CHI + al) * N2 + CHI + al2] = gs * g11;
+                }
+              }
             }
-          }
-          __syncthreads();
-          if (c + 1 < L - 1) lpark();   // into the other buffer: As2 is read until the end of site c
-          if constexpr (MF64) {
-            // Q_bb' = P_bb' A_c[b'] (into gX), then G_c = kx A_c[b]^T Q_bb' (into gY)
-            mfma_gemm_f64_batched<4, CHI, CHI, CHI, NT>(
-                [&](int blk, int i, int k) { return gY[(blk * CHI + i) * LDC + k]; },
-                [&](int blk, int k, int j) { return As2[((blk & 1) * CHI + k) * LDC + j]; },
-                [&](int blk, int i, int j, T v) { gX[(blk * CHI + i) * LDC + j] = v; });
+            if constexpr (KW < CHI) {
+              // the whole rescaled G_{c-1} (zero outside its bonds) for the second sweep
+              for (int o = tid; o < N2 * N2; o += NT) gdst[o] = gs * gX[(o / N2) * LDT + o % N2];
+            }
             __syncthreads();
-            mfma_gemm_f64_batched<4, CHI, CHI, CHI, NT>(
-                [&](int blk, int i, int k) { return As2[((blk >> 1) * CHI + k) * LDC + i]; },
-                [&](int blk, int k, int j) { return gX[(blk * CHI + k) * LDC + j]; },
-                [&](int blk, int i, int j, T v) {
-                  const int b = blk >> 1, b2 = blk & 1;
-                  const T g = ((b == b2) ? kxd : kxo) * v;
-                  gY[(b * CHI + i) * LDT + b2 * CHI + j] = g;
-                  mx = fmax(mx, fabs(g));
-                });
-          } else {
+            if (c + 1 < L - 1) lpark();   // into the other buffer: As2 is read until the end of site c
+            if constexpr (MF64) {
+              // Q_bb' = P_bb' A_c[b'] (into gX), then G_c = kx A_c[b]^T Q_bb' (into gY)
+              mfma_gemm_f64_batched<4, KW, KW, KW, NT>(
+                  [&](int blk, int i, int k) { return gY[(blk * CHI + i) * LDC + k]; },
+                  [&](int blk, int k, int j) { return As2[((blk & 1) * CHI + k) * LDC + j]; },
+                  [&](int blk, int i, int j, T v) { gX[(blk * CHI + i) * LDC + j] = v; });
+              __syncthreads();
+              mfma_gemm_f64_batched<4, KW, KW, KW, NT>(
+                  [&](int blk, int i, int k) { return As2[((blk >> 1) * CHI + k) * LDC + i]; },
+                  [&](int blk, int k, int j) { return gX[(blk * CHI + k) * LDC + j]; },
+                  [&](int blk, int i, int j, T v) {
+                    const int b = blk >> 1, b2 = blk & 1;
+                    const T g = ((b == b2) ? kxd : kxo) * v;
+                    gY[(b * CHI + i) * LDT + b2 * CHI + j] = g;
+                    mx = fmax(mx, fabs(g));
+                  });
+              if constexpr (KW < CHI) {
+                // G_c is zero outside its bonds (at most KW): fill, so that a full-width next site
+                // reads zeros there
+                for (int o = tid; o < N2 * N2; o += NT) {
+                  const int i = o / N2, k = o % N2;
+                  if (i % CHI >= KW || k % CHI >= KW) gY[i * LDT + k] = T(0);
+                }
+              }
+            } else {
             // Q_bb' = P_bb' A_c[b'] (into gX)
             for (int t = tid; t < 4 * tmb * tmb; t += NT) {
               const int blk = t / (tmb * tmb), tt = t % (tmb * tmb);
@@ -725,8 +758,15 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
                   mx = fmax(mx, fabs(g));
                 }
             }
+            }
+          };
+          if constexpr (ADAPT) {
+            if (bdin[c] <= KWS && bdin[c + 1] <= KWS) left_site(std::integral_constant<int, KWS>{});
+            else left_site(std::integral_constant<int, CHI>{});
+          } else {
+            left_site(std::integral_constant<int, CHI>{});
           }
-          }
+        }
         if (c == 0 && L > 2) lpark();
         mx = wave_max(mx);
         if ((tid & (WAVE - 1)) == 0) red[tid / WAVE] = mx;
@@ -897,459 +937,498 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
 #pragma unroll
         for (int b = 0; b < 2; ++b)
           wh[a][b] = xsc * ((c > 0) ? bond_weight<T>(jh, c - 1, a, b, ep, em) : (a == 0 ? T(1) : T(0)));
-      // Z[(a,al)][(x,be)] = sum_b wh(a,b) wv(x,b) (A_c[b] Xt_b)[al][be]
-      if constexpr (MF64) {
-        // both products of an output tile on 16x16x4 FP64 matrix-core tiles, combined in registers
-        typedef double v4d __attribute__((ext_vector_type(4)));
-        constexpr int TT = CHI / 16;
-        const int lane = tid & 63, wvi = tid >> 6, i16 = lane & 15, qg = lane >> 4;
-        for (int t = wvi; t < TT * TT; t += NW) {
-          const int r0 = (t % TT) * 16, c0 = (t / TT) * 16;
-          v4d p0 = {0.0, 0.0, 0.0, 0.0}, p1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-          for (int k0 = 0; k0 < CHI; k0 += 4) {
-            const int k = k0 + qg;
-            const double a0 = bufS[(r0 + i16) * LDA_S + k], a1 = bufS[(CHI + r0 + i16) * LDA_S + k];
-            const double x0 = bufR[(c0 + i16) * LDT + k], x1 = bufR[(c0 + i16) * LDT + CHI + k];
-            p0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, p0, 0, 0, 0);
-            p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, p1, 0, 0, 0);
-          }
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            const int al = r0 + qg + 4 * rr, be = c0 + i16;
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-              for (int x = 0; x < 2; ++x)
-                Zr[(a * CHI + al) * LDZ + x * CHI + be] =
-                    wh[a][0] * wv[x][0] * p0[rr] + wh[a][1] * wv[x][1] * p1[rr];
-          }
-        }
-      } else
-      {
-        constexpr int tm = CHI / TL;
-        for (int t = tid; t < tm * tm; t += NT) {
-          const int al0 = (t % tm) * TL, be0 = (t / tm) * TL;
-          T p0[TL][TL], p1[TL][TL];
-#pragma unroll
-          for (int u = 0; u < TL; ++u)
-#pragma unroll
-            for (int v = 0; v < TL; ++v) { p0[u][v] = T(0); p1[u][v] = T(0); }
-#pragma unroll 8
-          for (int ap = 0; ap < CHI; ++ap) {
-            T a0[TL], a1[TL], x0[TL], x1[TL];
-#pragma unroll
-            for (int u = 0; u < TL; ++u) {
-              a0[u] = bufS[(al0 + u) * LDA_S + ap];
-              a1[u] = bufS[(CHI + al0 + u) * LDA_S + ap];
-              x0[u] = bufR[(be0 + u) * LDT + ap];
-              x1[u] = bufR[(be0 + u) * LDT + CHI + ap];
-            }
-#pragma unroll
-            for (int u = 0; u < TL; ++u)
-#pragma unroll
-              for (int v = 0; v < TL; ++v) {
-                p0[u][v] += a0[u] * x0[v];
-                p1[u][v] += a1[u] * x1[v];
-              }
-          }
-#pragma unroll
-          for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int x = 0; x < 2; ++x) {
-              const T f0 = wh[a][0] * wv[x][0], f1 = wh[a][1] * wv[x][1];
-#pragma unroll
-              for (int u = 0; u < TL; ++u)
-#pragma unroll
-                for (int v = 0; v < TL; ++v)
-                  Zr[(a * CHI + al0 + u) * LDZ + x * CHI + be0 + v] = f0 * p0[u][v] + f1 * p1[u][v];
-            }
-        }
-      }
-      __syncthreads();
-      if (c > 0) park_site();   // bufS and Astage are not read again during site c
-      if (c == 0) {
-        // site 0: left bond (a = 0, alpha = 0): A_0[x][0][be] = Z[(0,0)][(x,be)]
-        T part = 0;
-        for (int o = tid; o < 2 * CHI; o += NT) {
-          const T d = Zr[o];
-          sc[o] = d;
-          part += d * d;
-        }
-        const T nrm2 = block_sum<NT>(part, red);
-        const T nrm = sqrt(nrm2);
-        for (int o = tid; o < int(site); o += NT) {
-          const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
-          Aout[o] = narrow<E>((al == 0 && nrm > T(0)) ? sc[x * CHI + be] / nrm : T(0));
-        }
-        lambda += double(log2acc) * 0.69314718055994530942 + log(double(nrm));
-        if (tid == 0) R.lognorm[r - 1] = lambda;
-        break;
-      }
-      int rank = N2;
-      T fro2 = 0;
-      if constexpr (GRAM) {
-        // H = Z^T G_{c-1} Z (row-major in bufR), via W = G_{c-1} Z (in Tw).  Rounding leaves H
-        // slightly asymmetric; the factorisation reads its columns only.
-#pragma unroll
-        for (int t = 0; t < GPT; ++t) {
-          const int o = tid + NT * t;
-          if ((N2 * N2) % NT == 0 || o < N2 * N2) bufR[(o / N2) * LDT + (o % N2)] = gpf[t];
-        }
-        __syncthreads();
-        auto ga = [&](int i, int k) { return bufR[i * LDT + k]; };
-        auto gb = [&](int k, int col) { return Zr[k * LDZ + col]; };
-        auto gc = [&](int i, int col, T v) { Tw[i * LDT + col] = v; };
-        auto ha = [&](int c1, int i) { return Zr[i * LDZ + c1]; };
-        auto hb = [&](int i, int c2) { return Tw[i * LDT + c2]; };
-        auto hc = [&](int c1, int c2, T v) { bufR[c1 * LDT + c2] = v; };
-        if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ga, gb, gc);
-        else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ga, gb, gc);
-        __syncthreads();
+      // Sites whose bonds (both of site c of E_r, and the right bond of site c of E_{r-1}) are at
+      // most KWS run on the KWS-wide part of every block.  Z, W, H and the Cholesky factor are
+      // then stored compactly (index (s, al) at s KW + al); the site of E_{r-1}, V and Xt_c keep the
+      // full layout, zero outside the bonds.  Returns true after site 0 (end of the row).
+      auto right_site = [&](auto kwc) -> bool {
+        constexpr int KW = decltype(kwc)::value, NK = 2 * KW;
+        auto phys = [](int u) { return (u / KW) * CHI + u % KW; };
+        // Z[(a,al)][(x,be)] = sum_b wh(a,b) wv(x,b) (A_c[b] Xt_b)[al][be]
         if constexpr (MF64) {
-          // H is symmetric: the tiles on and above the diagonal, each mirrored below
+          // both products of an output tile on 16x16x4 FP64 matrix-core tiles, combined in registers
           typedef double v4d __attribute__((ext_vector_type(4)));
-          constexpr int TH = N2 / 16, NTILE = TH * (TH + 1) / 2;
+          constexpr int TT = KW / 16;
           const int lane = tid & 63, wvi = tid >> 6, i16 = lane & 15, qg = lane >> 4;
-          for (int t = wvi; t < NTILE; t += NW) {
-            int ti = 0, rem = t;
-            while (rem >= TH - ti) { rem -= TH - ti; ++ti; }
-            const int tj = ti + rem;
-            const int r0 = ti * 16, c0 = tj * 16;
-            v4d acc = {0.0, 0.0, 0.0, 0.0};
-            for (int k0 = 0; k0 < N2; k0 += 16) {
-              double a[4], b[4];
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                a[u] = ha(r0 + i16, k0 + 4 * u + qg);
-                b[u] = hb(k0 + 4 * u + qg, c0 + i16);
-              }
-#pragma unroll
-              for (int u = 0; u < 4; ++u)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+          for (int t = wvi; t < TT * TT; t += NW) {
+            const int r0 = (t % TT) * 16, c0 = (t / TT) * 16;
+            v4d p0 = {0.0, 0.0, 0.0, 0.0}, p1 = {0.0, 0.0, 0.0, 0.0};
+  #pragma unroll
+            for (int k0 = 0; k0 < KW; k0 += 4) {
+              const int k = k0 + qg;
+              const double a0 = bufS[(r0 + i16) * LDA_S + k], a1 = bufS[(CHI + r0 + i16) * LDA_S + k];
+              const double x0 = bufR[(c0 + i16) * LDT + k], x1 = bufR[(c0 + i16) * LDT + CHI + k];
+              p0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, x0, p0, 0, 0, 0);
+              p1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, x1, p1, 0, 0, 0);
             }
-#pragma unroll
+  #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-              const int i = r0 + qg + 4 * rr, j = c0 + i16;
-              bufR[i * LDT + j] = acc[rr];
-              if (ti != tj) bufR[j * LDT + i] = acc[rr];
+              const int al = r0 + qg + 4 * rr, be = c0 + i16;
+  #pragma unroll
+              for (int a = 0; a < 2; ++a)
+  #pragma unroll
+                for (int x = 0; x < 2; ++x)
+                  Zr[(a * KW + al) * LDZ + x * KW + be] =
+                      wh[a][0] * wv[x][0] * p0[rr] + wh[a][1] * wv[x][1] * p1[rr];
             }
           }
-        } else {
-          gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ha, hb, hc);
-        }
-        __syncthreads();
-        // ---- pivoted Cholesky of H, stopping at the numerical rank: H[p, p] = L L^T ----
-        // One wavefront, lane a = row a (2 CHI <= 64), so the loop needs no workgroup barrier.
-        // Left-looking: with p_j the row of largest remaining diagonal d,
-        //   L[a][j] = (H[a][p_j] - sum_{i<j} L[a][i] L[p_j][i]) / sqrt(d[p_j]),  d[a] -= L[a][j]^2;
-        // row j of L^T (natural column order) goes to Tw.  The pivot comes from one unsigned wave
-        // maximum over keys (float bits of d with the low 6 bits = 63 - row: larger d first, to
-        // 2^-17 relative, ties to the smaller row); its exact d by readlane.  Within one wavefront
-        // LDS operations complete in order, so the rows of L^T written at step i are visible to
-        // every lane at later steps.
-        static_assert(N2 <= WAVE, "one wavefront holds every row");
-        if (tid < WAVE) {
-          const int a = tid;
-          const bool live = a < N2;
-          T d = live ? bufR[a * LDT + a] : T(0);
-          const T f2 = wave_sum(live ? fmax(d, T(0)) : T(0));
-          const T tol2 = T(Tol::rank) * T(Tol::rank) * f2;
-          bool pkd = !live;
-          int rk = N2;
-          for (int j = 0; j < N2; ++j) {
-            const uint32_t key =
-                pkd ? 0u : ((__float_as_uint(float(fmax(d, T(0)))) & ~63u) | uint32_t(63 - a));
-            const uint32_t bk = wave_max_u32(key);
-            const int piv = 63 - int(bk & 63u);
-            const T best = readlane_v(d, piv);
-            if (bk == 0u || !(best > tol2)) { rk = j; break; }
-            // 1/sqrt(d) from the hardware estimate refined by two Newton steps
-            T inv = T(__builtin_amdgcn_rsq(double(best)));
-            inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
-            inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
-            const T sq = best * inv;
-            const T hap = bufR[a * LDT + piv];
-            // four rows per round, loads issued together (rows past j are clamped and masked)
-            T dot = 0;
-            for (int i0 = 0; i0 < j; i0 += 4) {
-              T x[4], y[4];
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int ii = (i0 + u < N2) ? i0 + u : N2 - 1;
-                x[u] = Tw[ii * LDT + a];
-                y[u] = Tw[ii * LDT + piv];
+        } else
+        {
+          constexpr int tm = CHI / TL;
+          for (int t = tid; t < tm * tm; t += NT) {
+            const int al0 = (t % tm) * TL, be0 = (t / tm) * TL;
+            T p0[TL][TL], p1[TL][TL];
+  #pragma unroll
+            for (int u = 0; u < TL; ++u)
+  #pragma unroll
+              for (int v = 0; v < TL; ++v) { p0[u][v] = T(0); p1[u][v] = T(0); }
+  #pragma unroll 8
+            for (int ap = 0; ap < CHI; ++ap) {
+              T a0[TL], a1[TL], x0[TL], x1[TL];
+  #pragma unroll
+              for (int u = 0; u < TL; ++u) {
+                a0[u] = bufS[(al0 + u) * LDA_S + ap];
+                a1[u] = bufS[(CHI + al0 + u) * LDA_S + ap];
+                x0[u] = bufR[(be0 + u) * LDT + ap];
+                x1[u] = bufR[(be0 + u) * LDT + CHI + ap];
               }
-#pragma unroll
-              for (int u = 0; u < 4; ++u) dot += (i0 + u < j) ? x[u] * y[u] : T(0);
+  #pragma unroll
+              for (int u = 0; u < TL; ++u)
+  #pragma unroll
+                for (int v = 0; v < TL; ++v) {
+                  p0[u][v] += a0[u] * x0[v];
+                  p1[u][v] += a1[u] * x1[v];
+                }
             }
-            const bool arow = !pkd && a != piv;
-            const T La = (a == piv) ? sq : (arow ? (hap - dot) * inv : T(0));
-            if (live) Tw[j * LDT + a] = La;
-            d -= arow ? La * La : T(0);
-            if (a == piv) pkd = true;
-            if (a == 0) perm[j] = piv;
-          }
-          if (live) unpk[a] = pkd ? 0 : 1;
-          if (a == 0) {
-            imisc[7] = rk;
-            misc[0] = f2;
+  #pragma unroll
+            for (int a = 0; a < 2; ++a)
+  #pragma unroll
+              for (int x = 0; x < 2; ++x) {
+                const T f0 = wh[a][0] * wv[x][0], f1 = wh[a][1] * wv[x][1];
+  #pragma unroll
+                for (int u = 0; u < TL; ++u)
+  #pragma unroll
+                  for (int v = 0; v < TL; ++v)
+                    Zr[(a * CHI + al0 + u) * LDZ + x * CHI + be0 + v] = f0 * p0[u][v] + f1 * p1[u][v];
+              }
           }
         }
         __syncthreads();
-        rank = imisc[7];
-        fro2 = misc[0];
-        rank_unpicked(rank);
-        // J = rows 0..rank-1 of L^T in pivoted column order (row-major in bufR, ld LDT)
-        const int nr = rank + (rank & 1);
-        for (int o = tid; o < nr * N2; o += NT) {
-          const int i = o / N2, kk = o % N2;
-          bufR[i * LDT + kk] = (i < rank) ? Tw[i * LDT + perm[kk]] : T(0);
+        if (c > 0) park_site();   // bufS and Astage are not read again during site c
+        if (c == 0) {
+          // site 0: left bond (a = 0, alpha = 0): A_0[x][0][be] = Z[(0,0)][(x,be)]
+          T part = 0;
+          for (int o = tid; o < 2 * CHI; o += NT) {
+            const T d = (o % CHI < KW) ? Zr[(o / CHI) * KW + o % CHI] : T(0);
+            sc[o] = d;
+            part += d * d;
+          }
+          const T nrm2 = block_sum<NT>(part, red);
+          const T nrm = sqrt(nrm2);
+          for (int o = tid; o < int(site); o += NT) {
+            const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
+            Aout[o] = narrow<E>((al == 0 && nrm > T(0)) ? sc[x * CHI + be] / nrm : T(0));
+          }
+          lambda += double(log2acc) * 0.69314718055994530942 + log(double(nrm));
+          if (tid == 0) R.lognorm[r - 1] = lambda;
+          return true;
         }
-        __syncthreads();
-      } else {
-        // R_{c-1} into bufR, then T = R_{c-1} Z
-        const T* rsrc = rs + size_t(c - 1) * N2 * N2;
-        for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = rsrc[o];
-        __syncthreads();
-        auto ta = [&](int i, int a) { return bufR[a * LDT + i]; };
-        auto tb = [&](int a, int col) { return Zr[a * LDZ + col]; };
-        auto tc = [&](int i, int col, T v) { Tw[col * LDT + i] = v; };
-        if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ta, tb, tc);
-        else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ta, tb, tc);
-        __syncthreads();
-
-        // ---- QR with column pivoting, stopping at the numerical rank ----
-        // Group g (TPC threads) owns physical column g; thread part keeps rows [part * RPT2, +RPT2)
-        // in registers and republishes them in Tw after each update, so that every thread reads the
-        // next pivot column from LDS and forms its reflector itself (one barrier per column).
-        constexpr int RPT2 = (N2 + TPC - 1) / TPC;
-        const int g = tid / TPC, part = tid % TPC, row0 = part * RPT2;
-        const bool owner = g < N2;
-        bool active = owner;
-        T mc[RPT2];
-        T cn = 0;
-        {
-          T cp[4] = {T(0), T(0), T(0), T(0)};
+        int rank = NK;
+        T fro2 = 0;
+        if constexpr (GRAM) {
+          // H = Z^T G_{c-1} Z (row-major in bufR), via W = G_{c-1} Z (in Tw).  Rounding leaves H
+          // slightly asymmetric; the factorisation reads its columns only.
   #pragma unroll
-          for (int t = 0; t < RPT2; ++t) {
-            const int rho = row0 + t;
-            mc[t] = (owner && rho < N2) ? Tw[g * LDT + rho] : T(0);
-            cp[t & 3] += mc[t] * mc[t];
+          for (int t = 0; t < GPT; ++t) {
+            const int o = tid + NT * t;
+            if ((N2 * N2) % NT == 0 || o < N2 * N2) bufR[(o / N2) * LDT + (o % N2)] = gpf[t];
           }
-          cn = group_sum<TPC>((cp[0] + cp[1]) + (cp[2] + cp[3]));
-        }
-        {
-          T bv = owner ? cn : T(-1);
-          int bi = owner ? g : N2;
-          wave_argmax(bv, bi);
-          if ((tid & (WAVE - 1)) == 0) { candv[tid / WAVE] = bv; candi[tid / WAVE] = bi; }
-        }
-        fro2 = block_sum<NT>((owner && part == 0) ? cn : T(0), red);
-        const T tolr2 = T(Tol::rank) * T(Tol::rank) * fro2;
-        rank = N2;
-        for (int j = 0; j < N2; ++j) {
-          const int buf = j & 1;
-          // arg-max of the per-wave candidates (ties -> smaller column), without branches
-          T cv[NW];
-          int ci[NW];
+          __syncthreads();
+          auto ga = [&](int i, int k) { return bufR[phys(i) * LDT + phys(k)]; };
+          auto gb = [&](int k, int col) { return Zr[k * LDZ + col]; };
+          auto gc = [&](int i, int col, T v) { Tw[i * LDT + col] = v; };
+          auto ha = [&](int c1, int i) { return Zr[i * LDZ + c1]; };
+          auto hb = [&](int i, int c2) { return Tw[i * LDT + c2]; };
+          auto hc = [&](int c1, int c2, T v) { bufR[c1 * LDT + c2] = v; };
+          if constexpr (MF64) mfma_gemm_f64<NK, NK, NK, NT>(ga, gb, gc);
+          else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ga, gb, gc);
+          __syncthreads();
+          if constexpr (MF64) {
+            // H is symmetric: the tiles on and above the diagonal, each mirrored below
+            typedef double v4d __attribute__((ext_vector_type(4)));
+            constexpr int TH = NK / 16, NTILE = TH * (TH + 1) / 2;
+            const int lane = tid & 63, wvi = tid >> 6, i16 = lane & 15, qg = lane >> 4;
+            for (int t = wvi; t < NTILE; t += NW) {
+              int ti = 0, rem = t;
+              while (rem >= TH - ti) { rem -= TH - ti; ++ti; }
+              const int tj = ti + rem;
+              const int r0 = ti * 16, c0 = tj * 16;
+              v4d acc = {0.0, 0.0, 0.0, 0.0};
+              for (int k0 = 0; k0 < NK; k0 += 16) {
+                double a[4], b[4];
   #pragma unroll
-          for (int w = 0; w < NW; ++w) {
-            cv[w] = candv[buf * NW + w];
-            ci[w] = candi[buf * NW + w];
-          }
-          T best = cv[0];
-          int piv = ci[0];
+                for (int u = 0; u < 4; ++u) {
+                  a[u] = ha(r0 + i16, k0 + 4 * u + qg);
+                  b[u] = hb(k0 + 4 * u + qg, c0 + i16);
+                }
   #pragma unroll
-          for (int w = 1; w < NW; ++w) {
-            const bool better = (cv[w] > best) | ((cv[w] == best) & (ci[w] < piv));
-            best = better ? cv[w] : best;
-            piv = better ? ci[w] : piv;
-          }
-          if (!(best > tolr2)) { rank = j; break; }
-          const T* pc = Tw + piv * LDT;
-          const T alpha = pc[j];
-          const T ss = fmax(best - alpha * alpha, T(0));
-          T tau = 0, beta = alpha, scal = 0;
-          if (ss > T(0)) hh_params(alpha, ss, beta, tau, scal);
-          if (tid == 0) { diag[j] = beta; perm[j] = piv; }
-          if (g == piv) active = false;
-          T v[RPT2];
-          T wp[4] = {T(0), T(0), T(0), T(0)};
-          // loads first and unconditional (a select on the loaded value would let the compiler
-          // move each load under its own branch and wait for it there)
+                for (int u = 0; u < 4; ++u)
+                  acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+              }
   #pragma unroll
-          for (int t = 0; t < RPT2; ++t) v[t] = pc[(N2 % TPC == 0 || row0 + t < N2) ? row0 + t : 0];
-  #pragma unroll
-          for (int t = 0; t < RPT2; ++t) {
-            const int rho = row0 + t;
-            const T sg = (rho > j && rho < N2) ? scal : T(0);
-            const T one = (rho == j) ? T(1) : T(0);
-            v[t] = v[t] * sg + one;
-            wp[t & 3] += v[t] * mc[t];
-          }
-          const T w = group_sum<TPC>((wp[0] + wp[1]) + (wp[2] + wp[3]));
-          T np[4] = {T(0), T(0), T(0), T(0)};
-          if (active) {
-            const T tw = tau * w;
-  #pragma unroll
-            for (int t = 0; t < RPT2; ++t) {
-              const int rho = row0 + t;
-              mc[t] -= tw * v[t];
-              np[t & 3] += (rho > j) ? mc[t] * mc[t] : T(0);
-              if (N2 % TPC == 0 || rho < N2) Tw[g * LDT + rho] = mc[t];
+              for (int rr = 0; rr < 4; ++rr) {
+                const int i = r0 + qg + 4 * rr, j = c0 + i16;
+                bufR[i * LDT + j] = acc[rr];
+                if (ti != tj) bufR[j * LDT + i] = acc[rr];
+              }
             }
+          } else {
+            gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ha, hb, hc);
           }
-          const T nn = group_sum<TPC>((np[0] + np[1]) + (np[2] + np[3]));
-          {
-            T bv = active ? nn : T(-1);
-            int bi = active ? g : N2;
-            wave_argmax(bv, bi);
-            if ((tid & (WAVE - 1)) == 0) {
-              candv[(buf ^ 1) * NW + tid / WAVE] = bv;
-              candi[(buf ^ 1) * NW + tid / WAVE] = bi;
+          __syncthreads();
+          // ---- pivoted Cholesky of H, stopping at the numerical rank: H[p, p] = L L^T ----
+          // One wavefront, lane a = row a (2 CHI <= 64), so the loop needs no workgroup barrier.
+          // Left-looking: with p_j the row of largest remaining diagonal d,
+          //   L[a][j] = (H[a][p_j] - sum_{i<j} L[a][i] L[p_j][i]) / sqrt(d[p_j]),  d[a] -= L[a][j]^2;
+          // row j of L^T (natural column order) goes to Tw.  The pivot comes from one unsigned wave
+          // maximum over keys (float bits of d with the low 6 bits = 63 - row: larger d first, to
+          // 2^-17 relative, ties to the smaller row); its exact d by readlane.  Within one wavefront
+          // LDS operations complete in order, so the rows of L^T written at step i are visible to
+          // every lane at later steps.
+          static_assert(NK <= WAVE, "one wavefront holds every row");
+          if (tid < WAVE) {
+            const int a = tid;
+            const bool live = a < NK;
+            T d = live ? bufR[a * LDT + a] : T(0);
+            const T f2 = wave_sum(live ? fmax(d, T(0)) : T(0));
+            const T tol2 = T(Tol::rank) * T(Tol::rank) * f2;
+            bool pkd = !live;
+            int rk = NK;
+            for (int j = 0; j < NK; ++j) {
+              const uint32_t key =
+                  pkd ? 0u : ((__float_as_uint(float(fmax(d, T(0)))) & ~63u) | uint32_t(63 - a));
+              const uint32_t bk = wave_max_u32(key);
+              const int piv = 63 - int(bk & 63u);
+              const T best = readlane_v(d, piv);
+              if (bk == 0u || !(best > tol2)) { rk = j; break; }
+              // 1/sqrt(d) from the hardware estimate refined by two Newton steps
+              T inv = T(__builtin_amdgcn_rsq(double(best)));
+              inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
+              inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
+              const T sq = best * inv;
+              const T hap = bufR[a * LDT + piv];
+              // four rows per round, loads issued together (rows past j are clamped and masked)
+              T dot = 0;
+              for (int i0 = 0; i0 < j; i0 += 4) {
+                T x[4], y[4];
+  #pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                  const int ii = (i0 + u < NK) ? i0 + u : NK - 1;
+                  x[u] = Tw[ii * LDT + a];
+                  y[u] = Tw[ii * LDT + piv];
+                }
+  #pragma unroll
+                for (int u = 0; u < 4; ++u) dot += (i0 + u < j) ? x[u] * y[u] : T(0);
+              }
+              const bool arow = !pkd && a != piv;
+              const T La = (a == piv) ? sq : (arow ? (hap - dot) * inv : T(0));
+              if (live) Tw[j * LDT + a] = La;
+              d -= arow ? La * La : T(0);
+              if (a == piv) pkd = true;
+              if (a == 0) perm[j] = piv;
+            }
+            if (live) unpk[a] = pkd ? 0 : 1;
+            if (a == 0) {
+              imisc[7] = rk;
+              misc[0] = f2;
             }
           }
           __syncthreads();
-        }
-        // columns never picked follow the pivots in ascending order
-        if (owner && part == 0) unpk[g] = active ? 1 : 0;
-        __syncthreads();
-        rank_unpicked(rank);
-        // J = rows 0..rank-1 of R in pivoted column order (row-major in bufR, ld LDT)
-        const int nr = rank + (rank & 1);
-        for (int o = tid; o < nr * N2; o += NT) {
-          const int i = o / N2, kk = o % N2;
-          T val = T(0);
-          if (i < rank) val = (kk > i) ? Tw[perm[kk] * LDT + i] : (kk == i ? diag[i] : T(0));
-          bufR[i * LDT + kk] = val;
-        }
-        __syncthreads();
-      }
-      const int nr = rank + (rank & 1);
+          rank = imisc[7];
+          fro2 = misc[0];
+          rank_unpicked(rank, NK);
+          // J = rows 0..rank-1 of L^T in pivoted column order (row-major in bufR, ld LDT)
+          const int nr = rank + (rank & 1);
+          for (int o = tid; o < nr * NK; o += NT) {
+            const int i = o / NK, kk = o % NK;
+            bufR[i * LDT + kk] = (i < rank) ? Tw[i * LDT + perm[kk]] : T(0);
+          }
+          __syncthreads();
+        } else {
+          // R_{c-1} into bufR, then T = R_{c-1} Z
+          const T* rsrc = rs + size_t(c - 1) * N2 * N2;
+          for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = rsrc[o];
+          __syncthreads();
+          auto ta = [&](int i, int a) { return bufR[a * LDT + i]; };
+          auto tb = [&](int a, int col) { return Zr[a * LDZ + col]; };
+          auto tc = [&](int i, int col, T v) { Tw[col * LDT + i] = v; };
+          if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ta, tb, tc);
+          else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ta, tb, tc);
+          __syncthreads();
 
-      // ---- one-sided Jacobi on the rows of J, parallel round-robin ordering ----
-      // Needed only when the numerical rank exceeds CHI: otherwise every direction is kept, and
-      // the span of the rows of J (what site c of E_{r-1} depends on) is already final.
-      if (nr >= 2 && rank > CHI) {
-        const T tol = T(Tol::rot) * sqrt(fro2);
-        const int gj = tid / TPP, l = tid % TPP;
-        const int npair = nr / 2;
-        for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
-          int rotated = 0;
-          for (int rd = 0; rd < nr - 1; ++rd) {
-            if (gj < npair) {
-              int p, q;
-              if (gj == 0) { p = nr - 1; q = rd; }
-              else { p = (rd + gj) % (nr - 1); q = (rd - gj + nr - 1) % (nr - 1); }
-              T xp[EPT], xq[EPT];
-              T a = 0, b = 0, cc = 0;
-#pragma unroll
-              for (int e = 0; e < EPT; ++e) {
-                const int k = l + TPP * e;
-                const int kc = (N2 % TPP == 0 || k < N2) ? k : 0;   // in bounds; masked below
-                xp[e] = bufR[p * LDT + kc];
-                xq[e] = bufR[q * LDT + kc];
+          // ---- QR with column pivoting, stopping at the numerical rank ----
+          // Group g (TPC threads) owns physical column g; thread part keeps rows [part * RPT2, +RPT2)
+          // in registers and republishes them in Tw after each update, so that every thread reads the
+          // next pivot column from LDS and forms its reflector itself (one barrier per column).
+          constexpr int RPT2 = (N2 + TPC - 1) / TPC;
+          const int g = tid / TPC, part = tid % TPC, row0 = part * RPT2;
+          const bool owner = g < N2;
+          bool active = owner;
+          T mc[RPT2];
+          T cn = 0;
+          {
+            T cp[4] = {T(0), T(0), T(0), T(0)};
+    #pragma unroll
+            for (int t = 0; t < RPT2; ++t) {
+              const int rho = row0 + t;
+              mc[t] = (owner && rho < N2) ? Tw[g * LDT + rho] : T(0);
+              cp[t & 3] += mc[t] * mc[t];
+            }
+            cn = group_sum<TPC>((cp[0] + cp[1]) + (cp[2] + cp[3]));
+          }
+          {
+            T bv = owner ? cn : T(-1);
+            int bi = owner ? g : N2;
+            wave_argmax(bv, bi);
+            if ((tid & (WAVE - 1)) == 0) { candv[tid / WAVE] = bv; candi[tid / WAVE] = bi; }
+          }
+          fro2 = block_sum<NT>((owner && part == 0) ? cn : T(0), red);
+          const T tolr2 = T(Tol::rank) * T(Tol::rank) * fro2;
+          rank = N2;
+          for (int j = 0; j < N2; ++j) {
+            const int buf = j & 1;
+            // arg-max of the per-wave candidates (ties -> smaller column), without branches
+            T cv[NW];
+            int ci[NW];
+    #pragma unroll
+            for (int w = 0; w < NW; ++w) {
+              cv[w] = candv[buf * NW + w];
+              ci[w] = candi[buf * NW + w];
+            }
+            T best = cv[0];
+            int piv = ci[0];
+    #pragma unroll
+            for (int w = 1; w < NW; ++w) {
+              const bool better = (cv[w] > best) | ((cv[w] == best) & (ci[w] < piv));
+              best = better ? cv[w] : best;
+              piv = better ? ci[w] : piv;
+            }
+            if (!(best > tolr2)) { rank = j; break; }
+            const T* pc = Tw + piv * LDT;
+            const T alpha = pc[j];
+            const T ss = fmax(best - alpha * alpha, T(0));
+            T tau = 0, beta = alpha, scal = 0;
+            if (ss > T(0)) hh_params(alpha, ss, beta, tau, scal);
+            if (tid == 0) { diag[j] = beta; perm[j] = piv; }
+            if (g == piv) active = false;
+            T v[RPT2];
+            T wp[4] = {T(0), T(0), T(0), T(0)};
+            // loads first and unconditional (a select on the loaded value would let the compiler
+            // move each load under its own branch and wait for it there)
+    #pragma unroll
+            for (int t = 0; t < RPT2; ++t) v[t] = pc[(N2 % TPC == 0 || row0 + t < N2) ? row0 + t : 0];
+    #pragma unroll
+            for (int t = 0; t < RPT2; ++t) {
+              const int rho = row0 + t;
+              const T sg = (rho > j && rho < N2) ? scal : T(0);
+              const T one = (rho == j) ? T(1) : T(0);
+              v[t] = v[t] * sg + one;
+              wp[t & 3] += v[t] * mc[t];
+            }
+            const T w = group_sum<TPC>((wp[0] + wp[1]) + (wp[2] + wp[3]));
+            T np[4] = {T(0), T(0), T(0), T(0)};
+            if (active) {
+              const T tw = tau * w;
+    #pragma unroll
+              for (int t = 0; t < RPT2; ++t) {
+                const int rho = row0 + t;
+                mc[t] -= tw * v[t];
+                np[t & 3] += (rho > j) ? mc[t] * mc[t] : T(0);
+                if (N2 % TPC == 0 || rho < N2) Tw[g * LDT + rho] = mc[t];
               }
-#pragma unroll
-              for (int e = 0; e < EPT; ++e) {
-                const T mk = (N2 % TPP == 0 || l + TPP * e < N2) ? T(1) : T(0);
-                xp[e] *= mk;
-                xq[e] *= mk;
-                a += xp[e] * xp[e];
-                b += xq[e] * xq[e];
-                cc += xp[e] * xq[e];
-              }
-              a = group_sum<TPP>(a);
-              b = group_sum<TPP>(b);
-              cc = group_sum<TPP>(cc);
-              if (a > T(0) && b > T(0) && cc * cc > tol * tol * fmax(a, b)) {
-                T cs, sn;
-                jacobi_rot(a, b, cc, cs, sn);
-#pragma unroll
-                for (int e = 0; e < EPT; ++e) {
-                  const int k = l + TPP * e;
-                  if (k < N2) {
-                    bufR[p * LDT + k] = cs * xp[e] - sn * xq[e];
-                    bufR[q * LDT + k] = sn * xp[e] + cs * xq[e];
-                  }
-                }
-                rotated = 1;
+            }
+            const T nn = group_sum<TPC>((np[0] + np[1]) + (np[2] + np[3]));
+            {
+              T bv = active ? nn : T(-1);
+              int bi = active ? g : N2;
+              wave_argmax(bv, bi);
+              if ((tid & (WAVE - 1)) == 0) {
+                candv[(buf ^ 1) * NW + tid / WAVE] = bv;
+                candi[(buf ^ 1) * NW + tid / WAVE] = bi;
               }
             }
             __syncthreads();
           }
-          if (!__syncthreads_or(rotated)) break;
-        }
-      }
-      // ---- row norms, descending order, kept rows (normalised) into V ----
-      {
-        const int gj = tid / TPP, l = tid % TPP;
-        for (int i0 = 0; i0 < N2; i0 += NT / TPP) {
-          const int i = i0 + gj;
-          T s2 = 0;
-#pragma unroll
-          for (int e = 0; e < EPT; ++e) {
-            const int k = l + TPP * e;
-            const T x = (i < rank && k < N2) ? bufR[i * LDT + k] : T(0);
-            s2 += x * x;
+          // columns never picked follow the pivots in ascending order
+          if (owner && part == 0) unpk[g] = active ? 1 : 0;
+          __syncthreads();
+          rank_unpicked(rank, NK);
+          // J = rows 0..rank-1 of R in pivoted column order (row-major in bufR, ld LDT)
+          const int nr = rank + (rank & 1);
+          for (int o = tid; o < nr * NK; o += NT) {
+            const int i = o / NK, kk = o % NK;
+            T val = T(0);
+            if (i < rank) val = (kk > i) ? Tw[perm[kk] * LDT + i] : (kk == i ? diag[i] : T(0));
+            bufR[i * LDT + kk] = val;
           }
-          s2 = group_sum<TPP>(s2);
-          if (l == 0 && i < N2) sc[i] = s2;
+          __syncthreads();
         }
-      }
-      __syncthreads();
-      for (int i = tid; i < rank; i += NT) {
-        int pos = i;
-        if (rank > CHI) {   // only the CHI largest are kept; otherwise any order will do
-          pos = 0;
-          for (int j2 = 0; j2 < rank; ++j2) pos += (sc[j2] > sc[i]) || (sc[j2] == sc[i] && j2 < i);
+        const int nr = rank + (rank & 1);
+
+        // ---- one-sided Jacobi on the rows of J, parallel round-robin ordering ----
+        // Needed only when the numerical rank exceeds CHI: otherwise every direction is kept, and
+        // the span of the rows of J (what site c of E_{r-1} depends on) is already final.
+        if (KW == CHI && nr >= 2 && rank > CHI) {
+          const T tol = T(Tol::rot) * sqrt(fro2);
+          const int gj = tid / TPP, l = tid % TPP;
+          const int npair = nr / 2;
+          for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+            int rotated = 0;
+            for (int rd = 0; rd < nr - 1; ++rd) {
+              if (gj < npair) {
+                int p, q;
+                if (gj == 0) { p = nr - 1; q = rd; }
+                else { p = (rd + gj) % (nr - 1); q = (rd - gj + nr - 1) % (nr - 1); }
+                T xp[EPT], xq[EPT];
+                T a = 0, b = 0, cc = 0;
+  #pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                  const int k = l + TPP * e;
+                  const int kc = (N2 % TPP == 0 || k < N2) ? k : 0;   // in bounds; masked below
+                  xp[e] = bufR[p * LDT + kc];
+                  xq[e] = bufR[q * LDT + kc];
+                }
+  #pragma unroll
+                for (int e = 0; e < EPT; ++e) {
+                  const T mk = (N2 % TPP == 0 || l + TPP * e < N2) ? T(1) : T(0);
+                  xp[e] *= mk;
+                  xq[e] *= mk;
+                  a += xp[e] * xp[e];
+                  b += xq[e] * xq[e];
+                  cc += xp[e] * xq[e];
+                }
+                a = group_sum<TPP>(a);
+                b = group_sum<TPP>(b);
+                cc = group_sum<TPP>(cc);
+                if (a > T(0) && b > T(0) && cc * cc > tol * tol * fmax(a, b)) {
+                  T cs, sn;
+                  jacobi_rot(a, b, cc, cs, sn);
+  #pragma unroll
+                  for (int e = 0; e < EPT; ++e) {
+                    const int k = l + TPP * e;
+                    if (k < N2) {
+                      bufR[p * LDT + k] = cs * xp[e] - sn * xq[e];
+                      bufR[q * LDT + k] = sn * xp[e] + cs * xq[e];
+                    }
+                  }
+                  rotated = 1;
+                }
+              }
+              __syncthreads();
+            }
+            if (!__syncthreads_or(rotated)) break;
+          }
         }
-        ord[pos] = i;
-      }
-      __syncthreads();
-      const int kept = rank < CHI ? rank : CHI;
-      for (int o = tid; o < CHI * N2; o += NT) {
-        const int al = o / N2, kk = o % N2;
-        T val = 0;
-        if (al < kept) {
-          const int row = ord[al];
-          const T s2 = sc[row];
-          if (s2 > T(0)) val = bufR[row * LDT + kk] / sqrt(s2);
+        // ---- row norms, descending order, kept rows (normalised) into V ----
+        {
+          const int gj = tid / TPP, l = tid % TPP;
+          for (int i0 = 0; i0 < N2; i0 += NT / TPP) {
+            const int i = i0 + gj;
+            T s2 = 0;
+  #pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+              const int k = l + TPP * e;
+              const T x = (i < rank && k < NK) ? bufR[i * LDT + k] : T(0);
+              s2 += x * x;
+            }
+            s2 = group_sum<TPP>(s2);
+            if (l == 0 && i < N2) sc[i] = s2;
+          }
         }
-        bufS[al * LDV + perm[kk]] = val;
+        __syncthreads();
+        for (int i = tid; i < rank; i += NT) {
+          int pos = i;
+          if (rank > CHI) {   // only the CHI largest are kept; otherwise any order will do
+            pos = 0;
+            for (int j2 = 0; j2 < rank; ++j2) pos += (sc[j2] > sc[i]) || (sc[j2] == sc[i] && j2 < i);
+          }
+          ord[pos] = i;
+        }
+        __syncthreads();
+        const int kept = rank < CHI ? rank : CHI;
+        if (tid == 0) bdout[c] = static_cast<unsigned char>(kept);
+        for (int o = tid; o < CHI * NK; o += NT) {
+          const int al = o / NK, kk = o % NK;
+          T val = 0;
+          if (al < kept) {
+            const int row = ord[al];
+            const T s2 = sc[row];
+            if (s2 > T(0)) val = bufR[row * LDT + kk] / sqrt(s2);
+          }
+          bufS[al * LDV + phys(perm[kk])] = val;
+        }
+        if constexpr (KW < CHI) {   // the columns (x, be >= KW) of V are zero
+          constexpr int NZ = 2 * (CHI - KW);
+          for (int o = tid; o < CHI * NZ; o += NT) {
+            const int al = o / NZ, z = o % NZ;
+            bufS[al * LDV + (z / (CHI - KW)) * CHI + KW + z % (CHI - KW)] = T(0);
+          }
+        }
+        // small kept rows are orthogonal to the large ones only up to rot ||T|| / sigma: make the
+        // kept rows orthonormal (span unchanged)
+        // One pass suffices in the Gram form: the rows come from a pivoted Cholesky factor whose
+        // conditioning is bounded by the FP32 rank tolerance, so FP64 Gram-Schmidt leaves them
+        // orthonormal to ~1e-10; FP64 environments need the second pass.
+        if constexpr (GRAM) mgs_pairs_rows<T, CHI, NT, LDV, KW>(bufS, kept, T(Tol::eta));
+        else mgs2_rows<T, CHI, NT, 2, LDV>(bufS, kept, T(Tol::eta));
+        E* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
+        for (int o = tid; o < int(site); o += NT) {
+          const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
+          bout[o] = narrow<E>(bufS[al * LDV + x * CHI + be]);
+        }
+        // Xt_c = 2^-e_{c-1} Z V^T (N2 x CHI, column-major in bufR), then a power-of-two rescale
+        const int ec = rexp[c - 1];
+        T mx = 0;
+        {
+          auto xa = [&](int j, int col) { return Zr[j * LDZ + col]; };
+          auto xb = [&](int col, int al) { return bufS[al * LDV + phys(col)]; };
+          auto xc = [&](int j, int al, T val) {
+            const T d = T(ldexp(val, -ec));
+            bufR[al * LDT + phys(j)] = d;
+            mx = fmax(mx, fabs(d));
+          };
+          if constexpr (KW < CHI) {   // the rows (a, al >= KW) of Xt_c are zero
+            constexpr int NZ = 2 * (CHI - KW);
+            for (int o = tid; o < CHI * NZ; o += NT) {
+              const int al = o / NZ, z = o % NZ;
+              bufR[al * LDT + (z / (CHI - KW)) * CHI + KW + z % (CHI - KW)] = T(0);
+            }
+          }
+          if constexpr (MF64) mfma_gemm_f64<NK, CHI, NK, NT>(xa, xb, xc);
+          else gemm_tiles<TL, TL, N2, NT, T>(N2, CHI, xa, xb, xc);
+        }
+        // the power-of-two rescale of Xt_c is applied to Z_{c-1} (per-wave maxima in red[])
+        mx = wave_max(mx);
+        if ((tid & (WAVE - 1)) == 0) red[tid / WAVE] = mx;
+        return false;
+      };
+      bool row_done;
+      if constexpr (ADAPT) {
+        if (bdin[c] <= KWS && bdin[c + 1] <= KWS && bdout[c + 1] <= KWS)
+          row_done = right_site(std::integral_constant<int, KWS>{});
+        else
+          row_done = right_site(std::integral_constant<int, CHI>{});
+      } else {
+        row_done = right_site(std::integral_constant<int, CHI>{});
       }
-      // small kept rows are orthogonal to the large ones only up to rot ||T|| / sigma: make the
-      // kept rows orthonormal (span unchanged)
-      // One pass suffices in the Gram form: the rows come from a pivoted Cholesky factor whose
-      // conditioning is bounded by the FP32 rank tolerance, so FP64 Gram-Schmidt leaves them
-      // orthonormal to ~1e-10; FP64 environments need the second pass.
-      if constexpr (GRAM) mgs_pairs_rows<T, CHI, NT, LDV>(bufS, kept, T(Tol::eta));
-      else mgs2_rows<T, CHI, NT, 2, LDV>(bufS, kept, T(Tol::eta));
-      E* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
-      for (int o = tid; o < int(site); o += NT) {
-        const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
-        bout[o] = narrow<E>(bufS[al * LDV + x * CHI + be]);
-      }
-      // Xt_c = 2^-e_{c-1} Z V^T (N2 x CHI, column-major in bufR), then a power-of-two rescale
-      const int ec = rexp[c - 1];
-      T mx = 0;
-      {
-        auto xa = [&](int j, int col) { return Zr[j * LDZ + col]; };
-        auto xb = [&](int col, int al) { return bufS[al * LDV + col]; };
-        auto xc = [&](int j, int al, T val) {
-          const T d = T(ldexp(val, -ec));
-          bufR[al * LDT + j] = d;
-          mx = fmax(mx, fabs(d));
-        };
-        if constexpr (MF64) mfma_gemm_f64<N2, CHI, N2, NT>(xa, xb, xc);
-        else gemm_tiles<TL, TL, N2, NT, T>(N2, CHI, xa, xb, xc);
-      }
-      // the power-of-two rescale of Xt_c is applied to Z_{c-1} (per-wave maxima in red[])
-      mx = wave_max(mx);
-      if ((tid & (WAVE - 1)) == 0) red[tid / WAVE] = mx;
+      if (row_done) break;
     }
     __syncthreads();
+    {   // the bonds of E_{r-1} are the input bonds of the next row
+      unsigned char* t = bdin;
+      bdin = bdout;
+      bdout = t;
+    }
   }
 
   // ---------------- ln Z_TN from the top row ----------------

@@ -538,7 +538,11 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     __syncthreads();
   };
 
-  const int tid = threadIdx.x;
+  // The thread index is re-issued at the top of every site (an empty asm that the compiler must
+  // assume redefines it), so addresses derived from it are recomputed per site instead of being
+  // hoisted out of the site loops and held in registers across them.
+  int tid = threadIdx.x;
+  auto fresh_tid = [&]() { asm volatile("" : "+v"(tid)); };
   const DevReal R = reals[blockIdx.x];
   const int L = R.L;
   const int W = words_per_row(L);
@@ -623,6 +627,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         Anx = tmp;
       }
       for (int c = 0; c < L - 1; ++c) {
+        fresh_tid();
         __syncthreads();
         if (c + 1 < L - 1) lfetch(c + 1);
         // kx(b,b') = sum_x wv(x,b) wv(x,b') = ep^2 + em^2 if b == b', 2 ep em otherwise, whatever
@@ -903,6 +908,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     fetch_site(L - 1);
     park_site();
     for (int c = L - 1; c >= 0; --c) {
+      fresh_tid();
       __syncthreads();
       for (int e = tid; e < int(site); e += NT) bufS[(e / CHI) * LDA_S + e % CHI] = Astage[e];
       if (c > 0) fetch_site(c - 1);
@@ -1104,6 +1110,38 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
             const T tol2 = T(Tol::rank) * T(Tol::rank) * f2;
             bool pkd = !live;
             int rk = NK;
+            if constexpr (KW < CHI) {
+              // Narrow sites: lane a keeps its row of L in registers, and the pivot row's entries
+              // come by readlane (wave-uniform lane), so no step waits on LDS for the dot product.
+              T Lr[NK];
+#pragma unroll
+              for (int j = 0; j < NK; ++j) {
+                const uint32_t key =
+                    pkd ? 0u : ((__float_as_uint(float(fmax(d, T(0)))) & ~63u) | uint32_t(63 - a));
+                const uint32_t bk = wave_max_u32(key);
+                const int piv = 63 - int(bk & 63u);
+                const T best = readlane_v(d, piv);
+                if (bk == 0u || !(best > tol2)) {
+                  rk = j;
+                  break;
+                }
+                const T hap = bufR[a * LDT + piv];
+                T inv = T(__builtin_amdgcn_rsq(double(best)));
+                inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
+                inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
+                const T sq = best * inv;
+                T dot = 0;
+#pragma unroll
+                for (int i = 0; i < j; ++i) dot += Lr[i] * readlane_v(Lr[i], piv);
+                const bool arow = !pkd && a != piv;
+                const T La = (a == piv) ? sq : (arow ? (hap - dot) * inv : T(0));
+                Lr[j] = La;
+                if (live) Tw[j * LDT + a] = La;
+                d -= arow ? La * La : T(0);
+                if (a == piv) pkd = true;
+                if (a == 0) perm[j] = piv;
+              }
+            } else
             for (int j = 0; j < NK; ++j) {
               const uint32_t key =
                   pkd ? 0u : ((__float_as_uint(float(fmax(d, T(0)))) & ~63u) | uint32_t(63 - a));

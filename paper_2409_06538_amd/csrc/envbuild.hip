@@ -112,7 +112,7 @@ struct EnvSmem {
   static constexpr size_t bufS = (size_t(2) * CHI * LDA_S > size_t(CHI) * LDV)
                                      ? size_t(2) * CHI * LDA_S : size_t(CHI) * LDV;
   static constexpr size_t stage = size_t(2) * CHI * (CHI + 2);   // next site of E_r
-  static constexpr size_t reals = bufA + bufR + bufS + stage + 4 * N2 + 2 * NW + NT / 64 + 8;
+  static constexpr size_t reals = bufA + bufR + bufS + stage + 4 * N2 + 2 * NW + 2 * NW + 8;
   // + 1024 exponents of the carried factors, + 2 x 1028 bytes of bond dimensions
   static constexpr size_t ints = 3 * N2 + 2 * NW + 8 + 1024 + 2 * 1028 / 4;
   static constexpr size_t bytes = reals * sizeof(T) + ints * sizeof(int);
@@ -340,12 +340,15 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
 // from <b,a>, <b,c>, <a,a>, <c,a>, <c,c>.  Rows whose residual norm^2 falls below eta are set to
 // zero; the rows are normalised at the end.  Only the 2 KW columns (x, be < KW), at x CHI + be,
 // take part (the others are zero).
-template <typename T, int CHI, int NT, int LDVR, int KW = CHI>
+template <typename T, int CHI, int NT, int LDVR, int KW = CHI, int TPP = env_tpp(CHI)>
 __device__ void mgs_pairs_rows(T* V, int k, T eta) {
-  constexpr int N2 = 2 * KW, TPP = env_tpp(CHI), EPR = (N2 + TPP - 1) / TPP;
+  constexpr int N2 = 2 * KW, EPR = (N2 + TPP - 1) / TPP;
+  static_assert(NT / TPP >= CHI, "a group of TPP threads for every row");
   auto col = [](int j) { return (j / KW) * CHI + j % KW; };
   const int grp = threadIdx.x / TPP, l = threadIdx.x % TPP;
   const bool mine = grp < k;
+  // wavefronts that hold no row only keep the barriers
+  const bool wave_live = (threadIdx.x / WAVE) * (WAVE / TPP) < k;
   T vb[EPR];
   __syncthreads();
 #pragma unroll
@@ -356,66 +359,70 @@ __device__ void mgs_pairs_rows(T* V, int k, T eta) {
   for (int a = 0; a < k; a += 2) {
     const int c = a + 1;
     const bool pair = c < k;
-    T va[EPR], vc[EPR];
-    T naa = 0, nca = 0, ncc = 0, dba = 0, dbc = 0;
-#pragma unroll
-    for (int e = 0; e < EPR; ++e) {
-      const int j = l + TPP * e;
-      const int jj = col(j < N2 ? j : 0);
-      const T ra = V[a * LDVR + jj], rc = V[(pair ? c : a) * LDVR + jj];
-      va[e] = (j < N2) ? ra : T(0);
-      vc[e] = (pair && j < N2) ? rc : T(0);
-      naa += va[e] * va[e];
-      nca += vc[e] * va[e];
-      ncc += vc[e] * vc[e];
-      dba += vb[e] * va[e];
-      dbc += vb[e] * vc[e];
-    }
-    naa = group_sum<TPP>(naa);
-    nca = group_sum<TPP>(nca);
-    ncc = group_sum<TPP>(ncc);
-    dba = group_sum<TPP>(dba);
-    dbc = group_sum<TPP>(dbc);
-    const bool aok = naa > eta;
-    const T ria = aok ? fast_rcp(naa) : T(0);
-    const T g = nca * ria;                  // c' = c - g a
-    const T ncp = ncc - g * nca;            // <c', c'>
-    const bool cok = pair && ncp > eta;
-    if (mine && grp > c) {
-      const T fa = dba * ria;
-      const T fc = cok ? (dbc - g * dba) * fast_rcp(ncp) : T(0);
-      const T ca = fa - fc * g;             // b -= fa a + fc c' = (fa - fc g) a + fc c
+    if (wave_live) {
+      T va[EPR], vc[EPR];
+      T naa = 0, nca = 0, ncc = 0, dba = 0, dbc = 0;
 #pragma unroll
       for (int e = 0; e < EPR; ++e) {
         const int j = l + TPP * e;
-        vb[e] -= ca * va[e] + fc * vc[e];
-        if (j < N2) V[grp * LDVR + col(j)] = vb[e];
+        const int jj = col(j < N2 ? j : 0);
+        const T ra = V[a * LDVR + jj], rc = V[(pair ? c : a) * LDVR + jj];
+        va[e] = (j < N2) ? ra : T(0);
+        vc[e] = (pair && j < N2) ? rc : T(0);
+        naa += va[e] * va[e];
+        nca += vc[e] * va[e];
+        ncc += vc[e] * vc[e];
+        dba += vb[e] * va[e];
+        dbc += vb[e] * vc[e];
       }
-    }
-    if (mine && grp == c) {
+      naa = group_sum<TPP>(naa);
+      nca = group_sum<TPP>(nca);
+      ncc = group_sum<TPP>(ncc);
+      dba = group_sum<TPP>(dba);
+      dbc = group_sum<TPP>(dbc);
+      const bool aok = naa > eta;
+      const T ria = aok ? fast_rcp(naa) : T(0);
+      const T g = nca * ria;                  // c' = c - g a
+      const T ncp = ncc - g * nca;            // <c', c'>
+      const bool cok = pair && ncp > eta;
+      if (mine && grp > c) {
+        const T fa = dba * ria;
+        const T fc = cok ? (dbc - g * dba) * fast_rcp(ncp) : T(0);
+        const T ca = fa - fc * g;             // b -= fa a + fc c' = (fa - fc g) a + fc c
 #pragma unroll
-      for (int e = 0; e < EPR; ++e) {
-        const int j = l + TPP * e;
-        vb[e] = cok ? vb[e] - g * va[e] : T(0);
-        if (j < N2) V[grp * LDVR + col(j)] = vb[e];
+        for (int e = 0; e < EPR; ++e) {
+          const int j = l + TPP * e;
+          vb[e] -= ca * va[e] + fc * vc[e];
+          if (j < N2) V[grp * LDVR + col(j)] = vb[e];
+        }
       }
-    }
-    if (mine && grp == a && !aok) {
+      if (mine && grp == c) {
 #pragma unroll
-      for (int e = 0; e < EPR; ++e) vb[e] = T(0);
+        for (int e = 0; e < EPR; ++e) {
+          const int j = l + TPP * e;
+          vb[e] = cok ? vb[e] - g * va[e] : T(0);
+          if (j < N2) V[grp * LDVR + col(j)] = vb[e];
+        }
+      }
+      if (mine && grp == a && !aok) {
+#pragma unroll
+        for (int e = 0; e < EPR; ++e) vb[e] = T(0);
+      }
     }
     __syncthreads();
   }
-  T n2 = 0;
+  if (wave_live) {
+    T n2 = 0;
 #pragma unroll
-  for (int e = 0; e < EPR; ++e) n2 += vb[e] * vb[e];
-  n2 = group_sum<TPP>(n2);
-  const T f = (n2 > T(0)) ? T(1) / sqrt(n2) : T(0);
+    for (int e = 0; e < EPR; ++e) n2 += vb[e] * vb[e];
+    n2 = group_sum<TPP>(n2);
+    const T f = (n2 > T(0)) ? T(1) / sqrt(n2) : T(0);
 #pragma unroll
-  for (int e = 0; e < EPR; ++e) {
-    const int j = l + TPP * e;
-    vb[e] *= f;
-    if (mine && j < N2) V[grp * LDVR + col(j)] = vb[e];
+    for (int e = 0; e < EPR; ++e) {
+      const int j = l + TPP * e;
+      vb[e] *= f;
+      if (mine && j < N2) V[grp * LDVR + col(j)] = vb[e];
+    }
   }
   __syncthreads();
 }
@@ -502,8 +509,8 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   T* sc = diag + N2;                // 2 N2 scalars scratch
   T* cnv = sc + 2 * N2;             // N2 (ss double buffer lives in its first 2 entries too)
   T* candv = cnv + N2;              // 2 x NW argmax candidates
-  T* red = candv + 2 * NW;          // NT/64
-  T* misc = red + NT / 64;          // 8
+  T* red = candv + 2 * NW;          // 2 x NW per-wave maxima (the left sweep alternates halves)
+  T* misc = red + 2 * NW;           // 8
   int* perm = reinterpret_cast<int*>(misc + 8);   // N2 logical -> physical column
   int* ord = perm + N2;                           // N2
   int* unpk = ord + N2;                           // N2: 1 = column not picked as a pivot
@@ -609,10 +616,13 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           }
         }
       };
+      // The per-wave maxima of G_cc are in half (cc & 1) of red[]: a site has no barrier after
+      // its reads of the previous half, so a wave that finishes early writes the other one.
       auto take_exponent = [&](int cc) {   // exponent of G_cc from the per-wave maxima
-        T m = red[0];
+        const T* rd = red + (cc & 1) * NW;
+        T m = rd[0];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) m = fmax(m, red[w]);
+        for (int w = 1; w < NW; ++w) m = fmax(m, rd[w]);
         const int e = (pow2_exponent(m) + 1) / 2;
         log2acc += e;
         if (tid == 0) rexp[cc] = e;
@@ -654,47 +664,64 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
             for (int b = 0; b < 2; ++b) wh2[a][b] = bond_weight<T>(jh, c - 1, a, b, ep, em);
           auto left_site = [&](auto kwc) {
             constexpr int KW = decltype(kwc)::value;
-            for (int o = tid; o < 4 * KW * KW; o += NT) {
-              const int blk = o / (KW * KW), al = (o / KW) % KW, al2 = o % KW;
-              const int b = blk >> 1, b2 = blk & 1;
-              // (selects, not indexing with the runtime b: that would put the table in scratch)
-              const T w0b = gs * (b ? wh2[0][1] : wh2[0][0]), w1b = gs * (b ? wh2[1][1] : wh2[1][0]);
-              const T w0c = b2 ? wh2[0][1] : wh2[0][0], w1c = b2 ? wh2[1][1] : wh2[1][0];
-              const T g00 = gX[al * LDT + al2], g01 = gX[al * LDT + CHI + al2];
-              const T g10 = gX[(CHI + al) * LDT + al2], g11 = gX[(CHI + al) * LDT + CHI + al2];
-              gY[(blk * CHI + al) * LDC + al2] =
-                  w0b * (w0c * g00 + w1c * g01) + w1b * (w0c * g10 + w1c * g11);
-              if constexpr (KW == CHI) {
-                if (blk == 0) {   // the rescaled G_{c-1}, once per entry, for the second sweep
-                  gdst[al * N2 + al2] = gs * g00;
-                  gdst[al * N2 + CHI + al2] = gs * g01;
-                  gdst[(CHI + al) * N2 + al2] = gs * g10;
-                  gdst[(CHI + al) * N2 + CHI + al2] = gs * g11;
-                }
-              }
-            }
-            if constexpr (KW < CHI) {
-              // the whole rescaled G_{c-1} (zero outside its bonds) for the second sweep
-              for (int o = tid; o < N2 * N2; o += NT) gdst[o] = gs * gX[(o / N2) * LDT + o % N2];
-            }
-            __syncthreads();
-            if (c + 1 < L - 1) lpark();   // into the other buffer: As2 is read until the end of site c
             if constexpr (MF64) {
-              // Q_bb' = P_bb' A_c[b'] (into gX), then G_c = kx A_c[b]^T Q_bb' (into gY)
-              mfma_gemm_f64_batched<4, KW, KW, KW, NT>(
-                  [&](int blk, int i, int k) { return gY[(blk * CHI + i) * LDC + k]; },
-                  [&](int blk, int k, int j) { return As2[((blk & 1) * CHI + k) * LDC + j]; },
-                  [&](int blk, int i, int j, T v) { gX[(blk * CHI + i) * LDC + j] = v; });
-              __syncthreads();
-              mfma_gemm_f64_batched<4, KW, KW, KW, NT>(
-                  [&](int blk, int i, int k) { return As2[((blk >> 1) * CHI + k) * LDC + i]; },
-                  [&](int blk, int k, int j) { return gX[(blk * CHI + k) * LDC + j]; },
-                  [&](int blk, int i, int j, T v) {
-                    const int b = blk >> 1, b2 = blk & 1;
-                    const T g = ((b == b2) ? kxd : kxo) * v;
+              // One wavefront per (b, b', column block of 16): P_bb' is formed from G_{c-1} as the
+              // operand of Q = P_bb' A_c[b'], and Q stays in the matrix-core accumulators, whose
+              // rows (q + 4 r of each lane group) are the rows the B operand of
+              // G_c = kx A_c[b]^T Q takes from each lane: no LDS round trip, no barrier.
+              typedef double v4d __attribute__((ext_vector_type(4)));
+              constexpr int TT = KW / 16;
+              const int lane = tid & (WAVE - 1), wvi = tid / WAVE, i16 = lane & 15, qg = lane >> 4;
+              // the rescaled G_{c-1} (zero outside its bonds) for the second sweep
+              for (int o = tid; o < N2 * N2; o += NT) gdst[o] = gs * gX[(o / N2) * LDT + o % N2];
+              if (wvi < 4 * TT) {
+                const int blk = wvi / TT, jb = wvi % TT;
+                const int b = blk >> 1, b2 = blk & 1;
+                const T w0b = gs * (b ? wh2[0][1] : wh2[0][0]), w1b = gs * (b ? wh2[1][1] : wh2[1][0]);
+                const T w0c = b2 ? wh2[0][1] : wh2[0][0], w1c = b2 ? wh2[1][1] : wh2[1][0];
+                v4d q[TT];
+#pragma unroll
+                for (int ib = 0; ib < TT; ++ib) {
+                  q[ib] = v4d{0.0, 0.0, 0.0, 0.0};
+                  const int al = ib * 16 + i16;
+#pragma unroll
+                  for (int kb = 0; kb < TT; ++kb) {
+                    double pa[4], ab[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                      const int al2 = kb * 16 + 4 * u + qg;
+                      const T g00 = gX[al * LDT + al2], g01 = gX[al * LDT + CHI + al2];
+                      const T g10 = gX[(CHI + al) * LDT + al2], g11 = gX[(CHI + al) * LDT + CHI + al2];
+                      pa[u] = w0b * (w0c * g00 + w1c * g01) + w1b * (w0c * g10 + w1c * g11);
+                      ab[u] = As2[(b2 * CHI + al2) * LDC + jb * 16 + i16];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                      q[ib] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[u], ab[u], q[ib], 0, 0, 0);
+                  }
+                }
+                const T f = (b == b2) ? kxd : kxo;
+#pragma unroll
+                for (int ib2 = 0; ib2 < TT; ++ib2) {
+                  v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                  for (int kb = 0; kb < TT; ++kb) {
+                    double at[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) at[u] = As2[(b * CHI + kb * 16 + 4 * u + qg) * LDC + ib2 * 16 + i16];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(at[u], q[kb][u], acc, 0, 0, 0);
+                  }
+#pragma unroll
+                  for (int r = 0; r < 4; ++r) {
+                    const int i = ib2 * 16 + qg + 4 * r, j = jb * 16 + i16;
+                    const T g = f * acc[r];
                     gY[(b * CHI + i) * LDT + b2 * CHI + j] = g;
                     mx = fmax(mx, fabs(g));
-                  });
+                  }
+                }
+              }
               if constexpr (KW < CHI) {
                 // G_c is zero outside its bonds (at most KW): fill, so that a full-width next site
                 // reads zeros there
@@ -703,7 +730,33 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
                   if (i % CHI >= KW || k % CHI >= KW) gY[i * LDT + k] = T(0);
                 }
               }
+              if (c + 1 < L - 1) lpark();   // into the other buffer (As2 is the current site)
             } else {
+              for (int o = tid; o < 4 * KW * KW; o += NT) {
+                const int blk = o / (KW * KW), al = (o / KW) % KW, al2 = o % KW;
+                const int b = blk >> 1, b2 = blk & 1;
+                // (selects, not indexing with the runtime b: that would put the table in scratch)
+                const T w0b = gs * (b ? wh2[0][1] : wh2[0][0]), w1b = gs * (b ? wh2[1][1] : wh2[1][0]);
+                const T w0c = b2 ? wh2[0][1] : wh2[0][0], w1c = b2 ? wh2[1][1] : wh2[1][0];
+                const T g00 = gX[al * LDT + al2], g01 = gX[al * LDT + CHI + al2];
+                const T g10 = gX[(CHI + al) * LDT + al2], g11 = gX[(CHI + al) * LDT + CHI + al2];
+                gY[(blk * CHI + al) * LDC + al2] =
+                    w0b * (w0c * g00 + w1c * g01) + w1b * (w0c * g10 + w1c * g11);
+                if constexpr (KW == CHI) {
+                  if (blk == 0) {   // the rescaled G_{c-1}, once per entry, for the second sweep
+                    gdst[al * N2 + al2] = gs * g00;
+                    gdst[al * N2 + CHI + al2] = gs * g01;
+                    gdst[(CHI + al) * N2 + al2] = gs * g10;
+                    gdst[(CHI + al) * N2 + CHI + al2] = gs * g11;
+                  }
+                }
+              }
+              if constexpr (KW < CHI) {
+                // the whole rescaled G_{c-1} (zero outside its bonds) for the second sweep
+                for (int o = tid; o < N2 * N2; o += NT) gdst[o] = gs * gX[(o / N2) * LDT + o % N2];
+              }
+              __syncthreads();
+              if (c + 1 < L - 1) lpark();   // into the other buffer: As2 is read until the end of site c
             // Q_bb' = P_bb' A_c[b'] (into gX)
             for (int t = tid; t < 4 * tmb * tmb; t += NT) {
               const int blk = t / (tmb * tmb), tt = t % (tmb * tmb);
@@ -763,7 +816,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
                   mx = fmax(mx, fabs(g));
                 }
             }
-            }
+                        }
           };
           if constexpr (ADAPT) {
             if (bdin[c] <= KWS && bdin[c + 1] <= KWS) left_site(std::integral_constant<int, KWS>{});
@@ -774,7 +827,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         }
         if (c == 0 && L > 2) lpark();
         mx = wave_max(mx);
-        if ((tid & (WAVE - 1)) == 0) red[tid / WAVE] = mx;
+        if ((tid & (WAVE - 1)) == 0) red[(c & 1) * NW + tid / WAVE] = mx;
         T* tmp = gX;
         gX = gY;
         gY = tmp;
@@ -1417,7 +1470,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         // One pass suffices in the Gram form: the rows come from a pivoted Cholesky factor whose
         // conditioning is bounded by the FP32 rank tolerance, so FP64 Gram-Schmidt leaves them
         // orthonormal to ~1e-10; FP64 environments need the second pass.
-        if constexpr (GRAM) mgs_pairs_rows<T, CHI, NT, LDV, KW>(bufS, kept, T(Tol::eta));
+        if constexpr (GRAM) mgs_pairs_rows<T, CHI, NT, LDV, KW, (KW < CHI ? 8 : TPP)>(bufS, kept, T(Tol::eta));
         else mgs2_rows<T, CHI, NT, 2, LDV>(bufS, kept, T(Tol::eta));
         E* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
         for (int o = tid; o < int(site); o += NT) {

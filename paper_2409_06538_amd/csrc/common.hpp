@@ -183,11 +183,41 @@ __device__ __forceinline__ T block_max(T v, T* red) {
   return s;
 }
 
+// Global-memory pointers.  A pointer read from memory (the realization table) is generic, and the
+// compiler then emits FLAT loads and stores, which count against the LDS wait counter as well: an
+// LDS wait would also wait for every outstanding global load or store, so a prefetch issued early
+// would stall the next LDS access.  Casting to the global address space gives global_load /
+// global_store, which count against the vector-memory counter only.
+template <typename T>
+using gmem = T __attribute__((address_space(1)));
+template <typename T>
+__device__ __forceinline__ gmem<T>* as_global(T* p) {
+  return (gmem<T>*)p;
+}
+
 // Environment storage types.  bfloat16 is the upper half of an IEEE binary32; narrowing rounds to
 // nearest, ties to even (NaN stays NaN).  Arithmetic always runs in the wider compute type.
 struct bf16_t {
   uint16_t bits;
 };
+
+// element loads and stores through global pointers (bfloat16 moves its 16 bits)
+template <typename E>
+__device__ __forceinline__ E gld(const gmem<E>* p, size_t i) {
+  return p[i];
+}
+template <>
+__device__ __forceinline__ bf16_t gld<bf16_t>(const gmem<bf16_t>* p, size_t i) {
+  return bf16_t{p[i].bits};
+}
+template <typename E>
+__device__ __forceinline__ void gst(gmem<E>* p, size_t i, E v) {
+  p[i] = v;
+}
+template <>
+__device__ __forceinline__ void gst<bf16_t>(gmem<bf16_t>* p, size_t i, bf16_t v) {
+  p[i].bits = v.bits;
+}
 
 __device__ __forceinline__ float widen(float v) { return v; }
 __device__ __forceinline__ double widen(double v) { return v; }

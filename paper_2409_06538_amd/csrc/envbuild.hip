@@ -118,9 +118,8 @@ struct EnvSmem {
   static constexpr size_t bytes = reals * sizeof(T) + ints * sizeof(int);
 };
 
-template <typename T>
-__device__ __forceinline__ T bond_weight(const uint64_t* row_bits, int c, int sa, int sb, T ep,
-                                         T em) {
+template <typename T, typename P>
+__device__ __forceinline__ T bond_weight(P row_bits, int c, int sa, int sb, T ep, T em) {
   // exp(beta J s_a s_b): J = -1 iff bit c is set; spin index 0 <-> +1, 1 <-> -1.
   const bool af = (row_bits[c >> 6] >> (c & 63)) & 1ull;
   const bool parallel = (sa == sb);
@@ -554,8 +553,9 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   const int L = R.L;
   const int W = words_per_row(L);
   const T ep = T(exp(R.beta)), em = T(exp(-R.beta));
-  E* env = reinterpret_cast<E*>(R.env);
-  T* rs = reinterpret_cast<T*>(R.ws);                 // L x N2 x N2 scratch: R_c column-major
+  gmem<E>* env = as_global(reinterpret_cast<E*>(R.env));
+  gmem<T>* rs = as_global(reinterpret_cast<T*>(R.ws));   // L x N2 x N2 scratch: R_c column-major
+  gmem<double>* lognorm = as_global(R.lognorm);
   const size_t site = size_t(2) * CHI * CHI;
   const size_t rowst = site * L;
   T* Zr = bufA;                                       // Z_c: N2 x N2 row-major, ld LDZ
@@ -564,20 +564,21 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   for (size_t e = tid; e < rowst; e += NT) {         // E_{L-1} = 1
     const size_t inner = e % site;
     const int a = int((inner % (CHI * CHI)) / CHI), b = int(inner % CHI);
-    env[size_t(L - 1) * rowst + e] = narrow<E>((a == 0 && b == 0) ? T(0.70710678118654752440) : T(0));
+    gst<E>(env, size_t(L - 1) * rowst + e,
+           narrow<E>((a == 0 && b == 0) ? T(0.70710678118654752440) : T(0)));
   }
   double lambda = 0.5 * double(L) * 0.69314718055994530942;
-  if (tid == 0) R.lognorm[L - 1] = lambda;
+  if (tid == 0) lognorm[L - 1] = lambda;
   for (int c = tid; c <= L; c += NT) {
     bdin[c] = 1;
     bdout[c] = 1;
   }
 
   for (int r = L - 1; r >= 1; --r) {
-    const E* Ain = env + size_t(r) * rowst;
-    E* Aout = env + size_t(r - 1) * rowst;
-    const uint64_t* jh = R.Jh + size_t(r) * W;        // horizontal bonds of row r
-    const uint64_t* jv = R.Jv + size_t(r - 1) * W;    // vertical bonds between rows r-1 and r
+    const gmem<E>* Ain = env + size_t(r) * rowst;
+    gmem<E>* Aout = env + size_t(r - 1) * rowst;
+    const gmem<const uint64_t>* jh = as_global(R.Jh) + size_t(r) * W;      // horizontal bonds of row r
+    const gmem<const uint64_t>* jv = as_global(R.Jv) + size_t(r - 1) * W;  // vertical bonds, rows r-1 and r
     long long log2acc = 0;
 
     if constexpr (GRAM) {
@@ -603,7 +604,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
 #pragma unroll
         for (int t = 0; t < SPT; ++t) {
           const int e = tid + NT * t;
-          if ((2 * CHI * CHI) % NT == 0 || e < int(site)) lpf[t] = Ain[size_t(cc) * site + e];
+          if ((2 * CHI * CHI) % NT == 0 || e < int(site)) lpf[t] = gld<E>(Ain, size_t(cc) * site + e);
         }
       };
       auto lpark = [&]() {
@@ -656,7 +657,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           }
         } else {
           const T gs = T(ldexp(T(1), -2 * take_exponent(c - 1)));
-          T* gdst = rs + size_t(c - 1) * N2 * N2;
+          gmem<T>* gdst = rs + size_t(c - 1) * N2 * N2;
           T wh2[2][2];
 #pragma unroll
           for (int a = 0; a < 2; ++a)
@@ -839,7 +840,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       __syncthreads();
       {
         const T gs = T(ldexp(T(1), -2 * take_exponent(L - 2)));
-        T* gdst = rs + size_t(L - 2) * N2 * N2;
+        gmem<T>* gdst = rs + size_t(L - 2) * N2 * N2;
         for (int o = tid; o < N2 * N2; o += NT) gdst[o] = gs * gX[(o / N2) * LDT + o % N2];
       }
     } else // ---------------- left to right: R factors ----------------
@@ -856,7 +857,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         __syncthreads();
         for (int e = tid; e < int(site); e += NT) {
           const int b = e / (CHI * CHI), al = (e / CHI) % CHI, ap = e % CHI;
-          AsT[(b * CHI + ap) * LDAT + al] = widen(Ain[size_t(c) * site + e]);
+          AsT[(b * CHI + ap) * LDAT + al] = widen(gld<E>(Ain, size_t(c) * site + e));
         }
         if (c > 0) {
           T wh2[2][2];   // wh2[a][b]
@@ -916,7 +917,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         const int e = pow2_exponent(mx);
         log2acc += e;
         if (tid == 0) rexp[c] = e;
-        T* rdst = rs + size_t(c) * N2 * N2 + size_t(g) * N2;
+        gmem<T>* rdst = rs + size_t(c) * N2 * N2 + size_t(g) * N2;
         const T dg = diag[g];
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
@@ -948,7 +949,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
 #pragma unroll
       for (int t = 0; t < SPT; ++t) {
         const int e = tid + NT * t;
-        if ((2 * CHI * CHI) % NT == 0 || e < int(site)) apf[t] = Ain[size_t(cc) * site + e];
+        if ((2 * CHI * CHI) % NT == 0 || e < int(site)) apf[t] = gld<E>(Ain, size_t(cc) * site + e);
       }
     };
     auto park_site = [&]() {
@@ -967,7 +968,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       if (c > 0) fetch_site(c - 1);
       if constexpr (GRAM) {
         if (c > 0) {
-          const T* gsrc = rs + size_t(c - 1) * N2 * N2;
+          const gmem<T>* gsrc = rs + size_t(c - 1) * N2 * N2;
 #pragma unroll
           for (int t = 0; t < GPT; ++t) {
             const int o = tid + NT * t;
@@ -1086,10 +1087,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           const T nrm = sqrt(nrm2);
           for (int o = tid; o < int(site); o += NT) {
             const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
-            Aout[o] = narrow<E>((al == 0 && nrm > T(0)) ? sc[x * CHI + be] / nrm : T(0));
+            gst<E>(Aout, o, narrow<E>((al == 0 && nrm > T(0)) ? sc[x * CHI + be] / nrm : T(0)));
           }
           lambda += double(log2acc) * 0.69314718055994530942 + log(double(nrm));
-          if (tid == 0) R.lognorm[r - 1] = lambda;
+          if (tid == 0) lognorm[r - 1] = lambda;
           return true;
         }
         int rank = NK;
@@ -1247,7 +1248,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           __syncthreads();
         } else {
           // R_{c-1} into bufR, then T = R_{c-1} Z
-          const T* rsrc = rs + size_t(c - 1) * N2 * N2;
+          const gmem<T>* rsrc = rs + size_t(c - 1) * N2 * N2;
           for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = rsrc[o];
           __syncthreads();
           auto ta = [&](int i, int a) { return bufR[a * LDT + i]; };
@@ -1472,10 +1473,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         // orthonormal to ~1e-10; FP64 environments need the second pass.
         if constexpr (GRAM) mgs_pairs_rows<T, CHI, NT, LDV, KW, (KW < CHI ? 8 : TPP)>(bufS, kept, T(Tol::eta));
         else mgs2_rows<T, CHI, NT, 2, LDV>(bufS, kept, T(Tol::eta));
-        E* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
+        gmem<E>* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
         for (int o = tid; o < int(site); o += NT) {
           const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
-          bout[o] = narrow<E>(bufS[al * LDV + x * CHI + be]);
+          gst<E>(bout, o, narrow<E>(bufS[al * LDV + x * CHI + be]));
         }
         // Xt_c = 2^-e_{c-1} Z V^T (N2 x CHI, column-major in bufR), then a power-of-two rescale
         const int ec = rexp[c - 1];
@@ -1525,20 +1526,20 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   // ---------------- ln Z_TN from the top row ----------------
   if (lnZ_out != nullptr) {
     __syncthreads();
-    const E* A0 = env;   // row 0
-    const uint64_t* jh0 = R.Jh;
-    for (int o = tid; o < 2 * CHI; o += NT) sc[o] = widen(A0[(o / CHI) * CHI * CHI + (o % CHI)]);
+    const gmem<E>* A0 = env;   // row 0
+    const gmem<const uint64_t>* jh0 = as_global(R.Jh);
+    for (int o = tid; o < 2 * CHI; o += NT) sc[o] = widen(gld<E>(A0, (o / CHI) * CHI * CHI + (o % CHI)));
     double logacc = 0;
     for (int c = 1; c < L; ++c) {
       __syncthreads();
-      const E* A = A0 + size_t(c) * site;
+      const gmem<E>* A = A0 + size_t(c) * site;
       T mx = 0, val = 0;
       if (tid < 2 * CHI) {
         const int sp = tid / CHI, be = tid % CHI;
         for (int s2 = 0; s2 < 2; ++s2) {
           const T w = bond_weight<T>(jh0, c - 1, s2, sp, ep, em);
           T dd = 0;
-          for (int al = 0; al < CHI; ++al) dd += sc[s2 * CHI + al] * widen(A[(sp * CHI + al) * CHI + be]);
+          for (int al = 0; al < CHI; ++al) dd += sc[s2 * CHI + al] * widen(gld<E>(A, (sp * CHI + al) * CHI + be));
           val += w * dd;
         }
         mx = fabs(val);

@@ -6,15 +6,15 @@ Metropolis over them (a6).  Default workload: 64 realizations of the 64 x 64 ope
 p = 0.109 on the Nishimori line, chi = 32, 1000 proposals each, FP32 batched (one launch per
 stage for the whole batch).
 
-Consecutive steps overlap on two streams: the build of step t+1 (one workgroup per realization,
-on CUs kept free of proposal work by a CU mask) runs during the proposals and accepts of step t
-(on the other CUs); two sets of environments alternate.  The timed region starts with an empty
-pipeline and ends when the last step's accepts are done.  `serial` reports the same steps one
-after the other on one stream.  Also measured: the FP64 plain form (FP64 environments, one
+Consecutive steps overlap: the builds of steps t+1 and t+2 (one workgroup per realization each,
+on CUs kept free of proposal work by a CU mask, one stream each) run during the proposals and
+accepts of step t (on the other CUs); three sets of environments rotate.  The timed region starts
+with an empty pipeline and ends when the last step's accepts are done.  `serial` reports the same
+steps one after the other on one stream.  Also measured: the FP64 plain form (FP64 environments, one
 realization per call, one proposal per call) on a bounded sample, and the CPU FP64 oracle on the
 host (bounded sample, extrapolated; labelled).
 
-Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 10] [--warmup 1] [--serial]
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 1] [--serial]
 """
 import argparse
 import json
@@ -37,19 +37,19 @@ HBM_PEAK_GBS = 8000.0
 # only for the kernel sources they were taken on: reported as null once those change.
 COUNTED_TRAFFIC = {
     ("rbim64", "fp32", "env_build"): {
-        "fetch_kib": 5923933.0, "fetch_factor": 1048576.0 / 524299.5,
-        "write_kib": 10220222.8, "write_factor": 1.0,
+        "fetch_kib": 5928775.1, "fetch_factor": 1048576.0 / 524300.625,
+        "write_kib": 10230910.5, "write_factor": 1.0,
         "sources_sha256": {
-            "envbuild.hip": "c7ba958dc99e420f90b15680a4bbf944460b6383705a24cb79cdbe538d18318a",
-            "common.hpp": "d3d203ac7e1f0d0435cb5dfe9b83b18a8e2489c363933aa5b163e724c48f17b5",
+            "envbuild.hip": "51032cf02c089f396d7c8c17fc113ef404340121efb0dd92fdc1f88b6b6eac2f",
+            "common.hpp": "2bc982fcaf62715dab9d8874db2780a5211c7c295637a1e3d7cedcf3f832a587",
         },
     },
     ("rbim64", "fp32", "propose"): {
-        "fetch_kib": 63701457.1, "fetch_factor": 1048576.0 / 524299.5,
+        "fetch_kib": 62240253.0, "fetch_factor": 1048576.0 / 524300.625,
         "write_kib": 67237614.0, "write_factor": 1.0,
         "sources_sha256": {
             "sampler.hip": "36e477df883f9a1863bafa2e69bfcd168aa700f756c771cfdb0dc71be2dd0f25",
-            "common.hpp": "d3d203ac7e1f0d0435cb5dfe9b83b18a8e2489c363933aa5b163e724c48f17b5",
+            "common.hpp": "2bc982fcaf62715dab9d8874db2780a5211c7c295637a1e3d7cedcf3f832a587",
         },
     },
 }
@@ -110,12 +110,12 @@ def add_rooflines(res, args, Ls):
     return res
 
 
-def run_gpu(args):
+def run_gpu(args, w=None):
     import torch
     from paper_2409_06538_amd import binding
     import synth
 
-    w = synth.WORKLOADS[args.workload]
+    w = synth.WORKLOADS[args.workload] if w is None else w
     Ls, seeds = workload_sizes(w)
     chi, p, K = w["chi"], w["p"], args.proposals or w["proposals"]
     n = len(seeds)
@@ -196,18 +196,19 @@ def run_gpu(args):
     return add_rooflines(res, args, Ls)
 
 
-def reserved_cu_bits(word):
-    """Bit positions cleared in 32-bit word `word` of the CU mask: 8 per word, one per residue
-    mod 8 and two per byte, rotated by the word index.  Whether the mask enumerates CUs XCD by
-    XCD (32 per XCD, shader engines by byte or interleaved mod 4) or interleaved across the 8
-    XCDs with shader engines by byte, every XCD then keeps 8 CUs free, 2 in each shader engine."""
-    return [8 * ((x // 2 + word) % 4) + x for x in range(8)]
+def reserved_cu_bits(word, sets=1):
+    """Bit positions cleared in 32-bit word `word` of the CU mask: 8 per set, one per residue mod 8
+    and two per byte, rotated by the word index (and by two bytes for the second set).  Whether
+    the mask enumerates CUs XCD by XCD (32 per XCD, shader engines by byte or interleaved mod 4)
+    or interleaved across the 8 XCDs with shader engines by byte, every XCD then keeps 8 CUs per
+    set free, spread evenly over its shader engines."""
+    return [8 * ((x // 2 + word + 2 * k) % 4) + x for k in range(sets) for x in range(8)]
 
 
 def cu_masked_stream(reserve):
-    """A stream (default priority) whose kernels avoid 8 CUs of every XCD, so that the 64
-    workgroups of a concurrent build always find free CUs.  Returns (stream, mask words), or
-    (None, None) when no mask is asked for or the call fails."""
+    """A stream (default priority) whose kernels avoid 8 `reserve` CUs of every XCD, so that the
+    64 workgroups of each of `reserve` concurrent builds always find free CUs.  Returns (stream,
+    mask words), or (None, None) when no mask is asked for or the call fails."""
     import ctypes
     import torch
     if not reserve:
@@ -217,7 +218,7 @@ def cu_masked_stream(reserve):
     vals = []
     for w in range(words):
         v = 0xFFFFFFFF
-        for bit in reserved_cu_bits(w):
+        for bit in reserved_cu_bits(w, reserve):
             v &= ~(1 << bit)
         vals.append(v)
     mask = (ctypes.c_uint32 * words)(*vals)
@@ -235,10 +236,11 @@ def cu_masked_stream(reserve):
 
 
 def run_gpu_pipelined(args):
-    """Consecutive steps overlapped on two streams: the build of step t+1 (one workgroup per
-    realization, so a fraction of the CUs) runs while the proposals and accepts of step t use
-    the rest.  Two batches with their own environments and workspaces alternate, so a build never
-    overwrites environments that proposals still read."""
+    """Consecutive steps overlapped: the builds of the next `depth` steps (one workgroup per
+    realization each, so a fraction of the CUs; one stream per build in flight) run while the
+    proposals and accepts of step t use the rest of the chip (one stream, CU-masked).  depth + 1
+    batches with their own environments and workspaces rotate, so a build never overwrites
+    environments that proposals still read."""
     import torch
     from paper_2409_06538_amd import binding
     import synth
@@ -250,12 +252,13 @@ def run_gpu_pipelined(args):
     beta = binding.nishimori_beta(p)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    s_build = torch.cuda.Stream()
-    s_prop, cu_mask = cu_masked_stream(args.reserve_cus)
+    depth = args.builds_in_flight
+    s_builds = [torch.cuda.Stream() for _ in range(depth)]
+    s_prop, cu_mask = cu_masked_stream(depth if args.reserve_cus else 0)
     if s_prop is None:
         s_prop = torch.cuda.Stream()
     sets = []
-    for _ in range(2):
+    for _ in range(depth + 1):
         b = binding.Batch(Ls, [beta] * n, seeds, chi, args.precision, K=K, device=dev)
         out = (torch.empty(b.spins_shape(K), dtype=torch.int64, device=dev),
                torch.empty((n, K), dtype=torch.float64, device=dev),
@@ -270,12 +273,13 @@ def run_gpu_pipelined(args):
     def run(steps, record):
         sums, ev = [], []
         for t in range(steps):
-            st = sets[t % 2]
+            st = sets[t % (depth + 1)]
             b = st["b"]
+            s_build = s_builds[t % depth]
             e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
             with torch.cuda.stream(s_build):
                 if st["done"] is not None:
-                    s_build.wait_event(st["done"])     # proposals of step t-2 have read this env
+                    s_build.wait_event(st["done"])     # proposals of step t-depth-1 read this env
                 b.make_couplings(seeds, p)
                 e[0].record(s_build)
                 b.build_env(want_lnZ=False)
@@ -317,7 +321,8 @@ def run_gpu_pipelined(args):
             "wall_s": wall, "ms_per_step": 1e3 * wall / args.steps,
             "value": updates / wall, "accepted": accepted, "attempted": attempted,
             "acceptance": accepted / attempted, "build_ms": build_ms, "propose_ms": prop_ms,
-            "graph": False, "pipelined": True, "propose_cu_mask": cu_mask}, args, Ls)
+            "graph": False, "pipelined": True, "builds_in_flight": depth,
+            "propose_cu_mask": cu_mask}, args, Ls)
 
 
 def run_fp64_plain(args, L, chi, p, K_full, n_prop=20):
@@ -396,10 +401,36 @@ def calib_copy(mib):
     del src, dst
 
 
+SWEEP_LS = (16, 32, 64, 128, 256)
+SWEEP_CHIS = (8, 16, 32)
+
+
+def run_sweep(args):
+    """Acceptance and cost against L and chi (the quantities of the paper's acceptance-ratio and
+    cost figures, Sec. III B): for each (L, chi), 16 realizations at p = 0.109 on the Nishimori
+    line, 256 proposals each, one serial step timed after one warm-up.  One JSON line per point:
+    p_a, build and proposal times, the time per valid (accepted) sample per realization, and the
+    accepted spin-updates/s of the batch."""
+    import copy
+    for chi in SWEEP_CHIS:
+        for L in SWEEP_LS:
+            w = dict(L=L, p=0.109, chi=chi, seeds=tuple(range(16)), proposals=256)
+            a = copy.copy(args)
+            a.steps, a.warmup, a.graph = 1, 1, False
+            res = run_gpu(a, w)
+            wall_per_real = res["wall_s"]          # the realizations run side by side
+            print(json.dumps({
+                "sweep": "acceptance_cost", "L": L, "chi": chi, "precision": args.precision,
+                "realizations": res["n"], "proposals": res["K"], "acceptance": res["acceptance"],
+                "build_ms": res["build_ms"], "propose_ms": res["propose_ms"],
+                "ms_per_valid_sample": 1e3 * wall_per_real / max(1.0, res["acceptance"] * (res["K"] - 1)),
+                "accepted_spin_updates_per_s": res["value"]}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rbim64")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
@@ -414,8 +445,13 @@ def main():
     ap.add_argument("--no-serial", action="store_true",
                     help="skip the serial comparison run")
     ap.add_argument("--reserve-cus", type=int, default=1, choices=[0, 1],
-                    help="overlapped steps: keep 8 CUs of every XCD free of proposal work for the "
-                         "concurrent build (0: no CU mask)")
+                    help="overlapped steps: keep 8 CUs of every XCD per build in flight free of "
+                         "proposal work (0: no CU mask)")
+    ap.add_argument("--builds-in-flight", type=int, default=2, choices=[1, 2],
+                    help="overlapped steps: environment builds of later steps running at once")
+    ap.add_argument("--sweep", action="store_true",
+                    help="acceptance and cost against L and chi (one JSON line per point) instead "
+                         "of the benchmark line")
     ap.add_argument("--graph", action="store_true",
                     help="capture the whole step in one HIP graph and time its replays (phase "
                          "times then come from the eager warm-up steps)")
@@ -428,6 +464,9 @@ def main():
               "batch are independent, so N GPUs would each run their own share; this "
               "benchmark measures one GPU's share.", file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        run_sweep(args)
+        return
     serial = args.serial or args.graph
     res = run_gpu(args) if serial else run_gpu_pipelined(args)
     if not serial and not args.no_serial:
@@ -465,12 +504,13 @@ def main():
                                f"+-J lattice, p={res['p']}, Nishimori beta, chi={res['chi']}, "
                                f"{res['K']} proposals each, {args.precision} batched"
                                + (", one HIP graph per step" if res["graph"] else "")
-                               + (", consecutive steps overlapped on two streams (build of step "
-                                  "t+1 during the proposals of step t)" if res.get("pipelined")
-                                  else ""),
+                               + (f", consecutive steps overlapped (builds of the next "
+                                  f"{res.get('builds_in_flight')} step(s) during the proposals of "
+                                  f"step t)" if res.get("pipelined") else ""),
                    "L": L0 if uniform else res["Ls"], "chi": res["chi"], "realizations": res["n"],
                    "proposals": res["K"], "p": res["p"], "precision": args.precision,
                    "graph": res["graph"], "pipelined": bool(res.get("pipelined")),
+                   "builds_in_flight": res.get("builds_in_flight"),
                    "propose_cu_mask": res.get("propose_cu_mask")},
         "acceptance": res["acceptance"],
         "accepted": res["accepted"],

@@ -24,3 +24,14 @@ def test_workload_sizes():
     assert Ls[:5] == [32, 64, 128, 256, 32]
     Ls, seeds = bench.workload_sizes(synth.WORKLOADS["rbim64"])
     assert Ls == [64] * 64 and seeds == list(range(64))
+
+
+def test_reserved_cu_bits_two_sets():
+    """With two builds in flight, 16 CUs of every XCD are kept free, 4 in each shader engine."""
+    bits = [32 * w + b for w in range(8) for b in bench.reserved_cu_bits(w, 2)]
+    assert len(bits) == len(set(bits)) == 128
+    assert Counter(i // 32 for i in bits) == Counter({x: 16 for x in range(8)})
+    assert set(Counter((i // 32, (i % 32) // 8) for i in bits).values()) == {4}
+    assert set(Counter((i // 32, (i % 32) % 4) for i in bits).values()) == {4}
+    assert Counter(i % 8 for i in bits) == Counter({x: 16 for x in range(8)})
+    assert set(Counter((i % 8, (i // 8) % 4) for i in bits).values()) == {4}

@@ -313,33 +313,45 @@ __global__ __launch_bounds__(MF_NT) void propose_mfma_kernel(const DevReal* real
       if (SITE % MF_NT == 0 || e < SITE) pf[t] = src[e];
     }
   };
-  // right sweep: row alpha, column beta; left sweep (transposed): row beta, column alpha
+  // right sweep: row alpha, column beta; left sweep (transposed): row beta, column alpha.
+  // Returns whether this thread stored a nonzero entry outside the leading 16 x 16 block of a
+  // matrix: a site whose entries all lie inside it (both bonds at most 16, the rest zero padding)
+  // is narrow, and its products and V rows are the first tile only.
   auto store_site = [&](T* dst, bool transposed) {
+    bool wide = false;
 #pragma unroll
     for (int t = 0; t < SPT; ++t) {
       const int e = tid + MF_NT * t;
       if (SITE % MF_NT == 0 || e < SITE) {
         const int y = e / (CHI * CHI), a = (e / CHI) % CHI, b = e % CHI;
         const int rr = transposed ? b : a, cc = transposed ? a : b;
-        dst[(y * CHI + rr) * LDB + (cc & ~15) + M::pos(cc & 15)] = widen(pf[t]);
+        const T v = widen(pf[t]);
+        dst[(y * CHI + rr) * LDB + (cc & ~15) + M::pos(cc & 15)] = v;
+        wide = wide || ((a >= 16 || b >= 16) && v != T(0));
       }
     }
+    return wide;
   };
-  // C = sum over the chi contraction index of Bsb[y][16 ro + pl][.] times the register operand
-  auto tile_products = [&](const T* Bsb, const T (&opnd)[2][RT][4], V4 (&acc)[2][RT]) {
+  // C = sum over the chi contraction index of Bsb[y][16 ro + pl][.] times the register operand;
+  // nt (1 or RT, wave-uniform) tiles of rows and of the contraction index
+  auto tile_products = [&](const T* Bsb, const T (&opnd)[2][RT][4], V4 (&acc)[2][RT], int nt) {
 #pragma unroll
     for (int y = 0; y < 2; ++y)
 #pragma unroll
       for (int ro = 0; ro < RT; ++ro) {
         V4 a = {T(0), T(0), T(0), T(0)};
-        const T* ap = Bsb + (y * CHI + 16 * ro + pl) * LDB + 4 * q;
+        if (ro < nt) {
+          const T* ap = Bsb + (y * CHI + 16 * ro + pl) * LDB + 4 * q;
 #pragma unroll
-        for (int m = 0; m < RT; ++m) {
-          T av[4];
+          for (int m = 0; m < RT; ++m) {
+            if (m < nt) {
+              T av[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) av[r] = ap[16 * m + r];
+              for (int r = 0; r < 4; ++r) av[r] = ap[16 * m + r];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) a = M::mac(av[r], opnd[y][m][r], a);
+              for (int r = 0; r < 4; ++r) a = M::mac(av[r], opnd[y][m][r], a);
+            }
+          }
         }
         acc[y][ro] = a;
       }
@@ -370,17 +382,18 @@ __global__ __launch_bounds__(MF_NT) void propose_mfma_kernel(const DevReal* real
 #pragma unroll
         for (int i = 0; i < 4; ++i) rc[y][t][i] = (t == 0 && M::row(q, i) == 0) ? T(1) : T(0);
     load_site(r, L - 1);
-    store_site(Bs[b], false);
-    __syncthreads();
+    int nt = __syncthreads_or(store_site(Bs[b], false)) ? RT : 1;
     for (int c = L - 1; c >= 0; --c) {
       if (c > 0) load_site(r, c - 1);
+      bool wide = false;
       V4 acc[2][RT];
-      tile_products(Bs[b], rc, acc);
+      tile_products(Bs[b], rc, acc, nt);
       T* vo = vbase + size_t(c) * vstep;
 #pragma unroll
       for (int y = 0; y < 2; ++y)
 #pragma unroll
         for (int t = 0; t < RT; ++t)
+          if (t < nt)   // rows past the first tile of a narrow site are zero and not stored
 #pragma unroll
           for (int h = 0; h < 4; h += PV) {
             const int chunk = ((y * RT + t) * 4 + h) / PV;
@@ -419,10 +432,13 @@ __global__ __launch_bounds__(MF_NT) void propose_mfma_kernel(const DevReal* real
           for (int t = 0; t < RT; ++t)
 #pragma unroll
             for (int i = 0; i < 4; ++i) rc[y][t][i] = T(ldexp(rc[y][t][i], -e));
-        store_site(Bs[b ^ 1], false);
+        wide = store_site(Bs[b ^ 1], false);
       }
-      __syncthreads();
-      if (c > 0) b ^= 1;
+      const int nt_next = __syncthreads_or(wide) ? RT : 1;
+      if (c > 0) {
+        b ^= 1;
+        nt = nt_next;
+      }
     }
 
     // ---- left sweep: draw s_c from Z_c(y) = pre(y) (l . V_c(y)), then l <- pre(s) B_c[s]^T l ----
@@ -435,8 +451,7 @@ __global__ __launch_bounds__(MF_NT) void propose_mfma_kernel(const DevReal* real
         for (int i = 0; i < 4; ++i) el[y][t][i] = (t == 0 && M::row(q, i) == 0) ? T(1) : T(0);
     b ^= 1;
     load_site(r, 0);
-    store_site(Bs[b], true);
-    __syncthreads();
+    nt = __syncthreads_or(store_site(Bs[b], true)) ? RT : 1;
     Philox4 blk{};
     int sprev = 0;   // 0 <-> +1, 1 <-> -1 (spin at c-1 of this row)
     uint64_t curw = 0, tword = 0;
@@ -452,7 +467,7 @@ __global__ __launch_bounds__(MF_NT) void propose_mfma_kernel(const DevReal* real
           for (int h = 0; h < 4; h += PV) {
             const int chunk = ((y * RT + t) * 4 + h) / PV;
 #pragma unroll
-            for (int u = 0; u < PV; ++u) vv[y][t][h + u] = vi[chunk * 64 * PV + u];
+            for (int u = 0; u < PV; ++u) vv[y][t][h + u] = (t < nt) ? vi[chunk * 64 * PV + u] : T(0);
           }
       T pre[2] = {T(1), T(1)};
       if (r > 0) {
@@ -506,7 +521,7 @@ __global__ __launch_bounds__(MF_NT) void propose_mfma_kernel(const DevReal* real
       }
       // l <- pre(s) B_c[s]^T l (both products; each proposal keeps its own)
       V4 u[2][RT];
-      tile_products(Bs[b], el, u);
+      tile_products(Bs[b], el, u, nt);
       T mx = 0;
       const T ps = s == 0 ? pre[0] : pre[1];
 #pragma unroll
@@ -525,9 +540,12 @@ __global__ __launch_bounds__(MF_NT) void propose_mfma_kernel(const DevReal* real
           el[1][t][i] = el[0][t][i];
         }
       sprev = s;
-      if (c + 1 < L) store_site(Bs[b ^ 1], true);
-      __syncthreads();
-      if (c + 1 < L) b ^= 1;
+      const bool wide_next = (c + 1 < L) ? store_site(Bs[b ^ 1], true) : false;
+      const int nt_next = __syncthreads_or(wide_next) ? RT : 1;
+      if (c + 1 < L) {
+        b ^= 1;
+        nt = nt_next;
+      }
     }
     b ^= 1;
 

@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "accepted spin-updates/s + acceptance rate, BF16/FP32 batched vs FP64 plain"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+PROPOSALS_PER_WG = 128    # proposals per workgroup of the matrix-core proposal kernel
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
@@ -93,21 +94,42 @@ def add_rooflines(res, args, Ls):
                        "traffic": counted_traffic(args.workload, args.precision, "env_build"),
                        "launch_ms": build_ms,
                        "algorithmic_flops_per_launch": flops}
-    # proposals: HBM-bound; algorithmic bytes = the per-row V store written and read back, plus
-    # each workgroup of 64 proposals streaming its realization's environments once per sweep
+    # proposals: HBM-bound; algorithmic bytes = the per-row V store written and read back (2 x
+    # 16 rows per proposal at a narrow site, 2 x chi elsewhere), plus each workgroup of
+    # PROPOSALS_PER_WG proposals streaming its realization's environments once per sweep
     elem = 8 if args.precision == "fp64" else 4
     esize = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
-    kpad = (K + 63) // 64 * 64
-    vbytes = sum(2.0 * L * L * 2 * chi * kpad * elem for L in Ls)
-    ebytes = sum(2.0 * L * L * 2 * chi * chi * esize * (kpad // 64) for L in Ls)
+    g = PROPOSALS_PER_WG
+    kpad = (K + g - 1) // g * g
+    nf = res.get("narrow_fraction", 0.0)
+    vrows = min(16, chi) * nf + chi * (1.0 - nf)
+    vbytes = sum(2.0 * L * L * 2 * vrows * kpad * elem for L in Ls)
+    ebytes = sum(2.0 * L * L * 2 * chi * chi * esize * (kpad // g) for L in Ls)
     pbytes = vbytes + ebytes
     pach = pbytes / (prop_ms * 1e-3) / 1e9
     res["roofline_propose"] = {"kernel": "propose_mfma_kernel" if chi % 16 == 0 else "propose_kernel",
                                "bound": "hbm", "achieved": pach, "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": pach / HBM_PEAK_GBS,
                                "traffic": counted_traffic(args.workload, args.precision, "propose"),
-                               "launch_ms": prop_ms, "algorithmic_bytes_per_launch": pbytes}
+                               "launch_ms": prop_ms, "algorithmic_bytes_per_launch": pbytes,
+                               "narrow_site_fraction": nf}
     return res
+
+
+def narrow_fraction(batch):
+    """Fraction of the environment sites whose entries all lie in the leading 16 x 16 block of
+    both matrices (the proposal kernel then stores one 16-row tile of V per spin value)."""
+    import torch
+    tot = wide = 0
+    for i, L in enumerate(batch.Ls):
+        e = batch.env_tensor(i)
+        if batch.chi <= 16:
+            tot += L * L
+            continue
+        w = ((e[..., 16:, :] != 0).flatten(2).any(-1) | (e[..., :, 16:] != 0).flatten(2).any(-1))
+        tot += L * L
+        wide += int(w.sum().item())
+    return 1.0 - wide / max(1, tot)
 
 
 def run_gpu(args, w=None):
@@ -192,6 +214,7 @@ def run_gpu(args, w=None):
         "acceptance": accepted / attempted,
         "build_ms": build_ms, "propose_ms": prop_ms,
         "graph": bool(args.graph),
+        "narrow_fraction": narrow_fraction(b),
     }
     return add_rooflines(res, args, Ls)
 
@@ -313,6 +336,7 @@ def run_gpu_pipelined(args):
     build_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / len(ev)
     prop_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / len(ev)
     wall = t1 - t0
+    nfrac = narrow_fraction(sets[0]["b"])
     del sets, sums, ev
     torch.cuda.synchronize()
     if cu_mask is not None:
@@ -322,6 +346,7 @@ def run_gpu_pipelined(args):
             "value": updates / wall, "accepted": accepted, "attempted": attempted,
             "acceptance": accepted / attempted, "build_ms": build_ms, "propose_ms": prop_ms,
             "graph": False, "pipelined": True, "builds_in_flight": depth,
+            "narrow_fraction": nfrac,
             "propose_cu_mask": cu_mask}, args, Ls)
 
 

@@ -258,7 +258,7 @@ struct Mf<double> {
   __host__ __device__ static constexpr int pos(int x) { return 4 * (x & 3) + (x >> 2); }
 };
 
-constexpr int MF_WAVES = 4;
+constexpr int MF_WAVES = 8;
 constexpr int MF_NT = 64 * MF_WAVES;
 constexpr int MF_PROP = 16 * MF_WAVES;   // proposals per workgroup
 
@@ -624,9 +624,9 @@ hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, 
 }
 
 size_t propose_scratch_bytes(tnmc_precision prec, int chi, int L, int K) {
-  static_assert(MF_PROP == PROP_NT, "both forms pad K to the same workgroup size");
+  static_assert(MF_PROP % PROP_NT == 0, "one padding serves both forms");
   const size_t elem = (prec == TNMC_FP64) ? 8 : 4;
-  const size_t kpad = size_t(K + PROP_NT - 1) / PROP_NT * PROP_NT;
+  const size_t kpad = size_t(K + MF_PROP - 1) / MF_PROP * MF_PROP;
   return size_t(L) * 2 * chi * kpad * elem;   // V_c(y) of one row for every proposal
 }
 

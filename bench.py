@@ -28,7 +28,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "accepted spin-updates/s + acceptance rate, BF16/FP32 batched vs FP64 plain"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-PROPOSALS_PER_WG = 128    # proposals per workgroup of the matrix-core proposal kernel
+def proposals_per_wg(precision, K):
+    """Proposals per workgroup of the matrix-core proposal kernel (16 per wavefront; the library
+    picks 4 wavefronts for K <= 64 or BF16 environments, else 8)."""
+    return 64 if (K <= 64 or precision == "bf16") else 128
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
 
@@ -96,10 +99,10 @@ def add_rooflines(res, args, Ls):
                        "algorithmic_flops_per_launch": flops}
     # proposals: HBM-bound; algorithmic bytes = the per-row V store written and read back (2 x
     # 16 rows per proposal at a narrow site, 2 x chi elsewhere), plus each workgroup of
-    # PROPOSALS_PER_WG proposals streaming its realization's environments once per sweep
+    # proposals_per_wg() proposals streaming its realization's environments once per sweep
     elem = 8 if args.precision == "fp64" else 4
     esize = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
-    g = PROPOSALS_PER_WG
+    g = proposals_per_wg(args.precision, K)
     kpad = (K + g - 1) // g * g
     nf = res.get("narrow_fraction", 0.0)
     vrows = min(16, chi) * nf + chi * (1.0 - nf)

@@ -13,6 +13,8 @@
 // row go to the workspace between the two sweeps.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -258,16 +260,25 @@ struct Mf<double> {
   __host__ __device__ static constexpr int pos(int x) { return 4 * (x & 3) + (x >> 2); }
 };
 
-constexpr int MF_WAVES = 8;
-constexpr int MF_NT = 64 * MF_WAVES;
-constexpr int MF_PROP = 16 * MF_WAVES;   // proposals per workgroup
+// Wavefronts per workgroup (each owns 16 proposals): more share each staged site tensor (less
+// environment traffic per proposal); the best count was measured per precision (8 with FP32 or
+// FP64 environments, 4 with BF16 ones), and 4 for up to 64 proposals (a single proposal runs
+// fastest with the site staging spread over 4 wavefronts).
+constexpr int MF_MAX_PROP = 128;   // K is padded to this in the workspace (any WAVES <= 8)
+template <typename E>
+constexpr int mf_waves_for(int K) {
+  return (K <= 64 || std::is_same<E, bf16_t>::value) ? 4 : 8;
+}
 
-template <typename T, typename E, int CHI>
-__global__ __launch_bounds__(MF_NT) void propose_mfma_kernel(const DevReal* reals, int K, int Lmax,
+template <typename T, typename E, int CHI, int MF_WAVES>
+__global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevReal* reals, int K, int Lmax,
                                                              uint64_t seed, uint64_t first,
                                                              const uint64_t* teacher,
                                                              uint64_t* spins_out, double* logq_out,
                                                              int32_t* E_out, uint32_t* fallbacks) {
+  constexpr int MF_NT = 64 * MF_WAVES;
+  constexpr int MF_PROP = 16 * MF_WAVES;   // proposals per workgroup
+  static_assert(MF_PROP <= MF_MAX_PROP, "workspace padding");
   using M = Mf<T>;
   using V4 = typename M::v4;
   constexpr int RT = CHI / 16;                   // 16-row tiles of a site matrix
@@ -590,9 +601,14 @@ hipError_t launch_propose(const DevReal* d_reals, int n, int K, int Lmax, uint64
                           double* d_logq, int32_t* d_E, uint32_t* d_fallbacks,
                           hipStream_t stream) {
   if constexpr (CHI % 16 == 0) {
-    dim3 grid((K + MF_PROP - 1) / MF_PROP, n);
-    hipLaunchKernelGGL((propose_mfma_kernel<T, E, CHI>), grid, dim3(MF_NT), 0, stream, d_reals, K,
-                       Lmax, seed, first, d_teacher, d_spins, d_logq, d_E, d_fallbacks);
+    auto go = [&](auto wc) {
+      constexpr int WAVES = decltype(wc)::value;
+      dim3 grid((K + 16 * WAVES - 1) / (16 * WAVES), n);
+      hipLaunchKernelGGL((propose_mfma_kernel<T, E, CHI, WAVES>), grid, dim3(64 * WAVES), 0, stream,
+                         d_reals, K, Lmax, seed, first, d_teacher, d_spins, d_logq, d_E, d_fallbacks);
+    };
+    if (mf_waves_for<E>(K) == 4) go(std::integral_constant<int, 4>{});
+    else go(std::integral_constant<int, 8>{});
   } else {
     dim3 grid((K + PROP_NT - 1) / PROP_NT, n);
     hipLaunchKernelGGL((propose_kernel<T, E, CHI>), grid, dim3(PROP_NT), 0, stream, d_reals, K,
@@ -624,9 +640,9 @@ hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, 
 }
 
 size_t propose_scratch_bytes(tnmc_precision prec, int chi, int L, int K) {
-  static_assert(MF_PROP % PROP_NT == 0, "one padding serves both forms");
+  static_assert(MF_MAX_PROP % PROP_NT == 0, "one padding serves both forms");
   const size_t elem = (prec == TNMC_FP64) ? 8 : 4;
-  const size_t kpad = size_t(K + MF_PROP - 1) / MF_PROP * MF_PROP;
+  const size_t kpad = size_t(K + MF_MAX_PROP - 1) / MF_MAX_PROP * MF_MAX_PROP;
   return size_t(L) * 2 * chi * kpad * elem;   // V_c(y) of one row for every proposal
 }
 

@@ -28,12 +28,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "accepted spin-updates/s + acceptance rate, BF16/FP32 batched vs FP64 plain"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-def proposals_per_wg(precision, K):
-    """Proposals per workgroup of the matrix-core proposal kernel (16 per wavefront; the library
-    picks 4 wavefronts for K <= 64 or BF16 environments, else 8)."""
-    return 64 if (K <= 64 or precision == "bf16") else 128
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 HBM_PEAK_GBS = 8000.0
+
+
+def proposals_per_wg(precision, n, K, Lmax):
+    """Proposals per workgroup of the matrix-core proposal kernel (16 per wavefront; the library
+    picks 8 wavefronts for FP32/FP64 environments with L <= 64 and at least 256 workgroups of 128
+    proposals, else 4)."""
+    wide = precision != "bf16" and Lmax <= 64 and n * ((K + 127) // 128) >= 256
+    return 128 if wide else 64
 
 
 # HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE counters, each
@@ -102,7 +106,7 @@ def add_rooflines(res, args, Ls):
     # proposals_per_wg() proposals streaming its realization's environments once per sweep
     elem = 8 if args.precision == "fp64" else 4
     esize = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
-    g = proposals_per_wg(args.precision, K)
+    g = proposals_per_wg(args.precision, len(Ls), K, max(Ls))
     kpad = (K + g - 1) // g * g
     nf = res.get("narrow_fraction", 0.0)
     vrows = min(16, chi) * nf + chi * (1.0 - nf)

@@ -260,14 +260,18 @@ struct Mf<double> {
   __host__ __device__ static constexpr int pos(int x) { return 4 * (x & 3) + (x >> 2); }
 };
 
-// Wavefronts per workgroup (each owns 16 proposals): more share each staged site tensor (less
-// environment traffic per proposal); the best count was measured per precision (8 with FP32 or
-// FP64 environments, 4 with BF16 ones), and 4 for up to 64 proposals (a single proposal runs
-// fastest with the site staging spread over 4 wavefronts).
+// Wavefronts per workgroup (each owns 16 proposals).  More wavefronts share each staged site
+// tensor (less environment traffic per proposal) but give fewer workgroups and a larger V store
+// per workgroup.  Measured: 8 is faster for FP32 and FP64 environments up to L = 64 when the grid
+// still covers every CU once; 4 for BF16 environments, for larger L, and for small grids (a
+// single proposal also runs fastest with the site staging spread over 4 wavefronts).
 constexpr int MF_MAX_PROP = 128;   // K is padded to this in the workspace (any WAVES <= 8)
+constexpr int MF_CUS = 256;
 template <typename E>
-constexpr int mf_waves_for(int K) {
-  return (K <= 64 || std::is_same<E, bf16_t>::value) ? 4 : 8;
+int mf_waves_for(int n, int K, int Lmax) {
+  const bool wide = !std::is_same<E, bf16_t>::value && Lmax <= 64 &&
+                    size_t(n) * size_t((K + MF_MAX_PROP - 1) / MF_MAX_PROP) >= size_t(MF_CUS);
+  return wide ? 8 : 4;
 }
 
 template <typename T, typename E, int CHI, int MF_WAVES>
@@ -607,7 +611,7 @@ hipError_t launch_propose(const DevReal* d_reals, int n, int K, int Lmax, uint64
       hipLaunchKernelGGL((propose_mfma_kernel<T, E, CHI, WAVES>), grid, dim3(64 * WAVES), 0, stream,
                          d_reals, K, Lmax, seed, first, d_teacher, d_spins, d_logq, d_E, d_fallbacks);
     };
-    if (mf_waves_for<E>(K) == 4) go(std::integral_constant<int, 4>{});
+    if (mf_waves_for<E>(n, K, Lmax) == 4) go(std::integral_constant<int, 4>{});
     else go(std::integral_constant<int, 8>{});
   } else {
     dim3 grid((K + PROP_NT - 1) / PROP_NT, n);

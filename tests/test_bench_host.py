@@ -35,3 +35,23 @@ def test_reserved_cu_bits_two_sets():
     assert set(Counter((i // 32, (i % 32) % 4) for i in bits).values()) == {4}
     assert Counter(i % 8 for i in bits) == Counter({x: 16 for x in range(8)})
     assert set(Counter((i % 8, (i // 8) % 4) for i in bits).values()) == {4}
+
+
+def test_rooflines_from_launch_times():
+    """The bench line's roofline objects from launch times alone (no GPU)."""
+    import argparse
+    args = argparse.Namespace(precision="fp32", workload="rbim64")
+    res = {"chi": 32, "K": 1000, "build_ms": 100.0, "propose_ms": 50.0, "narrow_fraction": 0.5}
+    out = bench.add_rooflines(res, args, [64] * 64)
+    r = out["roofline"]
+    assert r["bound"] == "alu" and r["peak"] == bench.FP32_VECTOR_PEAK_TFLOPS
+    assert abs(r["achieved"] - 270 * 32 ** 3 * 63 * 64 * 64 / 0.1 / 1e12) < 1e-9
+    p = out["roofline_propose"]
+    assert p["bound"] == "hbm" and p["peak"] == bench.HBM_PEAK_GBS
+    # V round trip at 16 rows (narrow half) and 32 rows, plus 8 workgroups streaming the sites twice
+    v = 2.0 * 64 * 64 * 2 * (16 * 0.5 + 32 * 0.5) * 1024 * 4 * 64
+    e = 2.0 * 64 * 64 * 2 * 32 * 32 * 4 * 8 * 64
+    assert abs(p["algorithmic_bytes_per_launch"] - (v + e)) < 1.0
+    assert bench.proposals_per_wg("fp32", 64, 1000, 64) == 128
+    assert bench.proposals_per_wg("bf16", 64, 1000, 64) == 64
+    assert bench.proposals_per_wg("fp32", 256, 1000, 256) == 64

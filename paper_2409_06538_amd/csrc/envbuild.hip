@@ -1164,8 +1164,8 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
             const T tol2 = T(Tol::rank) * T(Tol::rank) * f2;
             bool pkd = !live;
             int rk = NK;
-            if constexpr (KW < CHI) {
-              // Narrow sites: lane a keeps its row of L in registers, and the pivot row's entries
+            if constexpr (NK <= 32) {
+              // Widths up to 16: lane a keeps its row of L in registers, and the pivot row's entries
               // come by readlane (wave-uniform lane), so no step waits on LDS for the dot product.
               T Lr[NK];
 #pragma unroll
@@ -1471,7 +1471,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         // One pass suffices in the Gram form: the rows come from a pivoted Cholesky factor whose
         // conditioning is bounded by the FP32 rank tolerance, so FP64 Gram-Schmidt leaves them
         // orthonormal to ~1e-10; FP64 environments need the second pass.
-        if constexpr (GRAM) mgs_pairs_rows<T, CHI, NT, LDV, KW, (KW < CHI ? 8 : TPP)>(bufS, kept, T(Tol::eta));
+        if constexpr (GRAM) mgs_pairs_rows<T, CHI, NT, LDV, KW, (KW <= 16 ? 8 : TPP)>(bufS, kept, T(Tol::eta));
         else mgs2_rows<T, CHI, NT, 2, LDV>(bufS, kept, T(Tol::eta));
         gmem<E>* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
         for (int o = tid; o < int(site); o += NT) {

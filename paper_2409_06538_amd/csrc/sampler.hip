@@ -305,10 +305,10 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   const bool active = k < K;
   const int kk = active ? k : K - 1;   // inactive slots shadow a valid proposal, write nothing
   const T ep = T(exp(R.beta)), em = T(exp(-R.beta));
-  const E* env = reinterpret_cast<const E*>(R.env);
+  const gmem<E>* env = as_global(reinterpret_cast<E*>(R.env));
   // V store of this wavefront: [c][chunk][lane][PV]
-  T* vbase = reinterpret_cast<T*>(R.ws) + (size_t(blockIdx.x) * L * MF_WAVES + wv) * (64 * NV) +
-             lane * PV;
+  gmem<T>* vbase = as_global(reinterpret_cast<T*>(R.ws)) +
+                   (size_t(blockIdx.x) * L * MF_WAVES + wv) * (64 * NV) + lane * PV;
   const size_t vstep = size_t(MF_WAVES) * 64 * NV;   // per site
   const uint64_t pid = first + uint64_t(kk);
   const uint64_t* tin = teacher ? teacher + (size_t(ri) * K + kk) * size_t(Lmax) * Wmax : nullptr;
@@ -319,15 +319,37 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   int unsat = 0;
   int pr = 0;   // rows[pr]: row above; rows[pr ^ 1]: row being drawn
 
+  // Site staging: with VEC, thread tid loads the SPT contiguous elements from tid * SPT in
+  // 16-byte pieces; otherwise element tid + MF_NT t (strided, one element per load).
+  constexpr bool VEC = SITE % MF_NT == 0 && (SPT * sizeof(E)) % 16 == 0 && CHI % SPT == 0;
+  constexpr int NQ = VEC ? int(SPT * sizeof(E) / 16) : 1;   // 16-byte pieces per thread
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
   E pf[SPT];
+  u4 pq[NQ];
   auto load_site = [&](int r, int c) {
-    const E* src = env + (size_t(r) * L + c) * SITE;
+    const gmem<E>* src = env + (size_t(r) * L + c) * SITE;
+    if constexpr (VEC) {
+      const gmem<u4>* s4 = reinterpret_cast<const gmem<u4>*>(src + size_t(tid) * SPT);
 #pragma unroll
-    for (int t = 0; t < SPT; ++t) {
-      const int e = tid + MF_NT * t;
-      if (SITE % MF_NT == 0 || e < SITE) pf[t] = src[e];
+      for (int i = 0; i < NQ; ++i) pq[i] = s4[i];
+    } else {
+#pragma unroll
+      for (int t = 0; t < SPT; ++t) {
+        const int e = tid + MF_NT * t;
+        if (SITE % MF_NT == 0 || e < SITE) pf[t] = gld<E>(src, e);
+      }
     }
   };
+  auto elem = [&](int t) {   // element t of this thread's staged part
+    if constexpr (VEC) {
+      E v[SPT];
+      __builtin_memcpy(v, pq, sizeof(v));
+      return v[t];
+    } else {
+      return pf[t];
+    }
+  };
+  auto elem_index = [&](int t) { return VEC ? tid * SPT + t : tid + MF_NT * t; };
   // right sweep: row alpha, column beta; left sweep (transposed): row beta, column alpha.
   // Returns whether this thread stored a nonzero entry outside the leading 16 x 16 block of a
   // matrix: a site whose entries all lie inside it (both bonds at most 16, the rest zero padding)
@@ -336,11 +358,11 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
     bool wide = false;
 #pragma unroll
     for (int t = 0; t < SPT; ++t) {
-      const int e = tid + MF_NT * t;
+      const int e = elem_index(t);
       if (SITE % MF_NT == 0 || e < SITE) {
         const int y = e / (CHI * CHI), a = (e / CHI) % CHI, b = e % CHI;
         const int rr = transposed ? b : a, cc = transposed ? a : b;
-        const T v = widen(pf[t]);
+        const T v = widen(elem(t));
         dst[(y * CHI + rr) * LDB + (cc & ~15) + M::pos(cc & 15)] = v;
         wide = wide || ((a >= 16 || b >= 16) && v != T(0));
       }
@@ -383,8 +405,8 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
 
   int b = 0;
   for (int r = 0; r < L; ++r) {
-    const uint64_t* jh = R.Jh + size_t(r) * W;
-    const uint64_t* jv = (r > 0) ? R.Jv + size_t(r - 1) * W : nullptr;
+    const gmem<const uint64_t>* jh = as_global(R.Jh) + size_t(r) * W;
+    const gmem<const uint64_t>* jv = (r > 0) ? as_global(R.Jv) + size_t(r - 1) * W : nullptr;
     const uint64_t* prow = &rows[pr][0][slot];       // word w at prow[w * MF_PROP]
     uint64_t* crow = &rows[pr ^ 1][0][slot];
 
@@ -403,7 +425,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
       bool wide = false;
       V4 acc[2][RT];
       tile_products(Bs[b], rc, acc, nt);
-      T* vo = vbase + size_t(c) * vstep;
+      gmem<T>* vo = vbase + size_t(c) * vstep;
 #pragma unroll
       for (int y = 0; y < 2; ++y)
 #pragma unroll
@@ -413,11 +435,11 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
           for (int h = 0; h < 4; h += PV) {
             const int chunk = ((y * RT + t) * 4 + h) / PV;
             if constexpr (PV == 4) {
-              *reinterpret_cast<V4*>(vo + chunk * 64 * PV) = acc[y][t];
+              *reinterpret_cast<gmem<V4>*>(vo + chunk * 64 * PV) = acc[y][t];
             } else {
               typedef T v2 __attribute__((ext_vector_type(2)));
               v2 d = {acc[y][t][h], acc[y][t][h + 1]};
-              *reinterpret_cast<v2*>(vo + chunk * 64 * PV) = d;
+              *reinterpret_cast<gmem<v2>*>(vo + chunk * 64 * PV) = d;
             }
           }
       if (c > 0) {
@@ -472,7 +494,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
     uint64_t curw = 0, tword = 0;
     for (int c = 0; c < L; ++c) {
       if (c + 1 < L) load_site(r, c + 1);
-      const T* vi = vbase + size_t(c) * vstep;
+      const gmem<T>* vi = vbase + size_t(c) * vstep;
       T vv[2][RT][4];
 #pragma unroll
       for (int y = 0; y < 2; ++y)

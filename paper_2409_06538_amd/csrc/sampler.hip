@@ -314,7 +314,11 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   const uint64_t* tin = teacher ? teacher + (size_t(ri) * K + kk) * size_t(Lmax) * Wmax : nullptr;
 
   for (int e = tid; e < 2 * MAX_W * MF_PROP; e += MF_NT) (&rows[0][0][0])[e] = 0ull;
-  double logq = 0.0;
+  // log q accumulates as a product of the chosen conditionals, renormalised to [0.5, 1) with
+  // its binary exponent kept apart (no underflow), and one logarithm at the end: the same value
+  // to rounding as the sum of the logarithms, without a logarithm per site.
+  double qprod = 1.0;
+  int qexp = 0;
   uint32_t nfb = 0;
   int unsat = 0;
   int pr = 0;   // rows[pr]: row above; rows[pr ^ 1]: row being drawn
@@ -549,7 +553,11 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
         const uint64_t wsel = qq == 0 ? blk.w[0] : qq == 1 ? blk.w[1] : qq == 2 ? blk.w[2] : blk.w[3];
         up = u53(wsel) < pp;
       }
-      logq += up ? log(pp) : log(1.0 - pp);
+      {
+        int ex;
+        qprod = frexp(qprod * (up ? pp : 1.0 - pp), &ex);
+        qexp += ex;
+      }
       const int s = up ? 0 : 1;
       if (!up) curw |= (1ull << (c & 63));
       if ((c & 63) == 63 || c == L - 1) {
@@ -609,7 +617,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
     pr ^= 1;
   }
   if (active && q == 0) {
-    logq_out[size_t(ri) * K + k] = logq;
+    logq_out[size_t(ri) * K + k] = log(qprod) + double(qexp) * 0.69314718055994530942;
     if (!teacher) {
       E_out[size_t(ri) * K + k] = 2 * unsat - 2 * L * (L - 1);
       for (int r = L; r < Lmax; ++r) {

@@ -548,10 +548,18 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
         if ((c & 63) == 0) tword = tin[size_t(r) * Wmax + (c >> 6)];
         up = !((tword >> (c & 63)) & 1ull);
       } else {
-        if ((c & 3) == 0) blk = philox4x64_10(uint64_t(c) >> 2, uint64_t(r), pid, R.id, seed, STREAM_PROPOSAL);
+        // The four lane groups of a proposal draw for sites c .. c + 15 at once: group q forms the
+        // Philox block of sites c + 4 q .. c + 4 q + 3, and the word of site c comes from group
+        // (c / 4) mod 4 by a shuffle (the same words as one block per group every four sites).
+        if ((c & 15) == 0)
+          blk = philox4x64_10((uint64_t(c) >> 2) + uint64_t(q), uint64_t(r), pid, R.id, seed,
+                              STREAM_PROPOSAL);
         const int qq = c & 3;
-        const uint64_t wsel = qq == 0 ? blk.w[0] : qq == 1 ? blk.w[1] : qq == 2 ? blk.w[2] : blk.w[3];
-        up = u53(wsel) < pp;
+        const uint64_t mine = qq == 0 ? blk.w[0] : qq == 1 ? blk.w[1] : qq == 2 ? blk.w[2] : blk.w[3];
+        const int src = pl + 16 * ((c >> 2) & 3);
+        const unsigned lo = __shfl(unsigned(mine & 0xffffffffull), src);
+        const unsigned hi = __shfl(unsigned(mine >> 32), src);
+        up = u53((uint64_t(hi) << 32) | lo) < pp;
       }
       {
         int ex;

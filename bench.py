@@ -34,9 +34,8 @@ HBM_PEAK_GBS = 8000.0
 
 def proposals_per_wg(precision, n, K, Lmax):
     """Proposals per workgroup of the matrix-core proposal kernel (16 per wavefront; the library
-    picks 8 wavefronts for FP32/FP64 environments with L <= 64 and at least 256 workgroups of 128
-    proposals, else 4)."""
-    wide = precision != "bf16" and Lmax <= 64 and n * ((K + 127) // 128) >= 256
+    picks 8 wavefronts for L <= 64 and at least 256 workgroups of 128 proposals, else 4)."""
+    wide = Lmax <= 64 and n * ((K + 127) // 128) >= 256
     return 128 if wide else 64
 
 

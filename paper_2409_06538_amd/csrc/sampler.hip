@@ -262,14 +262,14 @@ struct Mf<double> {
 
 // Wavefronts per workgroup (each owns 16 proposals).  More wavefronts share each staged site
 // tensor (less environment traffic per proposal) but give fewer workgroups and a larger V store
-// per workgroup.  Measured: 8 is faster for FP32 and FP64 environments up to L = 64 when the grid
-// still covers every CU once; 4 for BF16 environments, for larger L, and for small grids (a
-// single proposal also runs fastest with the site staging spread over 4 wavefronts).
+// per workgroup.  Measured: 8 is faster up to L = 64 when the grid still covers every CU once;
+// 4 for larger L and for small grids (a single proposal also runs fastest with the site staging
+// spread over 4 wavefronts).
 constexpr int MF_MAX_PROP = 128;   // K is padded to this in the workspace (any WAVES <= 8)
 constexpr int MF_CUS = 256;
 template <typename E>
 int mf_waves_for(int n, int K, int Lmax) {
-  const bool wide = !std::is_same<E, bf16_t>::value && Lmax <= 64 &&
+  const bool wide = Lmax <= 64 &&
                     size_t(n) * size_t((K + MF_MAX_PROP - 1) / MF_MAX_PROP) >= size_t(MF_CUS);
   return wide ? 8 : 4;
 }
@@ -325,9 +325,11 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
 
   // Site staging: with VEC, thread tid loads the SPT contiguous elements from tid * SPT in
   // 16-byte pieces; otherwise element tid + MF_NT t (strided, one element per load).
-  constexpr bool VEC = SITE % MF_NT == 0 && (SPT * sizeof(E)) % 16 == 0 && CHI % SPT == 0;
-  constexpr int NQ = VEC ? int(SPT * sizeof(E) / 16) : 1;   // 16-byte pieces per thread
-  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  // (8-byte pieces when the thread's share is 8 bytes: 4 BF16 values with 8 wavefronts)
+  constexpr int PIECE = ((SPT * sizeof(E)) % 16 == 0) ? 16 : 8;
+  constexpr bool VEC = SITE % MF_NT == 0 && (SPT * sizeof(E)) % PIECE == 0 && CHI % SPT == 0;
+  constexpr int NQ = VEC ? int(SPT * sizeof(E) / PIECE) : 1;   // pieces per thread
+  typedef unsigned int u4 __attribute__((ext_vector_type(PIECE / 4)));
   E pf[SPT];
   u4 pq[NQ];
   auto load_site = [&](int r, int c) {

@@ -53,5 +53,5 @@ def test_rooflines_from_launch_times():
     e = 2.0 * 64 * 64 * 2 * 32 * 32 * 4 * 8 * 64
     assert abs(p["algorithmic_bytes_per_launch"] - (v + e)) < 1.0
     assert bench.proposals_per_wg("fp32", 64, 1000, 64) == 128
-    assert bench.proposals_per_wg("bf16", 64, 1000, 64) == 64
+    assert bench.proposals_per_wg("bf16", 64, 1000, 64) == 128
     assert bench.proposals_per_wg("fp32", 256, 1000, 256) == 64

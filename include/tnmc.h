@@ -125,7 +125,8 @@ tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tn
  * (1/2 if the sum is 0 or not finite), clamped to [1e-12, 1-1e-12]; s = +1 iff u < p+ with u
  * = draw c of the stream keyed (seed, 1) with counter words (r, first_proposal + k, id).
  * Outputs per (realization i, proposal k): d_spins [n][K][Lmax][W(Lmax)] words, d_logq [n][K]
- * (FP64 sum of ln p+ or ln(1-p+)), d_E [n][K] int32 exact energy (a5: E = 2U - N_B, U the number
+ * (FP64 sum of ln p+ or ln(1-p+), formed as the logarithm of the product of the conditionals with
+ * its binary exponent kept apart), d_E [n][K] int32 exact energy (a5: E = 2U - N_B, U the number
  * of unsatisfied bonds).  d_fallbacks (n uint32, device, may be NULL) counts sites where p+ fell
  * back to 1/2 (accumulated, not reset). */
 tnmc_status tnmc_propose(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,

@@ -138,43 +138,61 @@ def narrow_fraction(batch):
     return 1.0 - wide / max(1, tot)
 
 
+def disorder_strengths(w):
+    """The p values of a workload: one, or several sharing the coupling seeds (common random
+    numbers across p)."""
+    return list(w["ps"]) if "ps" in w else [w["p"]]
+
+
 def run_gpu(args, w=None):
+    """Steps one after the other on one stream (or replayed from one HIP graph).  A workload with
+    several disorder strengths runs every p in each step, one batch after the other, reusing
+    the same buffers."""
     import torch
     from paper_2409_06538_amd import binding
     import synth
 
     w = synth.WORKLOADS[args.workload] if w is None else w
     Ls, seeds = workload_sizes(w)
-    chi, p, K = w["chi"], w["p"], args.proposals or w["proposals"]
+    ps = disorder_strengths(w)
+    chi, K = w["chi"], args.proposals or w["proposals"]
     n = len(seeds)
-    beta = binding.nishimori_beta(p)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    b = binding.Batch(Ls, [beta] * n, seeds, chi, args.precision, K=K, device=dev)
+    b = binding.Batch(Ls, [binding.nishimori_beta(ps[0])] * n, seeds, chi, args.precision, K=K,
+                      device=dev)
     out = (torch.empty(b.spins_shape(K), dtype=torch.int64, device=dev),
            torch.empty((n, K), dtype=torch.float64, device=dev),
            torch.empty((n, K), dtype=torch.int32, device=dev))
     accum = torch.zeros((n, binding.OBS_COUNT), dtype=torch.float64, device=dev)
     chains = b.new_chains(1)
+    L2 = torch.tensor([L * L for L in Ls], dtype=torch.float64, device=dev)
     ev = []
 
     def step(events):
-        b.make_couplings(seeds, p)
-        if events is not None:
-            events[0].record()
-        b.build_env(want_lnZ=False)
-        if events is not None:
-            events[1].record()
-        b.propose(K, args.seed, first_proposal=0, out=out)
-        if events is not None:
-            events[2].record()
-        for t in (chains["spins"], chains["E"], chains["logq"], chains["init"]):
-            t.zero_()
-        acc, _ = b.accept(out, chains, seed=args.seed, accum=accum)
-        return acc
+        """One pass over every p; returns per-p [accepted, accepted x L^2] (device tensors)."""
+        sums = []
+        for j, p in enumerate(ps):
+            if len(ps) > 1:
+                b.set_betas([binding.nishimori_beta(p)] * n)
+            b.make_couplings(seeds, p)
+            if events is not None:
+                events[3 * j].record()
+            b.build_env(want_lnZ=False)
+            if events is not None:
+                events[3 * j + 1].record()
+            b.propose(K, args.seed, first_proposal=0, out=out)
+            if events is not None:
+                events[3 * j + 2].record()
+            for t in (chains["spins"], chains["E"], chains["logq"], chains["init"]):
+                t.zero_()
+            acc, _ = b.accept(out, chains, seed=args.seed, accum=accum)
+            per_real = acc.sum(dim=1, dtype=torch.float64)
+            sums.append(torch.stack([per_real.sum(), (per_real * L2).sum()]))
+        return torch.stack(sums)
 
     def new_events():
-        return [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        return [torch.cuda.Event(enable_timing=True) for _ in range(3 * len(ps))]
 
     for _ in range(max(1, args.warmup) if args.graph else args.warmup):
         e = new_events()
@@ -187,33 +205,31 @@ def run_gpu(args, w=None):
     if args.graph:
         graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(graph):
-            gacc = step(None)
+            gsums = step(None)
         torch.cuda.synchronize()
-    # accepted spin-updates of one step: per realization, accepted proposals x L^2
-    L2 = torch.tensor([L * L for L in Ls], dtype=torch.float64, device=dev)
     accs = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         if graph is not None:
             graph.replay()
-            acc = gacc
+            accs.append(gsums.clone())
         else:
             e = new_events()
-            acc = step(e)
+            accs.append(step(e))
             ev.append(e)
-        per_real = acc.sum(dim=1, dtype=torch.float64)
-        accs.append(torch.stack([per_real.sum(), (per_real * L2).sum()]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tot = torch.stack(accs).sum(dim=0).tolist()
-    accepted, updates = int(tot[0]), tot[1]
-    attempted = args.steps * n * (K - 1)
-    build_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / len(ev)
-    prop_ms = sum(e[1].elapsed_time(e[2]) for e in ev) / len(ev)
+    per_p = torch.stack(accs).sum(dim=0).tolist()            # [len(ps)][2]
+    accepted = int(sum(a for a, _ in per_p))
+    updates = sum(u for _, u in per_p)
+    attempted = args.steps * len(ps) * n * (K - 1)
+    nb = len(ev) * len(ps)
+    build_ms = sum(e[3 * j].elapsed_time(e[3 * j + 1]) for e in ev for j in range(len(ps))) / nb
+    prop_ms = sum(e[3 * j + 1].elapsed_time(e[3 * j + 2]) for e in ev for j in range(len(ps))) / nb
     wall = t1 - t0
     res = {
-        "Ls": sorted(set(Ls)), "chi": chi, "n": n, "K": K, "p": p, "beta": beta,
+        "Ls": sorted(set(Ls)), "chi": chi, "n": n, "K": K, "p": ps[0] if len(ps) == 1 else ps,
         "wall_s": wall, "ms_per_step": 1e3 * wall / args.steps,
         "value": updates / wall,
         "accepted": accepted, "attempted": attempted,
@@ -222,6 +238,10 @@ def run_gpu(args, w=None):
         "graph": bool(args.graph),
         "narrow_fraction": narrow_fraction(b),
     }
+    if len(ps) > 1:
+        res["acceptance_per_p"] = {str(p): per_p[j][0] / (args.steps * n * (K - 1))
+                                   for j, p in enumerate(ps)}
+        res["batches_per_step"] = len(ps)
     return add_rooflines(res, args, Ls)
 
 
@@ -498,7 +518,11 @@ def main():
     if args.sweep:
         run_sweep(args)
         return
-    serial = args.serial or args.graph
+    import synth
+    # overlapped steps keep depth + 1 batches resident; a workload with several disorder
+    # strengths runs its batches one after the other on one set of buffers instead
+    multi_p = len(disorder_strengths(synth.WORKLOADS[args.workload])) > 1
+    serial = args.serial or args.graph or multi_p
     res = run_gpu(args) if serial else run_gpu_pipelined(args)
     if not serial and not args.no_serial:
         # the same steps one after the other on one stream, for comparison
@@ -512,11 +536,15 @@ def main():
         calib_copy(args.calib_copy_mib)
     uniform = len(res["Ls"]) == 1
     L0 = res["Ls"][0]
-    # the FP64 plain form and the CPU oracle are measured on uniform-L workloads
-    plain = None if args.no_plain or not uniform else run_fp64_plain(args, L0, res["chi"], res["p"],
-                                                                     res["K"])
-    cpu = None if args.no_cpu or not uniform else run_cpu_baseline(L0, res["chi"], res["p"],
-                                                                   res["K"], args.seed)
+    p0 = res["p"][len(res["p"]) // 2] if multi_p else res["p"]
+    # the FP64 plain form and the CPU oracle are measured on uniform-L workloads with one
+    # disorder strength (the FP64 plain form where FP64 environments exist at this chi)
+    from paper_2409_06538_amd import binding
+    fp64_ok = bool(binding.load().tnmc_chi_supported(res["chi"], binding.PRECISIONS["fp64"]))
+    plain = None if args.no_plain or not uniform or not fp64_ok else \
+        run_fp64_plain(args, L0, res["chi"], p0, res["K"])
+    cpu = None if args.no_cpu or not uniform or multi_p else \
+        run_cpu_baseline(L0, res["chi"], p0, res["K"], args.seed)
     size = f"{L0}x{L0}" if uniform else "L x L (L in " + ", ".join(map(str, res["Ls"])) + ")"
     line = {
         "metric": METRIC,
@@ -532,8 +560,11 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {res['n']} realizations of the {size} open "
-                               f"+-J lattice, p={res['p']}, Nishimori beta, chi={res['chi']}, "
-                               f"{res['K']} proposals each, {args.precision} batched"
+                               + (f"+-J lattice for each p in {tuple(res['p'])} (the same coupling "
+                                  f"seeds, one batch per p), Nishimori beta, chi={res['chi']}, "
+                                  if multi_p else
+                                  f"+-J lattice, p={res['p']}, Nishimori beta, chi={res['chi']}, ")
+                               + f"{res['K']} proposals each, {args.precision} batched"
                                + (", one HIP graph per step" if res["graph"] else "")
                                + (f", consecutive steps overlapped (builds of the next "
                                   f"{res.get('builds_in_flight')} step(s) during the proposals of "
@@ -544,6 +575,7 @@ def main():
                    "builds_in_flight": res.get("builds_in_flight"),
                    "propose_cu_mask": res.get("propose_cu_mask")},
         "acceptance": res["acceptance"],
+        "acceptance_per_p": res.get("acceptance_per_p"),
         "accepted": res["accepted"],
         "attempted": res["attempted"],
         "build_ms": res["build_ms"],

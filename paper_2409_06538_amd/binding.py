@@ -137,6 +137,12 @@ class Batch:
         self.workspace = None
         self.ensure_workspace(K)
 
+    def set_betas(self, betas):
+        """Change the inverse temperature of every realization (the table is passed by value
+        on each call, so this takes effect from the next call on)."""
+        for i in range(self.n):
+            self.table[i].beta = float(betas[i])
+
     # -- workspace -------------------------------------------------------------------------
     def ensure_workspace(self, K):
         if K <= self.K and self.workspace is not None:

@@ -259,11 +259,11 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, FA fa, FB fb, FC fc) {
   }
 }
 
-// Householder reflector of column j from its owner group's registers m[] (rows > j are zeroed
-// by it): writes v (v_j = 1, zero above j) to vb, tau to taub, beta to diag[j].
+// Householder reflector from its owner group's registers m[], pivot row j (rows > j are zeroed
+// by it): writes v (v_j = 1, zero above j) to vb, tau to taub, beta to *dslot.
 template <typename T, int TPC, int RPT>
 __device__ __forceinline__ void make_reflector(const T (&m)[RPT], int j, int row0, int MQ, T* vb,
-                                               T* taub, T* diag, int part) {
+                                               T* taub, T* dslot, int part) {
   T sp[4] = {T(0), T(0), T(0), T(0)}, a = 0;
 #pragma unroll
   for (int t = 0; t < RPT; ++t) {
@@ -283,26 +283,59 @@ __device__ __forceinline__ void make_reflector(const T (&m)[RPT], int j, int row
   }
   if (part == 0) {
     *taub = tau;
-    diag[j] = beta;
+    *dslot = beta;
   }
 }
 
-// R factor of the register-resident M (R-only Householder QR), one barrier per column: after
-// applying reflector j, the owner of column j + 1 publishes reflector j + 1 into the other half
-// of the double buffer.  On return diag[] holds the diagonal of R; the strict upper triangle of
-// column g is m[t] at rows row0 + t < g.
+// Live-column numbering of the register-resident M (column g = tid / TPC): livek[g] = the rank
+// of column g among the nonzero columns (-1 for a zero column), *nlive = their count.  Columns
+// outside the bonds of the environment are exactly zero, so the QR below runs over the live
+// columns only.  Ends with a barrier.
 template <typename T, int CHI>
-__device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T* diag) {
+__device__ __forceinline__ void number_live_columns(const T (&m)[LeftCfg<CHI>::RPT], int* flag,
+                                                    int* livek, int* nlive) {
   using C = LeftCfg<CHI>;
-  constexpr int N2 = C::N2, MQ = C::MQ, TPC = C::TPC, RPT = C::RPT, VLD = C::VLD;
+  constexpr int N2 = C::N2, TPC = C::TPC, RPT = C::RPT;
+  static_assert(N2 <= 2 * WAVE, "two ballots number every column");
+  const int tid = threadIdx.x, g = tid / TPC, part = tid % TPC;
+  T nz = 0;
+#pragma unroll
+  for (int t = 0; t < RPT; ++t) nz += (m[t] != T(0)) ? T(1) : T(0);
+  nz = group_sum<TPC>(nz);
+  if (part == 0) flag[g] = nz > T(0);
+  __syncthreads();
+  if (tid < WAVE) {
+    const bool f0 = tid < N2 && flag[tid];
+    const bool f1 = tid + WAVE < N2 && flag[tid + WAVE];
+    const unsigned long long b0 = __ballot(f0), b1 = __ballot(f1);
+    const unsigned long long below = (tid == 0) ? 0ull : (~0ull >> (WAVE - tid));
+    if (tid < N2) livek[tid] = f0 ? __popcll(b0 & below) : -1;
+    if (tid + WAVE < N2) livek[tid + WAVE] = f1 ? __popcll(b0) + __popcll(b1 & below) : -1;
+    if (tid == 0) *nlive = __popcll(b0) + __popcll(b1);
+  }
+  __syncthreads();
+}
+
+// R factor of the register-resident M (R-only Householder QR) over its live columns, one
+// barrier per live column: after applying reflector k, the owner of live column k + 1 publishes
+// reflector k + 1 into the other half of the double buffer.  Live column g (live rank kg) ends
+// with its diagonal entry, at row kg, in diag[g] and the rows above it in m[t] (rows
+// row0 + t < kg); a zero column keeps m = 0 and gets diag[g] = 0.  The R rows are thus compact:
+// rows >= nlive are zero.
+template <typename T, int CHI>
+__device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T* diag, int kg,
+                                 int nlive) {
+  using C = LeftCfg<CHI>;
+  constexpr int MQ = C::MQ, TPC = C::TPC, RPT = C::RPT, VLD = C::VLD;
   const int tid = threadIdx.x;
   const int g = tid / TPC, part = tid % TPC, row0 = part * RPT;
-  if (g == 0) make_reflector<T, TPC, RPT>(m, 0, row0, MQ, vbuf, taub, diag, part);
+  if (kg < 0 && part == 0) diag[g] = T(0);
+  if (kg == 0) make_reflector<T, TPC, RPT>(m, 0, row0, MQ, vbuf, taub, diag + g, part);
   __syncthreads();
-  for (int j = 0; j < N2; ++j) {
-    const T* vj = vbuf + (j & 1) * VLD;
-    const T tau = taub[j & 1];
-    if (g > j) {
+  for (int k = 0; k < nlive; ++k) {
+    const T* vj = vbuf + (k & 1) * VLD;
+    const T tau = taub[k & 1];
+    if (kg > k) {
       // long slices re-read the reflector for the update instead of holding it in registers
       constexpr bool HOLD = RPT <= 32;
       T vv[HOLD ? RPT : 1];
@@ -321,9 +354,9 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
         if constexpr (HOLD) m[t] -= tw * vv[t];
         else m[t] -= tw * vj[row0 + t];
       }
-      if (g == j + 1)
-        make_reflector<T, TPC, RPT>(m, j + 1, row0, MQ, vbuf + ((j + 1) & 1) * VLD,
-                                    taub + ((j + 1) & 1), diag, part);
+      if (kg == k + 1)
+        make_reflector<T, TPC, RPT>(m, k + 1, row0, MQ, vbuf + ((k + 1) & 1) * VLD,
+                                    taub + ((k + 1) & 1), diag + g, part);
     }
     __syncthreads();
   }
@@ -851,9 +884,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       T* Rt = AsT + size_t(2) * CHI * LDAT;            // R~_b = sum_a wh(a,b) R_{c-1}[:, (a, .)]
       T* vbuf = Rt + size_t(2) * CHI * LDRT;           // 2 x VLD reflectors
       T* taub = vbuf + 2 * C::VLD;                     // 2 taus
-      const int g = tid / TPC, part = tid % TPC, row0 = part * RPT;
-      const int gb = g / CHI, gap = g % CHI;           // column g = (b, alpha')
       for (int c = 0; c < L - 1; ++c) {
+        fresh_tid();
+        const int g = tid / TPC, part = tid % TPC, row0 = part * RPT;
+        const int gb = g / CHI, gap = g % CHI;         // column g = (b, alpha')
         __syncthreads();
         for (int e = tid; e < int(site); e += NT) {
           const int b = e / (CHI * CHI), al = (e / CHI) % CHI, ap = e % CHI;
@@ -906,12 +940,14 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
 #pragma unroll
           for (int t = 0; t < RPT; ++t) m[t] = ((t & 1) ? w1 : w0) * d[t >> 1];
         }
-        householder_regs<T, CHI>(m, vbuf, taub, diag);
+        number_live_columns<T, CHI>(m, perm, ord, imisc + 6);
+        const int kg = ord[g];
+        householder_regs<T, CHI>(m, vbuf, taub, diag, kg, imisc[6]);
         // carry R with a power-of-two rescale; keep it for the second sweep
         T mx = 0;
 #pragma unroll
         for (int t = 0; t < RPT; ++t)
-          if (row0 + t < g) mx = fmax(mx, fabs(m[t]));
+          if (row0 + t < kg) mx = fmax(mx, fabs(m[t]));
         if (tid < N2) mx = fmax(mx, fabs(diag[tid]));
         mx = block_max<NT>(mx, red);
         const int e = pow2_exponent(mx);
@@ -923,7 +959,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         for (int t = 0; t < RPT; ++t) {
           const int rho = row0 + t;
           if (rho < N2) {
-            const T v = T(ldexp(rho < g ? m[t] : (rho == g ? dg : T(0)), -e));
+            const T v = T(ldexp(rho < kg ? m[t] : (rho == kg ? dg : T(0)), -e));
             bufR[g * LDT + rho] = v;
             rdst[rho] = v;
           }

@@ -260,14 +260,15 @@ __device__ __forceinline__ void gemm_tiles(int M, int N, FA fa, FB fb, FC fc) {
 }
 
 // Householder reflector from its owner group's registers m[], pivot row j (rows > j are zeroed
-// by it): writes v (v_j = 1, zero above j) to vb, tau to taub, beta to *dslot.
-template <typename T, int TPC, int RPT>
-__device__ __forceinline__ void make_reflector(const T (&m)[RPT], int j, int row0, int MQ, T* vb,
-                                               T* taub, T* dslot, int part) {
+// by it): writes v (v_j = 1, zero above j) to vb, tau to taub, beta to *dslot.  Thread `part`
+// of the group holds rows part + TPC t; only t < RL can be nonzero.
+template <typename T, int TPC, int RPT, int RL>
+__device__ __forceinline__ void make_reflector(const T (&m)[RPT], int j, int part, int MQ, T* vb,
+                                               T* taub, T* dslot) {
   T sp[4] = {T(0), T(0), T(0), T(0)}, a = 0;
 #pragma unroll
-  for (int t = 0; t < RPT; ++t) {
-    const int rho = row0 + t;
+  for (int t = 0; t < RL; ++t) {
+    const int rho = part + TPC * t;
     sp[t & 3] += (rho > j) ? m[t] * m[t] : T(0);
     a += (rho == j) ? m[t] : T(0);
   }
@@ -277,8 +278,8 @@ __device__ __forceinline__ void make_reflector(const T (&m)[RPT], int j, int row
   T tau = 0, beta = a, scal = 0;
   if (s > T(0)) hh_params(a, s, beta, tau, scal);
 #pragma unroll
-  for (int t = 0; t < RPT; ++t) {
-    const int rho = row0 + t;
+  for (int t = 0; t < RL; ++t) {
+    const int rho = part + TPC * t;
     vb[rho] = (rho > j && rho < MQ) ? m[t] * scal : (rho == j ? T(1) : T(0));
   }
   if (part == 0) {
@@ -317,32 +318,35 @@ __device__ __forceinline__ void number_live_columns(const T (&m)[LeftCfg<CHI>::R
 }
 
 // R factor of the register-resident M (R-only Householder QR) over its live columns, one
-// barrier per live column: after applying reflector k, the owner of live column k + 1 publishes
-// reflector k + 1 into the other half of the double buffer.  Live column g (live rank kg) ends
-// with its diagonal entry, at row kg, in diag[g] and the rows above it in m[t] (rows
-// row0 + t < kg); a zero column keeps m = 0 and gets diag[g] = 0.  The R rows are thus compact:
-// rows >= nlive are zero.
-template <typename T, int CHI>
+// barrier per reflector: after applying reflector k, the owner of live column k + 1 publishes
+// reflector k + 1 into the other half of the double buffer.  Thread `part` of the group owning
+// column g holds rows part + TPC t of it; rows >= TPC RL are zero, and so are the rows >= kmax
+// once a column has seen every reflector: kmax = min(live columns, nonzero rows) reflectors are
+// needed.  Live column g (live rank kg) ends with its diagonal entry (row kg) in diag[g] and the
+// rows above it in m[]; a zero column, or one with kg >= kmax, gets diag[g] = 0.  The R rows
+// are thus compact: rows >= kmax are zero.
+template <typename T, int CHI, int RL>
 __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T* diag, int kg,
-                                 int nlive) {
+                                 int kmax) {
   using C = LeftCfg<CHI>;
   constexpr int MQ = C::MQ, TPC = C::TPC, RPT = C::RPT, VLD = C::VLD;
+  static_assert(RL <= RPT && TPC * RL <= VLD, "live rows fit the reflector buffer");
   const int tid = threadIdx.x;
-  const int g = tid / TPC, part = tid % TPC, row0 = part * RPT;
-  if (kg < 0 && part == 0) diag[g] = T(0);
-  if (kg == 0) make_reflector<T, TPC, RPT>(m, 0, row0, MQ, vbuf, taub, diag + g, part);
+  const int g = tid / TPC, part = tid % TPC;
+  if ((kg < 0 || kg >= kmax) && part == 0) diag[g] = T(0);
+  if (kg == 0 && kmax > 0) make_reflector<T, TPC, RPT, RL>(m, 0, part, MQ, vbuf, taub, diag + g);
   __syncthreads();
-  for (int k = 0; k < nlive; ++k) {
+  for (int k = 0; k < kmax; ++k) {
     const T* vj = vbuf + (k & 1) * VLD;
     const T tau = taub[k & 1];
     if (kg > k) {
       // long slices re-read the reflector for the update instead of holding it in registers
-      constexpr bool HOLD = RPT <= 32;
-      T vv[HOLD ? RPT : 1];
+      constexpr bool HOLD = RL <= 32;
+      T vv[HOLD ? RL : 1];
       T wp[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
-      for (int t = 0; t < RPT; ++t) {
-        const T x = vj[row0 + t];
+      for (int t = 0; t < RL; ++t) {
+        const T x = vj[part + TPC * t];
         if constexpr (HOLD) vv[t] = x;
         wp[t & 3] += x * m[t];
       }
@@ -350,13 +354,13 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
       w = group_sum<TPC>(w);
       const T tw = tau * w;
 #pragma unroll
-      for (int t = 0; t < RPT; ++t) {
+      for (int t = 0; t < RL; ++t) {
         if constexpr (HOLD) m[t] -= tw * vv[t];
-        else m[t] -= tw * vj[row0 + t];
+        else m[t] -= tw * vj[part + TPC * t];
       }
-      if (kg == k + 1)
-        make_reflector<T, TPC, RPT>(m, k + 1, row0, MQ, vbuf + ((k + 1) & 1) * VLD,
-                                    taub + ((k + 1) & 1), diag + g, part);
+      if (kg == k + 1 && k + 1 < kmax)
+        make_reflector<T, TPC, RPT, RL>(m, k + 1, part, MQ, vbuf + ((k + 1) & 1) * VLD,
+                                        taub + ((k + 1) & 1), diag + g);
     }
     __syncthreads();
   }
@@ -884,9 +888,12 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       T* Rt = AsT + size_t(2) * CHI * LDAT;            // R~_b = sum_a wh(a,b) R_{c-1}[:, (a, .)]
       T* vbuf = Rt + size_t(2) * CHI * LDRT;           // 2 x VLD reflectors
       T* taub = vbuf + 2 * C::VLD;                     // 2 taus
+      // rows per thread that can be nonzero: a quarter, half or all of RPT
+      constexpr int RQ = RPT / 4 > 0 ? RPT / 4 : 1, RH = RPT / 2 > 0 ? RPT / 2 : 1;
+      int kprev = 0;                                   // nonzero rows of R_{c-1}
       for (int c = 0; c < L - 1; ++c) {
         fresh_tid();
-        const int g = tid / TPC, part = tid % TPC, row0 = part * RPT;
+        const int g = tid / TPC, part = tid % TPC;
         const int gb = g / CHI, gap = g % CHI;         // column g = (b, alpha')
         __syncthreads();
         for (int e = tid; e < int(site); e += NT) {
@@ -899,8 +906,10 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           for (int a = 0; a < 2; ++a)
 #pragma unroll
             for (int b = 0; b < 2; ++b) wh2[a][b] = bond_weight<T>(jh, c - 1, a, b, ep, em);
-          for (int o = tid; o < 2 * CHI * N2; o += NT) {
-            const int b = o / (CHI * N2), al = (o / N2) % CHI, i = o % N2;
+          // only the columns (a, al < bdin[c]) of R_{c-1} can be nonzero
+          const int nal = bdin[c];
+          for (int o = tid; o < 2 * nal * N2; o += NT) {
+            const int b = o / (nal * N2), al = (o / N2) % nal, i = o % N2;
             Rt[(b * CHI + al) * LDRT + i] =
                 wh2[0][b] * bufR[al * LDT + i] + wh2[1][b] * bufR[(CHI + al) * LDT + i];
           }
@@ -908,46 +917,58 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         __syncthreads();
         const T w0 = bond_weight<T>(jv, c, 0, gb, ep, em);
         const T w1 = bond_weight<T>(jv, c, 1, gb, ep, em);
+        const T wx = (part & 1) ? w1 : w0;             // rows part + TPC t all have x = part & 1
         const T* acol = AsT + (gb * CHI + gap) * LDAT;   // A[b][.][ap]
+        // M_c rows (i, x): at site 0, i is the left bond of E_r (dimension bdin[0] = 1); after
+        // that, i runs over the nonzero rows of R_{c-1}
+        const int nrows = (c == 0) ? 2 * int(bdin[0]) : 2 * kprev;
+        const int tl = (nrows + TPC - 1) / TPC;
+        const int alim = bdin[c];
         T m[RPT];
-        if (c == 0 || (RPT & 1)) {
-          // site 0 has no left bond: rows (i, x) with i the bond index of E_r (< CHI)
+        auto site_qr = [&](auto rlc, T (&m)[RPT]) __attribute__((always_inline)) {
+          constexpr int RL = decltype(rlc)::value;
 #pragma unroll
-          for (int t = 0; t < RPT; ++t) {
-            const int rho = row0 + t, i = rho >> 1;
-            T d = 0;
-            if (c == 0) {
-              d = (i < CHI) ? acol[i < CHI ? i : 0] : T(0);
-            } else if (rho < MQ) {
-              const T* rcol = Rt + size_t(gb) * CHI * LDRT + i;
-              for (int al = 0; al < CHI; ++al) d += rcol[al * LDRT] * acol[al];
+          for (int t = 0; t < RPT; ++t) m[t] = T(0);
+          if (c == 0) {
+#pragma unroll
+            for (int t = 0; t < RL; ++t) {
+              const int rho = part + TPC * t, i = rho >> 1;
+              m[t] = (rho < MQ && i < CHI) ? wx * acol[i < CHI ? i : 0] : T(0);
             }
-            m[t] = (rho < MQ) ? ((rho & 1) ? w1 : w0) * d : T(0);
+          } else {
+            const T* rb = Rt + size_t(gb) * CHI * LDRT + (part >> 1);
+            // eight rows at a time over the bond, so that few loads are in flight
+            constexpr int CH = RL < 8 ? RL : 8;
+#pragma unroll
+            for (int t0 = 0; t0 < RL; t0 += CH) {
+              for (int al = 0; al < alim; ++al) {
+                const T a = acol[al];
+                const T* rr = rb + al * LDRT;
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                  const int t = t0 + u;
+                  if (t < RL && part + TPC * t < MQ) m[t] += rr[(TPC / 2) * t] * a;
+                }
+              }
+            }
+#pragma unroll
+            for (int t = 0; t < RL; ++t) m[t] *= wx;
           }
-        } else {
-          constexpr int IPT = RPT / 2 > 0 ? RPT / 2 : 1;
-          const int i0 = row0 / 2;
-          T d[IPT];
-#pragma unroll
-          for (int u = 0; u < IPT; ++u) d[u] = T(0);
-          const T* rrow = Rt + size_t(gb) * CHI * LDRT + i0;
-#pragma unroll 4
-          for (int al = 0; al < CHI; ++al) {
-            const T a = acol[al];
-#pragma unroll
-            for (int u = 0; u < IPT; ++u) d[u] += rrow[al * LDRT + u] * a;
-          }
-#pragma unroll
-          for (int t = 0; t < RPT; ++t) m[t] = ((t & 1) ? w1 : w0) * d[t >> 1];
-        }
-        number_live_columns<T, CHI>(m, perm, ord, imisc + 6);
+          number_live_columns<T, CHI>(m, perm, ord, imisc + 6);
+          const int kmax = imisc[6] < nrows ? imisc[6] : nrows;
+          householder_regs<T, CHI, RL>(m, vbuf, taub, diag, ord[g], kmax);
+          return kmax;
+        };
+        const int kmax = (tl <= RQ) ? site_qr(std::integral_constant<int, RQ>{}, m)
+                         : (tl <= RH) ? site_qr(std::integral_constant<int, RH>{}, m)
+                                      : site_qr(std::integral_constant<int, RPT>{}, m);
         const int kg = ord[g];
-        householder_regs<T, CHI>(m, vbuf, taub, diag, kg, imisc[6]);
+        kprev = kmax;
         // carry R with a power-of-two rescale; keep it for the second sweep
         T mx = 0;
 #pragma unroll
         for (int t = 0; t < RPT; ++t)
-          if (row0 + t < kg) mx = fmax(mx, fabs(m[t]));
+          if (part + TPC * t < kg) mx = fmax(mx, fabs(m[t]));
         if (tid < N2) mx = fmax(mx, fabs(diag[tid]));
         mx = block_max<NT>(mx, red);
         const int e = pow2_exponent(mx);
@@ -957,7 +978,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         const T dg = diag[g];
 #pragma unroll
         for (int t = 0; t < RPT; ++t) {
-          const int rho = row0 + t;
+          const int rho = part + TPC * t;
           if (rho < N2) {
             const T v = T(ldexp(rho < kg ? m[t] : (rho == kg ? dg : T(0)), -e));
             bufR[g * LDT + rho] = v;

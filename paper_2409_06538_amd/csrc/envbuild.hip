@@ -366,12 +366,10 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
   }
 }
 
-// Orthonormalise rows 0..k-1 of V (CHI x N2, row-major, ld LDVR) in place by modified Gram-Schmidt
-// applied PASSES times, one barrier per row.  A group of TPP threads owns one row.  A row whose residual
-// norm^2 falls below eta (the rows start with unit norm) lies in the span of the earlier rows to
-// rounding and is set to zero; the span of the others is unchanged.
-// One pass of modified Gram-Schmidt on rows 0..k-1 of V taking the rows two at a time, one
-// barrier per pair: with rows a and c = a+1 as they stand at the start of the step,
+// Orthonormalises rows 0..k-1 of V (CHI x N2, row-major, ld LDVR) in place, a group of TPP threads
+// per row; the rows start with unit norm, and a row whose residual norm^2 falls below eta lies in
+// the span of the earlier rows to rounding.  One pass of modified Gram-Schmidt taking the rows two
+// at a time, one barrier per pair: with rows a and c = a+1 as they stand at the start of the step,
 // c' = c - (<c,a>/<a,a>) a, and every later row b subtracts its projections on a and c', formed
 // from <b,a>, <b,c>, <a,a>, <c,a>, <c,c>.  Rows whose residual norm^2 falls below eta are set to
 // zero; the rows are normalised at the end.  Only the 2 KW columns (x, be < KW), at x CHI + be,
@@ -461,62 +459,6 @@ __device__ void mgs_pairs_rows(T* V, int k, T eta) {
     }
   }
   __syncthreads();
-}
-
-template <typename T, int CHI, int NT, int PASSES, int LDVR>
-__device__ void mgs2_rows(T* V, int k, T eta) {
-  constexpr int N2 = 2 * CHI, TPP = env_tpp(CHI), EPR = (N2 + TPP - 1) / TPP;
-  const int grp = threadIdx.x / TPP, l = threadIdx.x % TPP;
-  const bool mine = grp < k;
-  T vb[EPR];
-  __syncthreads();
-#pragma unroll
-  for (int e = 0; e < EPR; ++e) {
-    const int j = l + TPP * e;
-    vb[e] = (mine && j < N2) ? V[grp * LDVR + j] : T(0);
-  }
-  for (int pass = 0; pass < PASSES; ++pass) {
-    for (int a = 0; a < k; ++a) {
-      T va[EPR];
-      T n2 = 0, d = 0;
-#pragma unroll
-      for (int e = 0; e < EPR; ++e) {
-        const int j = l + TPP * e;
-        const T ra = V[a * LDVR + (j < N2 ? j : 0)];
-        va[e] = (mine && grp >= a && j < N2) ? (grp == a ? vb[e] : ra) : T(0);
-        n2 += va[e] * va[e];
-        d += va[e] * vb[e];
-      }
-      n2 = group_sum<TPP>(n2);
-      d = group_sum<TPP>(d);
-      if (mine && grp > a && n2 > eta) {
-        const T f = d * fast_rcp(n2);
-#pragma unroll
-        for (int e = 0; e < EPR; ++e) {
-          const int j = l + TPP * e;
-          vb[e] -= f * va[e];
-          if (j < N2) V[grp * LDVR + j] = vb[e];
-        }
-      }
-      if (mine && grp == a && !(n2 > eta)) {
-#pragma unroll
-        for (int e = 0; e < EPR; ++e) vb[e] = T(0);
-      }
-      __syncthreads();
-    }
-    T n2 = 0;
-#pragma unroll
-    for (int e = 0; e < EPR; ++e) n2 += vb[e] * vb[e];
-    n2 = group_sum<TPP>(n2);
-    const T f = (n2 > T(0)) ? T(1) / sqrt(n2) : T(0);
-#pragma unroll
-    for (int e = 0; e < EPR; ++e) {
-      const int j = l + TPP * e;
-      vb[e] *= f;
-      if (mine && j < N2) V[grp * LDVR + j] = vb[e];
-    }
-    __syncthreads();
-  }
 }
 
 // T: arithmetic type; E: storage type of the environments.  GRAM selects the Gram form of both
@@ -973,7 +915,8 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         mx = block_max<NT>(mx, red);
         const int e = pow2_exponent(mx);
         log2acc += e;
-        if (tid == 0) rexp[c] = e;
+        // exponent and the number of nonzero rows of R_c (< 256), packed: 256 e + kmax
+        if (tid == 0) rexp[c] = e * 256 + kmax;
         gmem<T>* rdst = rs + size_t(c) * N2 * N2 + size_t(g) * N2;
         const T dg = diag[g];
 #pragma unroll
@@ -1304,110 +1247,129 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           }
           __syncthreads();
         } else {
-          // R_{c-1} into bufR, then T = R_{c-1} Z
+          // R_{c-1} into bufR, then T = R_{c-1} Z.  Rows >= nrT of R_{c-1} are zero, and so
+          // are those of T: the product and the pivoted QR below run over TPC RL2 >= nrT rows.
+          const int nrT = rexp[c - 1] & 255;
+          constexpr int RPT2 = (N2 + TPC - 1) / TPC;
+          constexpr int R2Q = RPT2 / 4 > 0 ? RPT2 / 4 : 1, R2H = RPT2 / 2 > 0 ? RPT2 / 2 : 1;
+          const int tl2 = (nrT + TPC - 1) / TPC;
+          const int rl2 = (tl2 <= R2Q) ? R2Q : (tl2 <= R2H) ? R2H : RPT2;
+          const int mrows = (TPC * rl2 < N2) ? TPC * rl2 : N2;
           const gmem<T>* rsrc = rs + size_t(c - 1) * N2 * N2;
-          for (int o = tid; o < N2 * N2; o += NT) bufR[(o / N2) * LDT + (o % N2)] = rsrc[o];
+          for (int o = tid; o < N2 * mrows; o += NT) {
+            const int col = o / mrows, i = o % mrows;
+            bufR[col * LDT + i] = rsrc[size_t(col) * N2 + i];
+          }
           __syncthreads();
           auto ta = [&](int i, int a) { return bufR[a * LDT + i]; };
           auto tb = [&](int a, int col) { return Zr[a * LDZ + col]; };
           auto tc = [&](int i, int col, T v) { Tw[col * LDT + i] = v; };
           if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ta, tb, tc);
-          else gemm_tiles<TL, TL, N2, NT, T>(N2, N2, ta, tb, tc);
+          else gemm_tiles<TL, TL, N2, NT, T>((mrows + TL - 1) / TL * TL, N2, ta, tb, tc);
           __syncthreads();
 
           // ---- QR with column pivoting, stopping at the numerical rank ----
-          // Group g (TPC threads) owns physical column g; thread part keeps rows [part * RPT2, +RPT2)
-          // in registers and republishes them in Tw after each update, so that every thread reads the
-          // next pivot column from LDS and forms its reflector itself (one barrier per column).
-          constexpr int RPT2 = (N2 + TPC - 1) / TPC;
-          const int g = tid / TPC, part = tid % TPC, row0 = part * RPT2;
+          // Group g (TPC threads) owns physical column g; thread part keeps rows part + TPC t
+          // (t < RL2) in registers and republishes them in Tw after each update, so that every
+          // thread reads the next pivot column from LDS and forms its reflector itself (one
+          // barrier per column).
+          const int g = tid / TPC, part = tid % TPC;
           const bool owner = g < N2;
           bool active = owner;
-          T mc[RPT2];
-          T cn = 0;
-          {
-            T cp[4] = {T(0), T(0), T(0), T(0)};
-    #pragma unroll
-            for (int t = 0; t < RPT2; ++t) {
-              const int rho = row0 + t;
-              mc[t] = (owner && rho < N2) ? Tw[g * LDT + rho] : T(0);
-              cp[t & 3] += mc[t] * mc[t];
-            }
-            cn = group_sum<TPC>((cp[0] + cp[1]) + (cp[2] + cp[3]));
-          }
-          {
-            T bv = owner ? cn : T(-1);
-            int bi = owner ? g : N2;
-            wave_argmax(bv, bi);
-            if ((tid & (WAVE - 1)) == 0) { candv[tid / WAVE] = bv; candi[tid / WAVE] = bi; }
-          }
-          fro2 = block_sum<NT>((owner && part == 0) ? cn : T(0), red);
-          const T tolr2 = T(Tol::rank) * T(Tol::rank) * fro2;
-          rank = N2;
-          for (int j = 0; j < N2; ++j) {
-            const int buf = j & 1;
-            // arg-max of the per-wave candidates (ties -> smaller column), without branches
-            T cv[NW];
-            int ci[NW];
-    #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-              cv[w] = candv[buf * NW + w];
-              ci[w] = candi[buf * NW + w];
-            }
-            T best = cv[0];
-            int piv = ci[0];
-    #pragma unroll
-            for (int w = 1; w < NW; ++w) {
-              const bool better = (cv[w] > best) | ((cv[w] == best) & (ci[w] < piv));
-              best = better ? cv[w] : best;
-              piv = better ? ci[w] : piv;
-            }
-            if (!(best > tolr2)) { rank = j; break; }
-            const T* pc = Tw + piv * LDT;
-            const T alpha = pc[j];
-            const T ss = fmax(best - alpha * alpha, T(0));
-            T tau = 0, beta = alpha, scal = 0;
-            if (ss > T(0)) hh_params(alpha, ss, beta, tau, scal);
-            if (tid == 0) { diag[j] = beta; perm[j] = piv; }
-            if (g == piv) active = false;
-            T v[RPT2];
-            T wp[4] = {T(0), T(0), T(0), T(0)};
-            // loads first and unconditional (a select on the loaded value would let the compiler
-            // move each load under its own branch and wait for it there)
-    #pragma unroll
-            for (int t = 0; t < RPT2; ++t) v[t] = pc[(N2 % TPC == 0 || row0 + t < N2) ? row0 + t : 0];
-    #pragma unroll
-            for (int t = 0; t < RPT2; ++t) {
-              const int rho = row0 + t;
-              const T sg = (rho > j && rho < N2) ? scal : T(0);
-              const T one = (rho == j) ? T(1) : T(0);
-              v[t] = v[t] * sg + one;
-              wp[t & 3] += v[t] * mc[t];
-            }
-            const T w = group_sum<TPC>((wp[0] + wp[1]) + (wp[2] + wp[3]));
-            T np[4] = {T(0), T(0), T(0), T(0)};
-            if (active) {
-              const T tw = tau * w;
-    #pragma unroll
-              for (int t = 0; t < RPT2; ++t) {
-                const int rho = row0 + t;
-                mc[t] -= tw * v[t];
-                np[t & 3] += (rho > j) ? mc[t] * mc[t] : T(0);
-                if (N2 % TPC == 0 || rho < N2) Tw[g * LDT + rho] = mc[t];
-              }
-            }
-            const T nn = group_sum<TPC>((np[0] + np[1]) + (np[2] + np[3]));
+          auto qrcp = [&](auto rlc) __attribute__((always_inline)) {
+            constexpr int RL2 = decltype(rlc)::value;
+            T mc[RL2];
+            T cn = 0;
             {
-              T bv = active ? nn : T(-1);
-              int bi = active ? g : N2;
-              wave_argmax(bv, bi);
-              if ((tid & (WAVE - 1)) == 0) {
-                candv[(buf ^ 1) * NW + tid / WAVE] = bv;
-                candi[(buf ^ 1) * NW + tid / WAVE] = bi;
+              T cp[4] = {T(0), T(0), T(0), T(0)};
+    #pragma unroll
+              for (int t = 0; t < RL2; ++t) {
+                const int rho = part + TPC * t;
+                mc[t] = (owner && rho < N2) ? Tw[g * LDT + rho] : T(0);
+                cp[t & 3] += mc[t] * mc[t];
               }
+              cn = group_sum<TPC>((cp[0] + cp[1]) + (cp[2] + cp[3]));
             }
-            __syncthreads();
-          }
+            {
+              T bv = owner ? cn : T(-1);
+              int bi = owner ? g : N2;
+              wave_argmax(bv, bi);
+              if ((tid & (WAVE - 1)) == 0) { candv[tid / WAVE] = bv; candi[tid / WAVE] = bi; }
+            }
+            fro2 = block_sum<NT>((owner && part == 0) ? cn : T(0), red);
+            const T tolr2 = T(Tol::rank) * T(Tol::rank) * fro2;
+            rank = N2;
+            for (int j = 0; j < N2; ++j) {
+              const int buf = j & 1;
+              // arg-max of the per-wave candidates (ties -> smaller column), without branches
+              T cv[NW];
+              int ci[NW];
+    #pragma unroll
+              for (int w = 0; w < NW; ++w) {
+                cv[w] = candv[buf * NW + w];
+                ci[w] = candi[buf * NW + w];
+              }
+              T best = cv[0];
+              int piv = ci[0];
+    #pragma unroll
+              for (int w = 1; w < NW; ++w) {
+                const bool better = (cv[w] > best) | ((cv[w] == best) & (ci[w] < piv));
+                best = better ? cv[w] : best;
+                piv = better ? ci[w] : piv;
+              }
+              if (!(best > tolr2)) { rank = j; break; }
+              const T* pc = Tw + piv * LDT;
+              const T alpha = pc[j];
+              const T ss = fmax(best - alpha * alpha, T(0));
+              T tau = 0, beta = alpha, scal = 0;
+              if (ss > T(0)) hh_params(alpha, ss, beta, tau, scal);
+              if (tid == 0) { diag[j] = beta; perm[j] = piv; }
+              if (g == piv) active = false;
+              T v[RL2];
+              T wp[4] = {T(0), T(0), T(0), T(0)};
+              // loads first and unconditional (a select on the loaded value would let the
+              // compiler move each load under its own branch and wait for it there)
+    #pragma unroll
+              for (int t = 0; t < RL2; ++t) {
+                const int rho = part + TPC * t;
+                v[t] = pc[(N2 % TPC == 0 || rho < N2) ? rho : 0];
+              }
+    #pragma unroll
+              for (int t = 0; t < RL2; ++t) {
+                const int rho = part + TPC * t;
+                const T sg = (rho > j && rho < N2) ? scal : T(0);
+                const T one = (rho == j) ? T(1) : T(0);
+                v[t] = v[t] * sg + one;
+                wp[t & 3] += v[t] * mc[t];
+              }
+              const T w = group_sum<TPC>((wp[0] + wp[1]) + (wp[2] + wp[3]));
+              T np[4] = {T(0), T(0), T(0), T(0)};
+              if (active) {
+                const T tw = tau * w;
+    #pragma unroll
+                for (int t = 0; t < RL2; ++t) {
+                  const int rho = part + TPC * t;
+                  mc[t] -= tw * v[t];
+                  np[t & 3] += (rho > j) ? mc[t] * mc[t] : T(0);
+                  if (N2 % TPC == 0 || rho < N2) Tw[g * LDT + rho] = mc[t];
+                }
+              }
+              const T nn = group_sum<TPC>((np[0] + np[1]) + (np[2] + np[3]));
+              {
+                T bv = active ? nn : T(-1);
+                int bi = active ? g : N2;
+                wave_argmax(bv, bi);
+                if ((tid & (WAVE - 1)) == 0) {
+                  candv[(buf ^ 1) * NW + tid / WAVE] = bv;
+                  candi[(buf ^ 1) * NW + tid / WAVE] = bi;
+                }
+              }
+              __syncthreads();
+            }
+          };
+          if (rl2 == R2Q) qrcp(std::integral_constant<int, R2Q>{});
+          else if (rl2 == R2H) qrcp(std::integral_constant<int, R2H>{});
+          else qrcp(std::integral_constant<int, RPT2>{});
           // columns never picked follow the pivots in ascending order
           if (owner && part == 0) unpk[g] = active ? 1 : 0;
           __syncthreads();
@@ -1527,16 +1489,21 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         // kept rows orthonormal (span unchanged)
         // One pass suffices in the Gram form: the rows come from a pivoted Cholesky factor whose
         // conditioning is bounded by the FP32 rank tolerance, so FP64 Gram-Schmidt leaves them
-        // orthonormal to ~1e-10; FP64 environments need the second pass.
+        // orthonormal to ~1e-10; the QR form (FP64 environments, and FP32 arithmetic at
+        // chi = 48) takes a second pass.
         if constexpr (GRAM) mgs_pairs_rows<T, CHI, NT, LDV, KW, (KW <= 16 ? 8 : TPP)>(bufS, kept, T(Tol::eta));
-        else mgs2_rows<T, CHI, NT, 2, LDV>(bufS, kept, T(Tol::eta));
+        else {
+          // two passes, the rows taken two at a time (one barrier per pair)
+          mgs_pairs_rows<T, CHI, NT, LDV>(bufS, kept, T(Tol::eta));
+          mgs_pairs_rows<T, CHI, NT, LDV>(bufS, kept, T(Tol::eta));
+        }
         gmem<E>* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
         for (int o = tid; o < int(site); o += NT) {
           const int x = o / (CHI * CHI), al = (o / CHI) % CHI, be = o % CHI;
           gst<E>(bout, o, narrow<E>(bufS[al * LDV + x * CHI + be]));
         }
         // Xt_c = 2^-e_{c-1} Z V^T (N2 x CHI, column-major in bufR), then a power-of-two rescale
-        const int ec = rexp[c - 1];
+        const int ec = GRAM ? rexp[c - 1] : (rexp[c - 1] >> 8);
         T mx = 0;
         {
           auto xa = [&](int j, int col) { return Zr[j * LDZ + col]; };

@@ -155,6 +155,35 @@ __device__ __forceinline__ void mfma_gemm_f64(FA fa, FB fb, FC fc) {
   }
 }
 
+// C (M x N) = A (M x K) B (K x N) in FP32 on 16x16x4 matrix-core tiles (M, N multiples of 16,
+// K of 16), over the first `tm` row tiles only (rows >= 16 tm are not written).  Lane
+// (i, q) = (lane % 16, lane / 16) feeds A(i, k0 + q) and B(k0 + q, j) and receives rows 4 q + r of
+// column i of its tile (the FP32 instruction orders its results unlike the FP64 one).
+template <int M, int N, int K, int NT, typename FA, typename FB, typename FC>
+__device__ __forceinline__ void mfma_gemm_f32(FA fa, FB fb, FC fc, int tm = M / 16) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  static_assert(M % 16 == 0 && N % 16 == 0 && K % 16 == 0, "matrix-core tile shapes");
+  constexpr int TN = N / 16, NWV = NT / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i16 = lane & 15, q = lane >> 4;
+  for (int t = wv; t < tm * TN; t += NWV) {
+    const int r0 = (t % tm) * 16, c0 = (t / tm) * 16;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      float a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = fa(r0 + i16, k0 + 4 * u + q);
+        b[u] = fb(k0 + 4 * u + q, c0 + i16);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fc(r0 + 4 * q + r, c0 + i16, acc[r]);
+  }
+}
+
 // BATCH independent products C_b = A_b B_b of the shapes above in one tile loop, so that all
 // wavefronts share the tiles of all products.  fa(b, i, k), fb(b, k, j), fc(b, i, j, v).
 template <int BATCH, int M, int N, int K, int NT, typename FA, typename FB, typename FC>
@@ -471,6 +500,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   using Tol = JacobiTol<typename TolOf<E>::type>;
   // FP64 products on matrix-core tiles where the shapes allow
   constexpr bool MF64 = std::is_same<T, double>::value && CHI % 16 == 0;
+  constexpr bool MF32 = std::is_same<T, float>::value && CHI % 16 == 0;
   using S = EnvSmem<T, CHI>;
   constexpr int N2 = S::N2, MQ = S::MQ, LDT = S::LDT, LDZ = S::LDZ;
   constexpr int LDA_S = S::LDA_S, LDV = S::LDV;
@@ -1032,6 +1062,33 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
                       wh[a][0] * wv[x][0] * p0[rr] + wh[a][1] * wv[x][1] * p1[rr];
             }
           }
+        } else if constexpr (MF32) {
+          // the same on 16x16x4 FP32 matrix-core tiles (results in rows 4 q + r)
+          typedef float v4f __attribute__((ext_vector_type(4)));
+          constexpr int TT = KW / 16;
+          const int lane = tid & 63, wvi = tid >> 6, i16 = lane & 15, qg = lane >> 4;
+          for (int t = wvi; t < TT * TT; t += NW) {
+            const int r0 = (t % TT) * 16, c0 = (t / TT) * 16;
+            v4f p0 = {0.f, 0.f, 0.f, 0.f}, p1 = {0.f, 0.f, 0.f, 0.f};
+  #pragma unroll
+            for (int k0 = 0; k0 < KW; k0 += 4) {
+              const int k = k0 + qg;
+              const float a0 = bufS[(r0 + i16) * LDA_S + k], a1 = bufS[(CHI + r0 + i16) * LDA_S + k];
+              const float x0 = bufR[(c0 + i16) * LDT + k], x1 = bufR[(c0 + i16) * LDT + CHI + k];
+              p0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, x0, p0, 0, 0, 0);
+              p1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, x1, p1, 0, 0, 0);
+            }
+  #pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+              const int al = r0 + 4 * qg + rr, be = c0 + i16;
+  #pragma unroll
+              for (int a = 0; a < 2; ++a)
+  #pragma unroll
+                for (int x = 0; x < 2; ++x)
+                  Zr[(a * KW + al) * LDZ + x * KW + be] =
+                      wh[a][0] * wv[x][0] * p0[rr] + wh[a][1] * wv[x][1] * p1[rr];
+            }
+          }
         } else
         {
           constexpr int tm = CHI / TL;
@@ -1265,6 +1322,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           auto tb = [&](int a, int col) { return Zr[a * LDZ + col]; };
           auto tc = [&](int i, int col, T v) { Tw[col * LDT + i] = v; };
           if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ta, tb, tc);
+          else if constexpr (MF32) mfma_gemm_f32<N2, N2, N2, NT>(ta, tb, tc, (mrows + 15) / 16);
           else gemm_tiles<TL, TL, N2, NT, T>((mrows + TL - 1) / TL * TL, N2, ta, tb, tc);
           __syncthreads();
 
@@ -1521,6 +1579,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
             }
           }
           if constexpr (MF64) mfma_gemm_f64<NK, CHI, NK, NT>(xa, xb, xc);
+          else if constexpr (MF32) mfma_gemm_f32<NK, CHI, NK, NT>(xa, xb, xc);
           else gemm_tiles<TL, TL, N2, NT, T>(N2, CHI, xa, xb, xc);
         }
         // the power-of-two rescale of Xt_c is applied to Z_{c-1} (per-wave maxima in red[])

@@ -9,8 +9,11 @@ stage for the whole batch).
 Consecutive steps overlap: the builds of steps t+1 and t+2 (one workgroup per realization each,
 on CUs kept free of proposal work by a CU mask, one stream each) run during the proposals and
 accepts of step t (on the other CUs); three sets of environments rotate.  The timed region starts
-with an empty pipeline and ends when the last step's accepts are done.  `serial` reports the same
-steps one after the other on one stream.  Also measured: the FP64 plain form (FP64 environments, one
+with an empty pipeline and ends when the last step's accepts are done.  Batches of more than 64
+realizations run their two builds in flight without the CU mask.  `--workload rbim256` runs the
+L = 256, chi = 48 BF16 workload at its three disorder strengths (one batch per p, consecutive
+pipeline stages); `--workload mixed` the mixed-L batch.  `serial` reports the same steps one
+after the other on one stream.  Also measured: the FP64 plain form (FP64 environments, one
 realization per call, one proposal per call) on a bounded sample, and the CPU FP64 oracle on the
 host (bounded sample, extrapolated; labelled).
 
@@ -285,50 +288,60 @@ def cu_masked_stream(reserve):
 
 
 def run_gpu_pipelined(args):
-    """Consecutive steps overlapped: the builds of the next `depth` steps (one workgroup per
+    """Consecutive steps overlapped: the builds of the next `depth` batches (one workgroup per
     realization each, so a fraction of the CUs; one stream per build in flight) run while the
-    proposals and accepts of step t use the rest of the chip (one stream, CU-masked).  depth + 1
-    batches with their own environments and workspaces rotate, so a build never overwrites
-    environments that proposals still read."""
+    proposals and accepts of the current batch use the rest of the chip (one stream, CU-masked).
+    depth + 1 sets of environments and workspaces rotate, so a build never overwrites
+    environments that proposals still read.  A workload with several disorder strengths runs
+    its batches (one per p, the same coupling seeds) as consecutive pipeline stages."""
     import torch
     from paper_2409_06538_amd import binding
     import synth
 
     w = synth.WORKLOADS[args.workload]
     Ls, seeds = workload_sizes(w)
-    chi, p, K = w["chi"], w["p"], args.proposals or w["proposals"]
+    ps = disorder_strengths(w)
+    chi, K = w["chi"], args.proposals or w["proposals"]
     n = len(seeds)
-    beta = binding.nishimori_beta(p)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    # each build in flight keeps 8 CUs of every XCD (64 CUs) per 64 realizations free of
+    # proposal work; at most two such sets are cleared.  Larger batches (whose builds in flight
+    # would need more) run unmasked: their builds then fill the chip together and the proposals
+    # take the CUs each build frees.
+    per_build = (n + 63) // 64
     depth = args.builds_in_flight
+    reserve = depth * per_build if args.reserve_cus and depth * per_build <= 2 else 0
     s_builds = [torch.cuda.Stream() for _ in range(depth)]
-    s_prop, cu_mask = cu_masked_stream(depth if args.reserve_cus else 0)
+    s_prop, cu_mask = cu_masked_stream(reserve)
     if s_prop is None:
         s_prop = torch.cuda.Stream()
     sets = []
     for _ in range(depth + 1):
-        b = binding.Batch(Ls, [beta] * n, seeds, chi, args.precision, K=K, device=dev)
+        b = binding.Batch(Ls, [binding.nishimori_beta(ps[0])] * n, seeds, chi, args.precision,
+                          K=K, device=dev)
         out = (torch.empty(b.spins_shape(K), dtype=torch.int64, device=dev),
                torch.empty((n, K), dtype=torch.float64, device=dev),
                torch.empty((n, K), dtype=torch.int32, device=dev))
         sets.append({"b": b, "out": out, "chains": b.new_chains(1),
                      "accum": torch.zeros((n, binding.OBS_COUNT), dtype=torch.float64, device=dev),
-                     "acc": torch.empty((n, K), dtype=torch.uint8, device=dev),
                      "done": None})
     L2 = torch.tensor([L * L for L in Ls], dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
 
-    def run(steps, record):
+    def run(steps):
+        """`steps` passes over every p: one pipeline stage per (step, p)."""
         sums, ev = [], []
-        for t in range(steps):
-            st = sets[t % (depth + 1)]
+        for u in range(steps * len(ps)):
+            p = ps[u % len(ps)]
+            st = sets[u % (depth + 1)]
             b = st["b"]
-            s_build = s_builds[t % depth]
+            s_build = s_builds[u % depth]
             e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
             with torch.cuda.stream(s_build):
                 if st["done"] is not None:
-                    s_build.wait_event(st["done"])     # proposals of step t-depth-1 read this env
+                    s_build.wait_event(st["done"])     # proposals of stage u-depth-1 read this env
+                b.set_betas([binding.nishimori_beta(p)] * n)
                 b.make_couplings(seeds, p)
                 e[0].record(s_build)
                 b.build_env(want_lnZ=False)
@@ -350,15 +363,16 @@ def run_gpu_pipelined(args):
             ev.append(e)
         return sums, ev
 
-    run(max(1, args.warmup), False)
+    run(max(1, args.warmup))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sums, ev = run(args.steps, True)
+    sums, ev = run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    tot = torch.stack(sums).sum(dim=0).tolist()
-    accepted, updates = int(tot[0]), tot[1]
-    attempted = args.steps * n * (K - 1)
+    per_stage = torch.stack(sums).tolist()                   # [steps * len(ps)][2]
+    accepted = int(sum(a for a, _ in per_stage))
+    updates = sum(x for _, x in per_stage)
+    attempted = args.steps * len(ps) * n * (K - 1)
     build_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / len(ev)
     prop_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / len(ev)
     wall = t1 - t0
@@ -367,13 +381,19 @@ def run_gpu_pipelined(args):
     torch.cuda.synchronize()
     if cu_mask is not None:
         s_prop.destroy()
-    return add_rooflines({"Ls": sorted(set(Ls)), "chi": chi, "n": n, "K": K, "p": p, "beta": beta,
-            "wall_s": wall, "ms_per_step": 1e3 * wall / args.steps,
-            "value": updates / wall, "accepted": accepted, "attempted": attempted,
-            "acceptance": accepted / attempted, "build_ms": build_ms, "propose_ms": prop_ms,
-            "graph": False, "pipelined": True, "builds_in_flight": depth,
-            "narrow_fraction": nfrac,
-            "propose_cu_mask": cu_mask}, args, Ls)
+    res = {"Ls": sorted(set(Ls)), "chi": chi, "n": n, "K": K, "p": ps[0] if len(ps) == 1 else ps,
+           "wall_s": wall, "ms_per_step": 1e3 * wall / args.steps,
+           "value": updates / wall, "accepted": accepted, "attempted": attempted,
+           "acceptance": accepted / attempted, "build_ms": build_ms, "propose_ms": prop_ms,
+           "graph": False, "pipelined": True, "builds_in_flight": depth,
+           "narrow_fraction": nfrac,
+           "propose_cu_mask": cu_mask}
+    if len(ps) > 1:
+        res["acceptance_per_p"] = {
+            str(p): sum(per_stage[u][0] for u in range(j, len(per_stage), len(ps)))
+            / (args.steps * n * (K - 1)) for j, p in enumerate(ps)}
+        res["batches_per_step"] = len(ps)
+    return add_rooflines(res, args, Ls)
 
 
 def run_fp64_plain(args, L, chi, p, K_full, n_prop=20):
@@ -519,18 +539,16 @@ def main():
         run_sweep(args)
         return
     import synth
-    # overlapped steps keep depth + 1 batches resident; a workload with several disorder
-    # strengths runs its batches one after the other on one set of buffers instead
     multi_p = len(disorder_strengths(synth.WORKLOADS[args.workload])) > 1
-    serial = args.serial or args.graph or multi_p
+    serial = args.serial or args.graph
     res = run_gpu(args) if serial else run_gpu_pipelined(args)
     if not serial and not args.no_serial:
         # the same steps one after the other on one stream, for comparison
         import copy
         a2 = copy.copy(args)
-        a2.steps, a2.warmup = 3, 1
+        a2.steps, a2.warmup = (1, 0) if multi_p else (3, 1)
         r2 = run_gpu(a2)
-        res["serial"] = {"value": r2["value"], "ms_per_step": r2["ms_per_step"], "steps": 3,
+        res["serial"] = {"value": r2["value"], "ms_per_step": r2["ms_per_step"], "steps": a2.steps,
                          "build_ms": r2["build_ms"], "propose_ms": r2["propose_ms"]}
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)

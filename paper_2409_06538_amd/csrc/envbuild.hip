@@ -868,9 +868,14 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         const int g = tid / TPC, part = tid % TPC;
         const int gb = g / CHI, gap = g % CHI;         // column g = (b, alpha')
         __syncthreads();
-        for (int e = tid; e < int(site); e += NT) {
-          const int b = e / (CHI * CHI), al = (e / CHI) % CHI, ap = e % CHI;
-          AsT[(b * CHI + ap) * LDAT + al] = widen(gld<E>(Ain, size_t(c) * site + e));
+        // only the block (al < bdin[c], ap < bdin[c+1]) of site c of E_r can be nonzero; the
+        // rest of AsT is never read
+        const int bl = bdin[c], br = bdin[c + 1], blk = bl * br;
+        for (int o = tid; o < 2 * blk; o += NT) {
+          const int b = o >= blk ? 1 : 0, rem = o - b * blk;
+          const int al = rem / br, ap = rem - al * br;
+          AsT[(b * CHI + ap) * LDAT + al] =
+              widen(gld<E>(Ain, size_t(c) * site + size_t(b) * CHI * CHI + al * CHI + ap));
         }
         if (c > 0) {
           T wh2[2][2];   // wh2[a][b]
@@ -895,7 +900,8 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         // that, i runs over the nonzero rows of R_{c-1}
         const int nrows = (c == 0) ? 2 * int(bdin[0]) : 2 * kprev;
         const int tl = (nrows + TPC - 1) / TPC;
-        const int alim = bdin[c];
+        const int alim = bl;
+        const bool colz = gap >= br;                     // column outside the right bond: zero
         T m[RPT];
         auto site_qr = [&](auto rlc, T (&m)[RPT]) __attribute__((always_inline)) {
           constexpr int RL = decltype(rlc)::value;
@@ -905,7 +911,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
 #pragma unroll
             for (int t = 0; t < RL; ++t) {
               const int rho = part + TPC * t, i = rho >> 1;
-              m[t] = (rho < MQ && i < CHI) ? wx * acol[i < CHI ? i : 0] : T(0);
+              m[t] = (rho < MQ && i < alim && !colz) ? wx * acol[i < alim ? i : 0] : T(0);
             }
           } else {
             const T* rb = Rt + size_t(gb) * CHI * LDRT + (part >> 1);
@@ -924,7 +930,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
               }
             }
 #pragma unroll
-            for (int t = 0; t < RL; ++t) m[t] *= wx;
+            for (int t = 0; t < RL; ++t) m[t] = colz ? T(0) : m[t] * wx;
           }
           number_live_columns<T, CHI>(m, perm, ord, imisc + 6);
           const int kmax = imisc[6] < nrows ? imisc[6] : nrows;

@@ -55,3 +55,12 @@ def test_rooflines_from_launch_times():
     assert bench.proposals_per_wg("fp32", 64, 1000, 64) == 128
     assert bench.proposals_per_wg("bf16", 64, 1000, 64) == 128
     assert bench.proposals_per_wg("fp32", 256, 1000, 256) == 64
+
+
+def test_disorder_strengths():
+    """The L = 256 workload runs three disorder strengths on the same coupling seeds; the others
+    one."""
+    assert bench.disorder_strengths(synth.WORKLOADS["rbim256"]) == [0.10, 0.109, 0.12]
+    assert bench.disorder_strengths(synth.WORKLOADS["rbim64"]) == [0.109]
+    Ls, seeds = bench.workload_sizes(synth.WORKLOADS["rbim256"])
+    assert Ls == [256] * 128 and seeds == list(range(128))

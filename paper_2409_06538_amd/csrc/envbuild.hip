@@ -348,22 +348,21 @@ __device__ __forceinline__ void number_live_columns(const T (&m)[LeftCfg<CHI>::R
 
 // R factor of the register-resident M (R-only Householder QR) over its live columns, one
 // barrier per reflector: after applying reflector k, the owner of live column k + 1 publishes
-// reflector k + 1 into the other half of the double buffer.  Thread `part` of the group owning
-// column g holds rows part + TPC t of it; rows >= TPC RL are zero, and so are the rows >= kmax
-// once a column has seen every reflector: kmax = min(live columns, nonzero rows) reflectors are
-// needed.  Live column g (live rank kg) ends with its diagonal entry (row kg) in diag[g] and the
-// rows above it in m[]; a zero column, or one with kg >= kmax, gets diag[g] = 0.  The R rows
-// are thus compact: rows >= kmax are zero.
-template <typename T, int CHI, int RL>
-__device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T* diag, int kg,
+// reflector k + 1 into the other half of the double buffer.  A group of TP threads owns a
+// column; thread `part` of it holds rows part + TP t; rows >= TP RL are zero, and so are the rows
+// >= kmax once a column has seen every reflector: kmax = min(live columns, nonzero rows)
+// reflectors are needed.  A live column (live rank kg) ends with its diagonal entry (row kg) in
+// *dslot and the rows above it in m[]; a column with kg >= kmax gets *dslot = 0, a zero column
+// (kg < 0) is left alone.  The R rows are thus compact: rows >= kmax are zero.
+template <typename T, int CHI, int RL, int TP>
+__device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T* dslot, int kg,
                                  int kmax) {
   using C = LeftCfg<CHI>;
-  constexpr int MQ = C::MQ, TPC = C::TPC, RPT = C::RPT, VLD = C::VLD;
-  static_assert(RL <= RPT && TPC * RL <= VLD, "live rows fit the reflector buffer");
-  const int tid = threadIdx.x;
-  const int g = tid / TPC, part = tid % TPC;
-  if ((kg < 0 || kg >= kmax) && part == 0) diag[g] = T(0);
-  if (kg == 0 && kmax > 0) make_reflector<T, TPC, RPT, RL>(m, 0, part, MQ, vbuf, taub, diag + g);
+  constexpr int MQ = C::MQ, RPT = C::RPT, VLD = C::VLD;
+  static_assert(RL <= RPT && TP * RL <= VLD, "live rows fit the reflector buffer");
+  const int part = threadIdx.x % TP;
+  if (kg >= kmax && part == 0) *dslot = T(0);
+  if (kg == 0 && kmax > 0) make_reflector<T, TP, RPT, RL>(m, 0, part, MQ, vbuf, taub, dslot);
   __syncthreads();
   for (int k = 0; k < kmax; ++k) {
     const T* vj = vbuf + (k & 1) * VLD;
@@ -375,21 +374,21 @@ __device__ void householder_regs(T (&m)[LeftCfg<CHI>::RPT], T* vbuf, T* taub, T*
       T wp[4] = {T(0), T(0), T(0), T(0)};
 #pragma unroll
       for (int t = 0; t < RL; ++t) {
-        const T x = vj[part + TPC * t];
+        const T x = vj[part + TP * t];
         if constexpr (HOLD) vv[t] = x;
         wp[t & 3] += x * m[t];
       }
       T w = (wp[0] + wp[1]) + (wp[2] + wp[3]);
-      w = group_sum<TPC>(w);
+      w = group_sum<TP>(w);
       const T tw = tau * w;
 #pragma unroll
       for (int t = 0; t < RL; ++t) {
         if constexpr (HOLD) m[t] -= tw * vv[t];
-        else m[t] -= tw * vj[part + TPC * t];
+        else m[t] -= tw * vj[part + TP * t];
       }
       if (kg == k + 1 && k + 1 < kmax)
-        make_reflector<T, TPC, RPT, RL>(m, k + 1, part, MQ, vbuf + ((k + 1) & 1) * VLD,
-                                        taub + ((k + 1) & 1), diag + g);
+        make_reflector<T, TP, RPT, RL>(m, k + 1, part, MQ, vbuf + ((k + 1) & 1) * VLD,
+                                       taub + ((k + 1) & 1), dslot);
     }
     __syncthreads();
   }
@@ -865,8 +864,6 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       int kprev = 0;                                   // nonzero rows of R_{c-1}
       for (int c = 0; c < L - 1; ++c) {
         fresh_tid();
-        const int g = tid / TPC, part = tid % TPC;
-        const int gb = g / CHI, gap = g % CHI;         // column g = (b, alpha')
         __syncthreads();
         // only the block (al < bdin[c], ap < bdin[c+1]) of site c of E_r can be nonzero; the
         // rest of AsT is never read
@@ -892,25 +889,32 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           }
         }
         __syncthreads();
-        const T w0 = bond_weight<T>(jv, c, 0, gb, ep, em);
-        const T w1 = bond_weight<T>(jv, c, 1, gb, ep, em);
-        const T wx = (part & 1) ? w1 : w0;             // rows part + TPC t all have x = part & 1
-        const T* acol = AsT + (gb * CHI + gap) * LDAT;   // A[b][.][ap]
         // M_c rows (i, x): at site 0, i is the left bond of E_r (dimension bdin[0] = 1); after
         // that, i runs over the nonzero rows of R_{c-1}
         const int nrows = (c == 0) ? 2 * int(bdin[0]) : 2 * kprev;
-        const int tl = (nrows + TPC - 1) / TPC;
         const int alim = bl;
-        const bool colz = gap >= br;                     // column outside the right bond: zero
         T m[RPT];
-        auto site_qr = [&](auto rlc, T (&m)[RPT]) __attribute__((always_inline)) {
-          constexpr int RL = decltype(rlc)::value;
+        // One site with TP threads per column.  TP = TPC: every column has a group (column g =
+        // tid / TPC), the zero ones are found by ballot.  TP = 2 TPC (right bond <= CHI / 2): the
+        // CHI groups take the 2 br columns (b, alpha' < br) in order, so each thread holds half as
+        // many rows; the other columns of R_c are written as zeros.
+        auto site_qr = [&](auto rlc, auto tpc, T (&m)[RPT]) __attribute__((always_inline)) {
+          constexpr int RL = decltype(rlc)::value, TP = decltype(tpc)::value;
+          constexpr bool REMAP = TP != TPC;
+          const int part = tid % TP, h = tid / TP;
+          const int g = !REMAP ? h : (h < br ? h : (h < 2 * br ? CHI + h - br : -1));
+          const int gb = g < 0 ? 0 : g / CHI, gap = g < 0 ? 0 : g % CHI;
+          const bool colz = g < 0 || gap >= br;          // column outside the right bond: zero
+          const T w0 = bond_weight<T>(jv, c, 0, gb, ep, em);
+          const T w1 = bond_weight<T>(jv, c, 1, gb, ep, em);
+          const T wx = (part & 1) ? w1 : w0;             // rows part + TP t all have x = part & 1
+          const T* acol = AsT + (gb * CHI + gap) * LDAT;   // A[b][.][ap]
 #pragma unroll
           for (int t = 0; t < RPT; ++t) m[t] = T(0);
           if (c == 0) {
 #pragma unroll
             for (int t = 0; t < RL; ++t) {
-              const int rho = part + TPC * t, i = rho >> 1;
+              const int rho = part + TP * t, i = rho >> 1;
               m[t] = (rho < MQ && i < alim && !colz) ? wx * acol[i < alim ? i : 0] : T(0);
             }
           } else {
@@ -925,44 +929,77 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                   const int t = t0 + u;
-                  if (t < RL && part + TPC * t < MQ) m[t] += rr[(TPC / 2) * t] * a;
+                  if (t < RL && part + TP * t < MQ) m[t] += rr[(TP / 2) * t] * a;
                 }
               }
             }
 #pragma unroll
             for (int t = 0; t < RL; ++t) m[t] = colz ? T(0) : m[t] * wx;
           }
-          number_live_columns<T, CHI>(m, perm, ord, imisc + 6);
-          const int kmax = imisc[6] < nrows ? imisc[6] : nrows;
-          householder_regs<T, CHI, RL>(m, vbuf, taub, diag, ord[g], kmax);
-          return kmax;
-        };
-        const int kmax = (tl <= RQ) ? site_qr(std::integral_constant<int, RQ>{}, m)
-                         : (tl <= RH) ? site_qr(std::integral_constant<int, RH>{}, m)
-                                      : site_qr(std::integral_constant<int, RPT>{}, m);
-        const int kg = ord[g];
-        kprev = kmax;
-        // carry R with a power-of-two rescale; keep it for the second sweep
-        T mx = 0;
-#pragma unroll
-        for (int t = 0; t < RPT; ++t)
-          if (part + TPC * t < kg) mx = fmax(mx, fabs(m[t]));
-        if (tid < N2) mx = fmax(mx, fabs(diag[tid]));
-        mx = block_max<NT>(mx, red);
-        const int e = pow2_exponent(mx);
-        log2acc += e;
-        // exponent and the number of nonzero rows of R_c (< 256), packed: 256 e + kmax
-        if (tid == 0) rexp[c] = e * 256 + kmax;
-        gmem<T>* rdst = rs + size_t(c) * N2 * N2 + size_t(g) * N2;
-        const T dg = diag[g];
-#pragma unroll
-        for (int t = 0; t < RPT; ++t) {
-          const int rho = part + TPC * t;
-          if (rho < N2) {
-            const T v = T(ldexp(rho < kg ? m[t] : (rho == kg ? dg : T(0)), -e));
-            bufR[g * LDT + rho] = v;
-            rdst[rho] = v;
+          int kg, kmax;
+          if constexpr (!REMAP) {
+            number_live_columns<T, CHI>(m, perm, ord, imisc + 6);
+            kg = ord[g];
+            kmax = imisc[6] < nrows ? imisc[6] : nrows;
+          } else {
+            kg = g < 0 ? -1 : h;
+            kmax = 2 * br < nrows ? 2 * br : nrows;
           }
+          // a zero column keeps diag = 0 (in the remapped form every column outside the bond)
+          if (!REMAP && kg < 0 && part == 0) diag[g] = T(0);
+          if (REMAP && tid < N2 && (tid % CHI) >= br) diag[tid] = T(0);
+          householder_regs<T, CHI, RL, TP>(m, vbuf, taub, diag + (g < 0 ? 0 : g), kg, kmax);
+          // carry R with a power-of-two rescale; keep it for the second sweep
+          T mx = 0;
+#pragma unroll
+          for (int t = 0; t < RL; ++t)
+            if (part + TP * t < kg) mx = fmax(mx, fabs(m[t]));
+          if (tid < N2) mx = fmax(mx, fabs(diag[tid]));
+          mx = block_max<NT>(mx, red);
+          const int e = pow2_exponent(mx);
+          log2acc += e;
+          // exponent and the number of nonzero rows of R_c (< 256), packed: 256 e + kmax
+          if (tid == 0) rexp[c] = e * 256 + kmax;
+          gmem<T>* rsite = rs + size_t(c) * N2 * N2;
+          if (g >= 0) {
+            const T dg = diag[g];
+#pragma unroll
+            for (int t = 0; t < RPT; ++t) {
+              const int rho = part + TP * t;
+              if (TP * t < N2 && rho < N2) {
+                const T v = T(ldexp(rho < kg ? m[t] : (rho == kg ? dg : T(0)), -e));
+                bufR[g * LDT + rho] = v;
+                rsite[size_t(g) * N2 + rho] = v;
+              }
+            }
+          }
+          if constexpr (REMAP) {
+            // the columns (b, alpha' >= br) of R_c are zero
+            const int nz = CHI - br;
+            for (int o = tid; o < 2 * nz * N2; o += NT) {
+              const int col = (o / (nz * N2)) * CHI + br + (o / N2) % nz, rho = o % N2;
+              bufR[col * LDT + rho] = T(0);
+              rsite[size_t(col) * N2 + rho] = T(0);
+            }
+          }
+          kprev = kmax;
+        };
+        bool done = false;
+        if constexpr (RPT >= 16) {   // chi >= 32: enough rows per thread to halve
+          constexpr int TP2 = 2 * TPC, R2 = RPT / 2, RQ2 = R2 / 4, RH2 = R2 / 2;
+          if (2 * br <= CHI) {
+            const int tl = (nrows + TP2 - 1) / TP2;
+            if (tl <= RQ2) site_qr(std::integral_constant<int, RQ2>{}, std::integral_constant<int, TP2>{}, m);
+            else if (tl <= RH2) site_qr(std::integral_constant<int, RH2>{}, std::integral_constant<int, TP2>{}, m);
+            else site_qr(std::integral_constant<int, R2>{}, std::integral_constant<int, TP2>{}, m);
+            done = true;
+          }
+        }
+        if (!done) {
+          const int tl = (nrows + TPC - 1) / TPC;
+          if (tl <= RQ) site_qr(std::integral_constant<int, RQ>{}, std::integral_constant<int, TPC>{}, m);
+          else if (tl <= RH) site_qr(std::integral_constant<int, RH>{}, std::integral_constant<int, TPC>{}, m);
+          else site_qr(std::integral_constant<int, RPT>{}, std::integral_constant<int, TPC>{}, m);
         }
       }
     }
@@ -1337,22 +1374,31 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           // (t < RL2) in registers and republishes them in Tw after each update, so that every
           // thread reads the next pivot column from LDS and forms its reflector itself (one
           // barrier per column).
-          const int g = tid / TPC, part = tid % TPC;
-          const bool owner = g < N2;
-          bool active = owner;
-          auto qrcp = [&](auto rlc) __attribute__((always_inline)) {
-            constexpr int RL2 = decltype(rlc)::value;
+          // TP = TPC: every physical column g = tid / TPC has a group.  TP = 2 TPC (right bond
+          // bdo of the new site <= CHI / 2): the CHI groups take the 2 bdo columns (x, be < bdo)
+          // of T in order (the others are zero and never pivots), so each thread holds half as
+          // many rows.
+          const int bdo = bdout[c + 1];
+          int g = 0, part = 0;
+          bool owner = false, active = false;
+          auto qrcp = [&](auto rlc, auto tpc) __attribute__((always_inline)) {
+            constexpr int RL2 = decltype(rlc)::value, TP = decltype(tpc)::value;
+            part = tid % TP;
+            const int h = tid / TP;
+            g = (TP == TPC) ? h : (h < bdo ? h : (h < 2 * bdo ? CHI + h - bdo : N2));
+            owner = g < N2;
+            active = owner;
             T mc[RL2];
             T cn = 0;
             {
               T cp[4] = {T(0), T(0), T(0), T(0)};
     #pragma unroll
               for (int t = 0; t < RL2; ++t) {
-                const int rho = part + TPC * t;
+                const int rho = part + TP * t;
                 mc[t] = (owner && rho < N2) ? Tw[g * LDT + rho] : T(0);
                 cp[t & 3] += mc[t] * mc[t];
               }
-              cn = group_sum<TPC>((cp[0] + cp[1]) + (cp[2] + cp[3]));
+              cn = group_sum<TP>((cp[0] + cp[1]) + (cp[2] + cp[3]));
             }
             {
               T bv = owner ? cn : T(-1);
@@ -1395,30 +1441,30 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
               // compiler move each load under its own branch and wait for it there)
     #pragma unroll
               for (int t = 0; t < RL2; ++t) {
-                const int rho = part + TPC * t;
-                v[t] = pc[(N2 % TPC == 0 || rho < N2) ? rho : 0];
+                const int rho = part + TP * t;
+                v[t] = pc[(N2 % TP == 0 || rho < N2) ? rho : 0];
               }
     #pragma unroll
               for (int t = 0; t < RL2; ++t) {
-                const int rho = part + TPC * t;
+                const int rho = part + TP * t;
                 const T sg = (rho > j && rho < N2) ? scal : T(0);
                 const T one = (rho == j) ? T(1) : T(0);
                 v[t] = v[t] * sg + one;
                 wp[t & 3] += v[t] * mc[t];
               }
-              const T w = group_sum<TPC>((wp[0] + wp[1]) + (wp[2] + wp[3]));
+              const T w = group_sum<TP>((wp[0] + wp[1]) + (wp[2] + wp[3]));
               T np[4] = {T(0), T(0), T(0), T(0)};
               if (active) {
                 const T tw = tau * w;
     #pragma unroll
                 for (int t = 0; t < RL2; ++t) {
-                  const int rho = part + TPC * t;
+                  const int rho = part + TP * t;
                   mc[t] -= tw * v[t];
                   np[t & 3] += (rho > j) ? mc[t] * mc[t] : T(0);
-                  if (N2 % TPC == 0 || rho < N2) Tw[g * LDT + rho] = mc[t];
+                  if (N2 % TP == 0 || rho < N2) Tw[g * LDT + rho] = mc[t];
                 }
               }
-              const T nn = group_sum<TPC>((np[0] + np[1]) + (np[2] + np[3]));
+              const T nn = group_sum<TP>((np[0] + np[1]) + (np[2] + np[3]));
               {
                 T bv = active ? nn : T(-1);
                 int bi = active ? g : N2;
@@ -1431,11 +1477,26 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
               __syncthreads();
             }
           };
-          if (rl2 == R2Q) qrcp(std::integral_constant<int, R2Q>{});
-          else if (rl2 == R2H) qrcp(std::integral_constant<int, R2H>{});
-          else qrcp(std::integral_constant<int, RPT2>{});
-          // columns never picked follow the pivots in ascending order
+          bool done = false;
+          if constexpr (RPT2 >= 8) {   // rows of T = TPC rl2 = 2 TPC (rl2 / 2)
+            if (2 * bdo <= CHI) {
+              using I2 = std::integral_constant<int, 2 * TPC>;
+              if (rl2 == R2Q) qrcp(std::integral_constant<int, R2Q / 2>{}, I2{});
+              else if (rl2 == R2H) qrcp(std::integral_constant<int, R2H / 2>{}, I2{});
+              else qrcp(std::integral_constant<int, RPT2 / 2>{}, I2{});
+              done = true;
+            }
+          }
+          if (!done) {
+            using I1 = std::integral_constant<int, TPC>;
+            if (rl2 == R2Q) qrcp(std::integral_constant<int, R2Q>{}, I1{});
+            else if (rl2 == R2H) qrcp(std::integral_constant<int, R2H>{}, I1{});
+            else qrcp(std::integral_constant<int, RPT2>{}, I1{});
+          }
+          // columns never picked follow the pivots in ascending order (the zero columns that
+          // have no group in the remapped form among them)
           if (owner && part == 0) unpk[g] = active ? 1 : 0;
+          if (done && tid < N2 && (tid % CHI) >= bdo) unpk[tid] = 1;
           __syncthreads();
           rank_unpicked(rank, NK);
           // J = rows 0..rank-1 of R in pivoted column order (row-major in bufR, ld LDT)

@@ -1618,9 +1618,16 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         // chi = 48) takes a second pass.
         if constexpr (GRAM) mgs_pairs_rows<T, CHI, NT, LDV, KW, (KW <= 16 ? 8 : TPP)>(bufS, kept, T(Tol::eta));
         else {
-          // two passes, the rows taken two at a time (one barrier per pair)
-          mgs_pairs_rows<T, CHI, NT, LDV>(bufS, kept, T(Tol::eta));
-          mgs_pairs_rows<T, CHI, NT, LDV>(bufS, kept, T(Tol::eta));
+          // two passes, the rows taken two at a time (one barrier per pair), over the columns
+          // (x, be < bdout[c+1]) only: the right bond of the new site bounds its nonzero columns
+          const int bdr = bdout[c + 1];
+          constexpr int KW1 = CHI > 16 ? 16 : CHI, KW2 = CHI > 24 ? 24 : CHI;
+          const int kwm = bdr <= KW1 ? KW1 : bdr <= KW2 ? KW2 : CHI;
+          for (int pass = 0; pass < 2; ++pass) {
+            if (kwm == KW1) mgs_pairs_rows<T, CHI, NT, LDV, KW1>(bufS, kept, T(Tol::eta));
+            else if (kwm == KW2) mgs_pairs_rows<T, CHI, NT, LDV, KW2>(bufS, kept, T(Tol::eta));
+            else mgs_pairs_rows<T, CHI, NT, LDV>(bufS, kept, T(Tol::eta));
+          }
         }
         gmem<E>* bout = Aout + size_t(c) * site;   // site c of E_{r-1}: B[x][al][be] = V[al][x*CHI + be]
         for (int o = tid; o < int(site); o += NT) {

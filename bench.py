@@ -473,7 +473,7 @@ def calib_copy(mib):
 
 
 SWEEP_LS = (16, 32, 64, 128, 256)
-SWEEP_CHIS = (8, 16, 32)
+SWEEP_CHIS = (8, 16, 32, 48)
 
 
 def run_sweep(args):

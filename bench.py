@@ -17,7 +17,7 @@ after the other on one stream.  Also measured: the FP64 plain form (FP64 environ
 realization per call, one proposal per call) on a bounded sample, and the CPU FP64 oracle on the
 host (bounded sample, extrapolated; labelled).
 
-Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 20] [--warmup 1] [--serial]
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 1] [--serial]
 """
 import argparse
 import json
@@ -472,6 +472,8 @@ def calib_copy(mib):
     del src, dst
 
 
+DEFAULT_STEPS = {"rbim16": 50, "rbim64": 50, "mixed": 4, "rbim256": 2}
+
 SWEEP_LS = (16, 32, 64, 128, 256)
 SWEEP_CHIS = (8, 16, 32, 48)
 
@@ -501,7 +503,10 @@ def run_sweep(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=0,
+                    help="timed steps (default: 50 for rbim64 and rbim16, whose steps take "
+                         "milliseconds, so that the pipeline fill and drain inside the timed "
+                         "region are amortised; 4 for mixed; 2 for rbim256)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rbim64")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
@@ -530,6 +535,8 @@ def main():
                     help="after the run, copy one buffer of this many MiB once (a plain copy "
                          "kernel of known size, the reference for hardware byte counters)")
     args = ap.parse_args()
+    if not args.steps:
+        args.steps = DEFAULT_STEPS.get(args.workload, 20)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the realizations of a "
               "batch are independent, so N GPUs would each run their own share; this "

@@ -7,7 +7,7 @@ low halves, mixes the high halves with words 1 and 3 and the key, and permutes; 
 advanced by two Weyl constants between rounds.
 
 The paper does not fix a generator (random draws appear in the sampling step of Sec. II B and in
-the Metropolis filter, Eq. (3)); this build uses Philox so that every draw is a pure function of
+the Metropolis filter, Eq. (3)); Philox is used here so that every draw is a pure function of
 (key, counter) and the HIP path can reproduce the oracle's stream exactly.
 
 Uniform convention (shared by both sides, defined here in prose): draw number ``i`` of a stream

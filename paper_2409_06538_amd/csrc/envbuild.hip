@@ -184,6 +184,39 @@ __device__ __forceinline__ void mfma_gemm_f32(FA fa, FB fb, FC fc, int tm = M / 
   }
 }
 
+// The same product over index blocks only: rows [mb BS, mb BS + 16 mt) for mb < MB, columns
+// [nb BS, nb BS + 16 nt) for nb < NB, and the contraction over [kb BS, kb BS + 16 kt) for kb < KB
+// (what lies outside is zero in the operands, or not needed in the result).
+template <int NT, int BS, int MB, int NB, int KB, typename FA, typename FB, typename FC>
+__device__ __forceinline__ void mfma_gemm_f32_blocks(FA fa, FB fb, FC fc, int mt, int nt, int kt) {
+  typedef float v4f __attribute__((ext_vector_type(4)));
+  static_assert(BS % 16 == 0, "block starts on a tile boundary");
+  constexpr int NWV = NT / 64;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int i16 = lane & 15, q = lane >> 4;
+  const int tiles_m = MB * mt, tiles_n = NB * nt;
+  for (int t = wv; t < tiles_m * tiles_n; t += NWV) {
+    const int tm = t % tiles_m, tn = t / tiles_m;
+    const int r0 = (tm / mt) * BS + (tm % mt) * 16, c0 = (tn / nt) * BS + (tn % nt) * 16;
+    v4f acc = {0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < KB; ++kb) {
+      for (int kk = 0; kk < kt; ++kk) {
+        const int k0 = kb * BS + kk * 16;
+        float a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = fa(r0 + i16, k0 + 4 * u + q);
+          b[u] = fb(k0 + 4 * u + q, c0 + i16);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], b[u], acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) fc(r0 + 4 * q + r, c0 + i16, acc[r]);
+  }
+}
+
 // BATCH independent products C_b = A_b B_b of the shapes above in one tile loop, so that all
 // wavefronts share the tiles of all products.  fa(b, i, k), fb(b, k, j), fc(b, i, j, v).
 template <int BATCH, int M, int N, int K, int NT, typename FA, typename FB, typename FC>
@@ -1364,9 +1397,21 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
           auto ta = [&](int i, int a) { return bufR[a * LDT + i]; };
           auto tb = [&](int a, int col) { return Zr[a * LDZ + col]; };
           auto tc = [&](int i, int col, T v) { Tw[col * LDT + i] = v; };
-          if constexpr (MF64) mfma_gemm_f64<N2, N2, N2, NT>(ta, tb, tc);
-          else if constexpr (MF32) mfma_gemm_f32<N2, N2, N2, NT>(ta, tb, tc, (mrows + 15) / 16);
-          else gemm_tiles<TL, TL, N2, NT, T>((mrows + TL - 1) / TL * TL, N2, ta, tb, tc);
+          if constexpr (MF64) {
+            mfma_gemm_f64<N2, N2, N2, NT>(ta, tb, tc);
+          } else if constexpr (MF32) {
+            // T is zero outside the columns (x, be < bdout[c+1]); the contraction runs over the
+            // columns (a, al < bdin[c]) of R_{c-1}, the others being zero
+            const int nbt = (bdout[c + 1] + 15) / 16, kbt = (bdin[c] + 15) / 16;
+            mfma_gemm_f32_blocks<NT, CHI, 1, 2, 2>(ta, tb, tc, (mrows + 15) / 16, nbt, kbt);
+            const int nz = CHI - 16 * nbt;
+            for (int o = tid; o < 2 * nz * mrows; o += NT) {
+              const int col = (o / (nz * mrows)) * CHI + 16 * nbt + (o / mrows) % nz;
+              Tw[col * LDT + o % mrows] = T(0);
+            }
+          } else {
+            gemm_tiles<TL, TL, N2, NT, T>((mrows + TL - 1) / TL * TL, N2, ta, tb, tc);
+          }
           __syncthreads();
 
           // ---- QR with column pivoting, stopping at the numerical rank ----
@@ -1652,9 +1697,21 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
               bufR[al * LDT + (z / (CHI - KW)) * CHI + KW + z % (CHI - KW)] = T(0);
             }
           }
-          if constexpr (MF64) mfma_gemm_f64<NK, CHI, NK, NT>(xa, xb, xc);
-          else if constexpr (MF32) mfma_gemm_f32<NK, CHI, NK, NT>(xa, xb, xc);
-          else gemm_tiles<TL, TL, N2, NT, T>(N2, CHI, xa, xb, xc);
+          if constexpr (MF64) {
+            mfma_gemm_f64<NK, CHI, NK, NT>(xa, xb, xc);
+          } else if constexpr (MF32) {
+            // only the rows (a, al < bdin[c]) of Z, the kept rows of V and their columns
+            // (x, be < bdout[c+1]) can be nonzero; the rest of Xt_c is written as zeros
+            const int mtx = (bdin[c] + 15) / 16, ntx = (kept + 15) / 16;
+            const int ktx = (bdout[c + 1] + 15) / 16;
+            mfma_gemm_f32_blocks<NT, CHI, 2, 1, 2>(xa, xb, xc, mtx, ntx, ktx);
+            for (int o = tid; o < CHI * N2; o += NT) {
+              const int al = o / N2, j = o % N2;
+              if (al >= 16 * ntx || j % CHI >= 16 * mtx) bufR[al * LDT + j] = T(0);
+            }
+          } else {
+            gemm_tiles<TL, TL, N2, NT, T>(N2, CHI, xa, xb, xc);
+          }
         }
         // the power-of-two rescale of Xt_c is applied to Z_{c-1} (per-wave maxima in red[])
         mx = wave_max(mx);

@@ -1766,7 +1766,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     __syncthreads();
     if (tid == 0) {
       const double s = double(sc[0]) + double(sc[CHI]);
-      lnZ_out[blockIdx.x] = lambda + logacc + log(s);
+      lnZ_out[R.slot] = lambda + logacc + log(s);
     }
   }
 }

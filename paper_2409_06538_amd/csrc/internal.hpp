@@ -12,7 +12,7 @@ namespace tnmc {
 // Device-side descriptor of one realization (built by the C ABI layer in the workspace).
 struct DevReal {
   int L;
-  int pad_;
+  int slot;   // index of this realization in the caller's batch (the table may be reordered)
   double beta;
   uint64_t id;
   const uint64_t* Jh;

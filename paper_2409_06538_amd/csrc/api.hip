@@ -85,15 +85,15 @@ hipError_t store_words(const uint64_t* src, size_t count, uint64_t* dst, hipStre
 }
 
 // Build the device descriptor table in the workspace; per-realization slices for `use`.  For the
-// build (one workgroup per realization, runtime growing as L^2) the table lists the realizations
-// by decreasing L, so that the longest workgroups are dispatched first; `slot` keeps each one's
-// index in the caller's batch.
+// build and the proposals (workgroups whose runtime grows as L^2) the table lists the
+// realizations by decreasing L, so that the longest workgroups are dispatched first; `slot`
+// keeps each one's index in the caller's batch, which indexes every output.
 hipError_t upload_desc(const tnmc_instance* inst, int32_t n, int32_t chi, int32_t K,
                        tnmc_precision p, Use use, void* ws, hipStream_t stream) {
   static_assert(sizeof(DevReal) % sizeof(uint64_t) == 0, "descriptor is whole words");
   std::vector<int> order(n);
   for (int i = 0; i < n; ++i) order[i] = i;
-  if (use == Use::build)
+  if (use == Use::build || use == Use::propose)
     std::stable_sort(order.begin(), order.end(),
                      [inst](int a, int b) { return inst[a].L > inst[b].L; });
   std::vector<DevReal> h(n);

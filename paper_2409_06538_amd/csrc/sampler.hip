@@ -40,8 +40,8 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
   // bit-packed rows of each proposal: [0] the row above, [1] the row being drawn
   __shared__ uint64_t rows[2][MAX_W][PROP_NT];
   const int tid = threadIdx.x;
-  const int ri = blockIdx.y;
-  const DevReal R = reals[ri];
+  const DevReal R = reals[blockIdx.y];
+  const int ri = R.slot;   // the caller's index of this realization (outputs, teacher rows)
   const int L = R.L;
   const int W = words_per_row(L);
   const int Wmax = words_per_row(Lmax);
@@ -296,8 +296,8 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int pl = lane & 15, q = lane >> 4;
   const int slot = wv * 16 + pl;
-  const int ri = blockIdx.y;
-  const DevReal R = reals[ri];
+  const DevReal R = reals[blockIdx.y];
+  const int ri = R.slot;   // the caller's index of this realization (outputs, teacher rows)
   const int L = R.L;
   const int W = words_per_row(L);
   const int Wmax = words_per_row(Lmax);

@@ -296,19 +296,29 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int pl = lane & 15, q = lane >> 4;
   const int slot = wv * 16 + pl;
-  const DevReal R = reals[blockIdx.y];
+  // Workgroups go to the 8 XCDs in turn (linear id w -> XCD w % 8).  When the realizations split
+  // evenly, all proposal chunks of realization y run on XCD y % 8, one after the other, so that
+  // they read its environments through the same L2.
+  int bx = blockIdx.x, by = blockIdx.y;
+  if (gridDim.y % 8 == 0) {
+    const int w = blockIdx.x + gridDim.x * blockIdx.y;
+    const int idx = w >> 3;
+    bx = idx % gridDim.x;
+    by = (w & 7) + 8 * (idx / gridDim.x);
+  }
+  const DevReal R = reals[by];
   const int ri = R.slot;   // the caller's index of this realization (outputs, teacher rows)
   const int L = R.L;
   const int W = words_per_row(L);
   const int Wmax = words_per_row(Lmax);
-  const int k = blockIdx.x * MF_PROP + slot;
+  const int k = bx * MF_PROP + slot;
   const bool active = k < K;
   const int kk = active ? k : K - 1;   // inactive slots shadow a valid proposal, write nothing
   const T ep = T(exp(R.beta)), em = T(exp(-R.beta));
   const gmem<E>* env = as_global(reinterpret_cast<E*>(R.env));
   // V store of this wavefront: [c][chunk][lane][PV]
   gmem<T>* vbase = as_global(reinterpret_cast<T*>(R.ws)) +
-                   (size_t(blockIdx.x) * L * MF_WAVES + wv) * (64 * NV) + lane * PV;
+                   (size_t(bx) * L * MF_WAVES + wv) * (64 * NV) + lane * PV;
   const size_t vstep = size_t(MF_WAVES) * 64 * NV;   // per site
   const uint64_t pid = first + uint64_t(kk);
   const uint64_t* tin = teacher ? teacher + (size_t(ri) * K + kk) * size_t(Lmax) * Wmax : nullptr;

@@ -460,6 +460,44 @@ def run_cpu_baseline(L, chi, p, K_full, seed, n_real=6, n_prop=150):
                       f"extrapolated to {K_full} proposals per realization; single thread"}
 
 
+def _cpu_worker(job):
+    """One realization on one core: full FP64 build, n_prop proposals, the chain."""
+    L, chi, p, seed, i, n_prop = job
+    from threadpoolctl import threadpool_limits
+    from oracle import accept, energy, envbuild, instance, sampler
+    beta = instance.nishimori_beta(p)
+    with threadpool_limits(limits=1):
+        Jh, Jv = instance.couplings(i, L, p)
+        t0 = time.perf_counter()
+        env = envbuild.build_env(Jh, Jv, beta, chi)
+        t_build = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        smp = sampler.run(env, Jh, Jv, beta, K=n_prop, seed=seed, realization=i)
+        E = energy.energy(smp["spins"], Jh, Jv)
+        ch = accept.chain(E, smp["logq"], beta, seed=seed, realization=i)
+        t_prop = time.perf_counter() - t0
+    return t_build, t_prop, int(ch["accepted"].sum())
+
+
+def run_cpu_all_cores(L, chi, p, K_full, seed, n_prop=150, max_workers=16):
+    """The oracle on every host core the process may use (at most max_workers): one process per
+    core, each a realization (coupling seeds 0..w-1) with a full build + n_prop proposals + the
+    chain, extrapolated to K_full proposals; the realizations run side by side, so the batch takes
+    the longest extrapolated time.  Runs before anything touches the GPU (forked workers)."""
+    import multiprocessing as mp
+    w = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(w) as pool:
+        out = pool.map(_cpu_worker, [(L, chi, p, seed, i, n_prop) for i in range(w)])
+    wall = time.perf_counter() - t0
+    t_real = max(tb + K_full * tp / n_prop for tb, tp, _ in out)
+    updates = sum((K_full - 1) * (a / (n_prop - 1)) * L * L for _, _, a in out)
+    return {"value": updates / t_real, "unit": "spin-updates/s", "cores": w, "kind": "oracle",
+            "sample": f"{w} realizations (coupling seeds 0..{w - 1}), one process each, each a "
+                      f"full FP64 build + {n_prop} proposals + accepts ({wall:.1f} s wall), "
+                      f"extrapolated to {K_full} proposals per realization"}
+
+
 def calib_copy(mib):
     """One device-to-device copy of `mib` MiB: reads and writes exactly mib MiB each."""
     import torch
@@ -546,7 +584,13 @@ def main():
         run_sweep(args)
         return
     import synth
-    multi_p = len(disorder_strengths(synth.WORKLOADS[args.workload])) > 1
+    wl = synth.WORKLOADS[args.workload]
+    multi_p = len(disorder_strengths(wl)) > 1
+    # the oracle on all host cores first, while no process has touched the GPU (forked workers)
+    cpu_all = None
+    if not args.no_cpu and not multi_p and "L" in wl and not args.sweep:
+        cpu_all = run_cpu_all_cores(wl["L"], wl["chi"], wl["p"], args.proposals or wl["proposals"],
+                                    args.seed)
     serial = args.serial or args.graph
     res = run_gpu(args) if serial else run_gpu_pipelined(args)
     if not serial and not args.no_serial:
@@ -570,6 +614,8 @@ def main():
         run_fp64_plain(args, L0, res["chi"], p0, res["K"])
     cpu = None if args.no_cpu or not uniform or multi_p else \
         run_cpu_baseline(L0, res["chi"], p0, res["K"], args.seed)
+    if cpu is not None:
+        cpu["all_cores"] = cpu_all
     size = f"{L0}x{L0}" if uniform else "L x L (L in " + ", ".join(map(str, res["Ls"])) + ")"
     line = {
         "metric": METRIC,

@@ -64,3 +64,10 @@ def test_disorder_strengths():
     assert bench.disorder_strengths(synth.WORKLOADS["rbim64"]) == [0.109]
     Ls, seeds = bench.workload_sizes(synth.WORKLOADS["rbim256"])
     assert Ls == [256] * 128 and seeds == list(range(128))
+
+
+def test_cpu_all_cores_baseline_shape():
+    """The all-core oracle baseline: one forked process per core, a bounded sample each."""
+    r = bench.run_cpu_all_cores(8, 4, 0.109, 100, 0, n_prop=10, max_workers=2)
+    assert r["kind"] == "oracle" and r["unit"] == "spin-updates/s"
+    assert 1 <= r["cores"] <= 2 and r["value"] > 0

@@ -510,7 +510,7 @@ def calib_copy(mib):
     del src, dst
 
 
-DEFAULT_STEPS = {"rbim16": 50, "rbim64": 50, "mixed": 4, "rbim256": 2}
+DEFAULT_STEPS = {"rbim16": 50, "rbim64": 50, "mixed": 4, "rbim256": 2, "rbim256_chi32": 2}
 
 SWEEP_LS = (16, 32, 64, 128, 256)
 SWEEP_CHIS = (8, 16, 32, 48)

@@ -20,6 +20,9 @@ WORKLOADS = {
     "rbim64": dict(L=64, p=0.109, chi=32, seeds=tuple(range(64)), proposals=1000, philox_seed=0),
     "rbim256": dict(L=256, ps=(0.10, 0.109, 0.12), chi=48, seeds=tuple(range(128)),
                     proposals=1000, philox_seed=0),
+    # the same lattices and disorder at chi = 32 (FP32 environments): the bond / precision trade-off
+    "rbim256_chi32": dict(L=256, ps=(0.10, 0.109, 0.12), chi=32, seeds=tuple(range(128)),
+                          proposals=1000, philox_seed=0),
     "mixed": dict(Ls=(32, 64, 128, 256), p=0.109, chi=32, seeds=tuple(range(256)),
                   proposals=1000, philox_seed=0),
     "rbim1024": dict(L=1024, p=0.109, chi=64, seeds=(0, 1), proposals=1000, philox_seed=0),

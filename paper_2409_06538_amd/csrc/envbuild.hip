@@ -1328,8 +1328,43 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
                 if (a == piv) pkd = true;
                 if (a == 0) perm[j] = piv;
               }
-            } else
-            for (int j = 0; j < NK; ++j) {
+            } else {
+            // Wider: the first 16 columns of L stay in registers as above; later columns read the
+            // earlier rows of L^T from LDS (16 register columns measured faster than 32, which
+            // made the kernel spill).
+            constexpr int NRG = 16;
+            T Lr[NRG];
+            bool stop = false;
+#pragma unroll
+            for (int j = 0; j < NRG; ++j) {
+              const uint32_t key =
+                  pkd ? 0u : ((__float_as_uint(float(fmax(d, T(0)))) & ~63u) | uint32_t(63 - a));
+              const uint32_t bk = wave_max_u32(key);
+              const int piv = 63 - int(bk & 63u);
+              const T best = readlane_v(d, piv);
+              if (bk == 0u || !(best > tol2)) {
+                rk = j;
+                stop = true;
+                break;
+              }
+              const T hap = bufR[a * LDT + piv];
+              T inv = T(__builtin_amdgcn_rsq(double(best)));
+              inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
+              inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
+              const T sq = best * inv;
+              T dot = 0;
+#pragma unroll
+              for (int i = 0; i < j; ++i) dot += Lr[i] * readlane_v(Lr[i], piv);
+              const bool arow = !pkd && a != piv;
+              const T La = (a == piv) ? sq : (arow ? (hap - dot) * inv : T(0));
+              Lr[j] = La;
+              if (live) Tw[j * LDT + a] = La;
+              d -= arow ? La * La : T(0);
+              if (a == piv) pkd = true;
+              if (a == 0) perm[j] = piv;
+            }
+            if (!stop)
+            for (int j = NRG; j < NK; ++j) {
               const uint32_t key =
                   pkd ? 0u : ((__float_as_uint(float(fmax(d, T(0)))) & ~63u) | uint32_t(63 - a));
               const uint32_t bk = wave_max_u32(key);
@@ -1342,9 +1377,11 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
               inv = inv * (T(1.5) - T(0.5) * best * inv * inv);
               const T sq = best * inv;
               const T hap = bufR[a * LDT + piv];
-              // four rows per round, loads issued together (rows past j are clamped and masked)
               T dot = 0;
-              for (int i0 = 0; i0 < j; i0 += 4) {
+#pragma unroll
+              for (int i = 0; i < NRG; ++i) dot += Lr[i] * readlane_v(Lr[i], piv);
+              // four rows per round, loads issued together (rows past j are clamped and masked)
+              for (int i0 = NRG; i0 < j; i0 += 4) {
                 T x[4], y[4];
   #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -1361,6 +1398,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
               d -= arow ? La * La : T(0);
               if (a == piv) pkd = true;
               if (a == 0) perm[j] = piv;
+            }
             }
             if (live) unpk[a] = pkd ? 0 : 1;
             if (a == 0) {

@@ -7,7 +7,7 @@
  *
  * Problem (Sec. II, Sec. III A): an L x L square lattice with free boundaries, couplings
  * J_ij = +-1 on nearest-neighbour bonds, i.i.d. with P(J = -1) = p, energy
- * E(s) = -sum J_ij s_i s_j (Eq. (8)), Boltzmann weight exp(-beta E) (Eq. (1)).  TNMC contracts the
+ * E(s) = -sum J_ij s_i s_j (Eq. (10)), Boltzmann weight exp(-beta E) (Eq. (1)).  TNMC contracts the
  * tensor network of Z (Eq. (2)) with bond dimension truncated to chi (Sec. II B), samples
  * whole-lattice proposals from the approximate conditionals q(s_i | s_<i) (Eqs. (4)-(6)) and
  * removes the truncation bias with the Metropolis filter (Eq. (3)).
@@ -53,14 +53,20 @@ typedef enum {
   TNMC_EINVAL = -1,   /* bad argument (sizes, null pointers, unsupported chi or L) */
   TNMC_ENOMEM = -2,   /* workspace smaller than tnmc_workspace_bytes */
   TNMC_EHIP = -3,     /* a HIP call or kernel launch failed */
-  TNMC_ENUMERIC = -4, /* reserved: non-finite values reported by tnmc_status_check */
+  TNMC_ENUMERIC = -4, /* tnmc_status_check: a realization's status word holds a fault bit */
   TNMC_ESTATE = -5    /* chain state inconsistent with the call */
 } tnmc_status;
 
-/* Precision of the environments and of the contractions.  TNMC_FP64 and TNMC_FP32 store and
- * compute in that type.  TNMC_BF16 stores the environments as bfloat16 (round to nearest even
- * from the FP32 result of each site) and computes every contraction and factorisation in FP32;
- * the stored, rounded tensors are the environments that later rows and the sampler use.  The
+/* Storage precision of the environments.  What each mode computes in:
+ *   TNMC_FP64  environments stored in FP64; build (Householder / pivoted QR) and sampler in FP64.
+ *   TNMC_FP32  environments stored in FP32.  Build: at chi <= 32 the Gram form in FP64
+ *              arithmetic (FP64 matrix-core products), each site rounded to FP32 when stored; at
+ *              chi = 48 the QR form in FP32 arithmetic (FP32 matrix-core products).  Sampler:
+ *              FP32 arithmetic (FP32 matrix-core tiles for chi a multiple of 16).
+ *   TNMC_BF16  environments stored as bfloat16 (round to nearest even from the build's result of
+ *              each site); build arithmetic as for TNMC_FP32; the sampler widens each staged site
+ *              to FP32 and computes in FP32.
+ * The stored, rounded tensors are the environments that later rows and the sampler use.  The
  * running log-normalisation of the environments, log q(s), energies' Boltzmann factors and the
  * acceptance ratio are FP64 in every mode.  Lower precision can only lower the acceptance rate:
  * the Metropolis step keeps the chain exact whatever q is (Eq. (3)). */
@@ -76,7 +82,20 @@ typedef struct {
   uint64_t* d_Jv;     /* (L-1) x W(L) words */
   void* d_env;        /* tnmc_env_bytes(L, chi, prec) bytes: written by tnmc_build_env */
   double* d_lognorm;  /* L doubles: lambda_r = ln ||E_r||_2, written by tnmc_build_env */
+  uint32_t* d_status; /* one status word (TNMC_ST_* bits, OR-ed in by the kernels), or NULL */
 } tnmc_instance;
+
+/* Bits of a realization's status word.  Kernels only set bits; the caller clears the word (any
+ * device write of 0) and reads it with tnmc_status_check.  Fault bits: */
+#define TNMC_ST_LOGNORM 0x1u   /* tnmc_build_env: a log-norm lambda_r or ln Z_TN is not finite */
+#define TNMC_ST_WEIGHT 0x2u    /* tnmc_propose / tnmc_logq: a conditional weight Z_c(y) is NaN or
+                                  infinite (p+ fell back to 1/2 there) */
+#define TNMC_ST_LOGQ 0x4u      /* tnmc_propose / tnmc_logq: a log q(s) is not finite */
+#define TNMC_ST_DELTA 0x8u     /* tnmc_accept: an acceptance exponent Delta is not finite */
+#define TNMC_ST_FAULTS (TNMC_ST_LOGNORM | TNMC_ST_WEIGHT | TNMC_ST_LOGQ | TNMC_ST_DELTA)
+/* Not a fault (the reading for vanishing weights after truncation): both conditional weights of
+ * a site were <= 0 and p+ = 1/2 was used. */
+#define TNMC_ST_FALLBACK 0x10u
 
 /* Number of observable accumulators per realization (see tnmc_accept). */
 #define TNMC_OBS_COUNT 9
@@ -106,13 +125,14 @@ tnmc_status tnmc_make_couplings(const tnmc_instance* inst, int32_t n, const uint
                                 hipStream_t stream);
 
 /* a2 + a3 -- environments (Sec. II B).  For every realization: E_{L-1} = 1; for r = L-1..1,
- * E_{r-1} = compress_chi(T_r E_r) where T_r applies the row's Boltzmann matrices (Eq. (7)):
+ * E_{r-1} = compress_chi(T_r E_r) where T_r applies the row's Boltzmann matrices (Eq. (10)):
  * (T_r f)(x) = sum_y prod_c exp(beta Jv[r-1][c] x_c y_c) prod_c exp(beta Jh[r][c] y_c y_{c+1}) f(y).
  * compress_chi is the canonical SVD compression (left-orthonormalise by QR, then truncate
  * right to left keeping the chi largest singular values at every bond).  Each E_r is stored as a
  * unit-norm MPS in d_env (sites 1..L-1 right-orthonormal) with d_lognorm[r] = ln ||E_r||_2.
  * d_lnZ (n doubles, device, may be NULL) receives ln Z_TN = lambda_0 + ln sum_x H_0(x) E_0(x)/||E_0||.
- * The workspace must hold tnmc_workspace_bytes. */
+ * The workspace must hold tnmc_workspace_bytes.  A non-finite lambda_r or ln Z_TN sets
+ * TNMC_ST_LOGNORM in the realization's status word. */
 tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,
                            void* d_workspace, size_t workspace_bytes, double* d_lnZ,
                            hipStream_t stream);
@@ -128,7 +148,8 @@ tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tn
  * (FP64 sum of ln p+ or ln(1-p+), formed as the logarithm of the product of the conditionals with
  * its binary exponent kept apart), d_E [n][K] int32 exact energy (a5: E = 2U - N_B, U the number
  * of unsatisfied bonds).  d_fallbacks (n uint32, device, may be NULL) counts sites where p+ fell
- * back to 1/2 (accumulated, not reset). */
+ * back to 1/2 (accumulated, not reset).  Status word bits: TNMC_ST_WEIGHT where a weight was not
+ * finite, TNMC_ST_FALLBACK where both weights were <= 0, TNMC_ST_LOGQ for a non-finite log q. */
 tnmc_status tnmc_propose(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,
                          int32_t K, uint64_t seed, uint64_t first_proposal, void* d_workspace,
                          size_t workspace_bytes, uint64_t* d_spins, double* d_logq, int32_t* d_E,
@@ -140,7 +161,7 @@ tnmc_status tnmc_logq(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_pr
                       int32_t K, const uint64_t* d_spins, void* d_workspace,
                       size_t workspace_bytes, double* d_logq, hipStream_t stream);
 
-/* a5 -- exact integer energies E(s) = -sum J_ij s_i s_j (Eq. (8)) of d_spins [n][K][Lmax][W] into
+/* a5 -- exact integer energies E(s) = -sum J_ij s_i s_j (Eq. (10)) of d_spins [n][K][Lmax][W] into
  * d_E [n][K]. */
 tnmc_status tnmc_energy(const tnmc_instance* inst, int32_t n, int32_t K, const uint64_t* d_spins,
                         int32_t* d_E, void* d_workspace, size_t workspace_bytes,
@@ -158,7 +179,8 @@ tnmc_status tnmc_energy(const tnmc_instance* inst, int32_t n, int32_t K, const u
  * call).  If d_accum != NULL, the observables of Sec. III C of every chain after every step are
  * added to d_accum [n][TNMC_OBS_COUNT]: count, sum E, sum E^2, sum m^2, sum m^4, sum m_edge^2,
  * sum q, sum q^2, sum q^4 (q = overlap of chains 0 and 1, when n_chain >= 2; m_edge over the
- * sites L/4 .. 3L/4-1 of each edge, divided by 2L). */
+ * sites L/4 .. 3L/4-1 of each edge, divided by 2L).  A non-finite Delta sets TNMC_ST_DELTA in the
+ * realization's status word (the proposal is then rejected: the comparisons are false). */
 tnmc_status tnmc_accept(const tnmc_instance* inst, int32_t n, int32_t n_chain, int32_t K,
                         const uint64_t* d_prop_spins, const double* d_prop_logq,
                         const int32_t* d_prop_E, uint64_t seed, uint64_t first_step,
@@ -173,6 +195,28 @@ tnmc_status tnmc_observables(const tnmc_instance* inst, int32_t n, int32_t n_cha
                              const uint64_t* d_chain_spins, const int32_t* d_chain_E,
                              double* d_accum, void* d_workspace, size_t workspace_bytes,
                              hipStream_t stream);
+
+/* f1 -- disorder averages of the sampled quantities (Sec. III C) over n realizations of one
+ * lattice side L at inverse temperature beta, from their d_accum rows [n][TNMC_OBS_COUNT] (as
+ * filled by tnmc_accept / tnmc_observables with n_chain chains per realization).  The thermal
+ * average < > of realization i is its sum over its sample count (count / n_chain for the overlap,
+ * formed once per step from chains 0 and 1); [ ] is the mean over the n realizations.  Writes
+ * d_out[TNMC_AVG_COUNT] (device): [<E>], [<E^2>], [<m^2>], [<m^4>], [<m_edge^2>], [<q>], [<q^2>],
+ * [<q^4>], [<q^2>^2], the Binder ratio Q_q = [<q^4>] / [<q^2>^2] (Eq. (15)), the overlap
+ * susceptibility chi_q = (L^2 / T) ([<q^2>] - [<q>]^2) (Eq. (16)) and the edge susceptibility
+ * chi_edge = L [<m_edge^2>] (Sec. III C).  The overlap entries need n_chain >= 2 (else they are 0
+ * and Q_q is not a number).  Mixed-L batches average each L's rows separately. */
+#define TNMC_AVG_COUNT 12
+tnmc_status tnmc_disorder_average(const double* d_accum, int32_t n, int32_t L, double beta,
+                                  int32_t n_chain, double* d_out, hipStream_t stream);
+
+/* Numeric status of a batch: waits until `stream` has finished, then reads the status word of
+ * every realization (0 where d_status is NULL) into h_words (n words, host memory, may be NULL).
+ * Returns TNMC_ENUMERIC if any word holds a fault bit (TNMC_ST_FAULTS), TNMC_OK otherwise,
+ * TNMC_EHIP if a HIP call fails.  It synchronises, so it cannot be captured into a HIP graph;
+ * the words are not cleared. */
+tnmc_status tnmc_status_check(const tnmc_instance* inst, int32_t n, uint32_t* h_words,
+                              hipStream_t stream);
 
 const char* tnmc_status_string(tnmc_status s);
 

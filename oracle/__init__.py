@@ -17,7 +17,7 @@ Modules
 -------
 philox       Philox4x64-10 counter-based generator (Salmon et al., SC'11) and 53-bit uniforms.
 instance     +-J couplings with antiferromagnetic probability p; Nishimori-line inverse temperature.
-energy       E(s) = -sum J_ij s_i s_j with open boundaries (Sec. III A, Eq. (8)).
+energy       E(s) = -sum J_ij s_i s_j with open boundaries (Sec. III A, Eq. (10)).
 exact        Brute-force enumeration and exact row transfer matrix (independent of the TN code).
 envbuild     Boundary-MPS environments: row MPO applied to an MPS, QR + SVD compression to chi.
 sampler      Whole-lattice proposals from the environments with log q(s); teacher-forced log q.

@@ -1,4 +1,4 @@
-"""Energy of the +-J random-bond Ising model with open boundaries (Sec. III A, Eq. (8)).
+"""Energy of the +-J random-bond Ising model with open boundaries (Sec. III A, Eq. (10)).
 
 E(s) = - sum over nearest-neighbour bonds (ij) of J_ij s_i s_j.  Written as the plain double
 loop over bonds; the batch of configurations is the only vectorised axis.

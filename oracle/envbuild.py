@@ -1,7 +1,7 @@
 """Boundary-MPS environments of the 2D open-lattice Ising tensor network (Sec. II B).
 
 The partition function of Eq. (2) is a network of copy tensors (delta) and Boltzmann matrices W
-(Eq. (7) for W; the T tensor of Sec. II B absorbs the W on the right and bottom bonds of each
+(Eq. (10) for W; the T tensor of Sec. II B absorbs the W on the right and bottom bonds of each
 site).  It is contracted from the last site upward, storing the process tensors for later
 sampling, with bond dimensions truncated by SVD to a fixed maximum D = chi (Sec. II B).
 
@@ -42,7 +42,7 @@ _SGN = np.array([1.0, -1.0])
 
 
 def _bond_matrix(beta, J):
-    """exp(beta J s s') for s, s' in (+1, -1): the Boltzmann matrix W of Eq. (7)."""
+    """exp(beta J s s') for s, s' in (+1, -1): the Boltzmann matrix W of Eq. (10)."""
     return np.exp(beta * J * np.outer(_SGN, _SGN))
 
 

@@ -1,7 +1,7 @@
 """Problem instances: +-J couplings on an open Lr x Lc square lattice and the Nishimori line.
 
 Sec. III A: J_ij = +1 with probability 1-p and -1 (antiferromagnetic) with probability p,
-independently per nearest-neighbour bond (the disorder law following Eq. (8)); free boundaries
+independently per nearest-neighbour bond (the disorder law of Eq. (11)); free boundaries
 in both directions (Sec. II).  Sec. III A also gives the Nishimori line, exp(-2/T) = p/(1-p)
 for J = 1, i.e. beta_N = (1/2) ln((1-p)/p).
 

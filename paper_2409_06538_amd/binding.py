@@ -22,6 +22,12 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 ENV_DTYPES = {FP64: torch.float64, FP32: torch.float32, BF16: torch.bfloat16}
 OBS_COUNT = 9
 OBS_NAMES = ("count", "E", "E2", "m2", "m4", "medge2", "q", "q2", "q4")
+# status word bits (include/tnmc.h)
+ST_LOGNORM, ST_WEIGHT, ST_LOGQ, ST_DELTA, ST_FALLBACK = 0x1, 0x2, 0x4, 0x8, 0x10
+ST_FAULTS = ST_LOGNORM | ST_WEIGHT | ST_LOGQ | ST_DELTA
+ENUMERIC = -4
+AVG_COUNT = 12
+AVG_NAMES = ("E", "E2", "m2", "m4", "medge2", "q", "q2", "q4", "q2sq", "Q_q", "chi_q", "chi_edge")
 
 _lib = None
 
@@ -29,7 +35,8 @@ _lib = None
 class Instance(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("pad_", ctypes.c_int32), ("beta", ctypes.c_double),
                 ("id", ctypes.c_uint64), ("d_Jh", ctypes.c_void_p), ("d_Jv", ctypes.c_void_p),
-                ("d_env", ctypes.c_void_p), ("d_lognorm", ctypes.c_void_p)]
+                ("d_env", ctypes.c_void_p), ("d_lognorm", ctypes.c_void_p),
+                ("d_status", ctypes.c_void_p)]
 
 
 class TNMCError(RuntimeError):
@@ -60,6 +67,8 @@ def load():
         "tnmc_accept": (ctypes.c_int, [P, i32, i32, i32, vp, vp, vp, u64, u64, vp, vp, vp, vp, vp,
                                        vp, vp, vp, sz, vp]),
         "tnmc_observables": (ctypes.c_int, [P, i32, i32, vp, vp, vp, vp, sz, vp]),
+        "tnmc_disorder_average": (ctypes.c_int, [vp, i32, i32, dbl, i32, vp, vp]),
+        "tnmc_status_check": (ctypes.c_int, [P, i32, vp, vp]),
         "tnmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
     for name, (res, args) in sigs.items():
@@ -74,7 +83,8 @@ def exported_symbols():
     """Names of the C entry points this binding declares."""
     return ["tnmc_chi_supported", "tnmc_env_bytes", "tnmc_workspace_bytes", "tnmc_make_couplings",
             "tnmc_build_env", "tnmc_propose", "tnmc_logq", "tnmc_energy", "tnmc_accept",
-            "tnmc_observables", "tnmc_status_string"]
+            "tnmc_observables", "tnmc_disorder_average", "tnmc_status_check",
+            "tnmc_status_string"]
 
 
 def _check(status, what):
@@ -118,6 +128,8 @@ class Batch:
             raise TNMCError(f"chi={chi} not supported for {precision}")
         self.Jh, self.Jv, self.env, self.lognorm = [], [], [], []
         self.table = (Instance * self.n)()
+        # one numeric status word per realization (TNMC_ST_* bits)
+        self.status = torch.zeros(self.n, dtype=torch.int32, device=self.device)
         for i, L in enumerate(self.Ls):
             W = words_per_row(L)
             jh = torch.zeros(L * W, dtype=torch.int64, device=self.device)
@@ -133,6 +145,7 @@ class Batch:
             t.L, t.pad_, t.beta, t.id = L, 0, float(betas[i]), int(ids[i])
             t.d_Jh, t.d_Jv = jh.data_ptr(), jv.data_ptr()
             t.d_env, t.d_lognorm = env.data_ptr(), lam.data_ptr()
+            t.d_status = self.status.data_ptr() + 4 * i
         self.K = 0
         self.workspace = None
         self.ensure_workspace(K)
@@ -247,6 +260,35 @@ class Batch:
         _check(load().tnmc_observables(self.table, self.n, chains["n_chain"], _ptr(chains["spins"]),
                                        _ptr(chains["E"]), _ptr(accum), ws, nb, _stream()),
                "tnmc_observables")
+
+    def disorder_average(self, accum, n_chain, rows=None):
+        """tnmc_disorder_average over the realizations `rows` (default: all; they must share one L
+        and one beta) of accum [n][9] -> tensor of AVG_COUNT values (AVG_NAMES order)."""
+        rows = list(range(self.n)) if rows is None else list(rows)
+        Ls = {self.Ls[i] for i in rows}
+        betas = {self.table[i].beta for i in rows}
+        if len(Ls) != 1 or len(betas) != 1:
+            raise TNMCError("disorder_average needs rows of one L and one beta")
+        sub = accum[rows].contiguous()
+        out = torch.empty(AVG_COUNT, dtype=torch.float64, device=self.device)
+        _check(load().tnmc_disorder_average(_ptr(sub), len(rows), Ls.pop(), betas.pop(),
+                                            int(n_chain), _ptr(out), _stream()),
+               "tnmc_disorder_average")
+        return out
+
+    def status_check(self):
+        """tnmc_status_check: wait for the stream, return (status code, status words as a list);
+        the code is 0 (ok) or ENUMERIC (a fault bit is set in some realization's word)."""
+        words = (ctypes.c_uint32 * self.n)()
+        st = load().tnmc_status_check(self.table, self.n, ctypes.cast(words, ctypes.c_void_p),
+                                      _stream())
+        if st not in (0, ENUMERIC):
+            _check(st, "tnmc_status_check")
+        return st, list(words)
+
+    def clear_status(self):
+        """Zero every realization's status word (a device fill on the current stream)."""
+        self.status.zero_()
 
     def env_tensor(self, i):
         """Environments of realization i as (L, L, 2, chi, chi)."""

@@ -111,6 +111,7 @@ hipError_t upload_desc(const tnmc_instance* inst, int32_t n, int32_t chi, int32_
     d.env = inst[i].d_env;
     d.lognorm = inst[i].d_lognorm;
     d.ws = base + off;
+    d.status = inst[i].d_status;
     if (use == Use::build) off += align_up(env_build_scratch_bytes(p, chi, inst[i].L));
     else if (use == Use::propose) off += align_up(propose_scratch_bytes(p, chi, inst[i].L, K));
   }
@@ -258,13 +259,39 @@ tnmc_status tnmc_observables(const tnmc_instance* inst, int32_t n, int32_t n_cha
   return hip_status(e);
 }
 
+tnmc_status tnmc_disorder_average(const double* d_accum, int32_t n, int32_t L, double beta,
+                                  int32_t n_chain, double* d_out, hipStream_t stream) {
+  if (d_accum == nullptr || d_out == nullptr || n < 1 || L < 2 || L > 1024 || n_chain < 1 ||
+      !(beta > 0.0) || !std::isfinite(beta))
+    return TNMC_EINVAL;
+  return hip_status(disorder_average_launch(d_accum, n, L, beta, n_chain, d_out, stream));
+}
+
+tnmc_status tnmc_status_check(const tnmc_instance* inst, int32_t n, uint32_t* h_words,
+                              hipStream_t stream) {
+  if (inst == nullptr || n < 1) return TNMC_EINVAL;
+  std::vector<uint32_t> w(size_t(n), 0u);
+  for (int i = 0; i < n; ++i)
+    if (inst[i].d_status != nullptr &&
+        hipMemcpyAsync(&w[i], inst[i].d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess)
+      return TNMC_EHIP;
+  if (hipStreamSynchronize(stream) != hipSuccess) return TNMC_EHIP;
+  bool fault = false;
+  for (int i = 0; i < n; ++i) {
+    if (h_words != nullptr) h_words[i] = w[i];
+    fault = fault || (w[i] & TNMC_ST_FAULTS) != 0;
+  }
+  return fault ? TNMC_ENUMERIC : TNMC_OK;
+}
+
 const char* tnmc_status_string(tnmc_status s) {
   switch (s) {
     case TNMC_OK: return "ok";
     case TNMC_EINVAL: return "invalid argument";
     case TNMC_ENOMEM: return "workspace too small";
     case TNMC_EHIP: return "HIP call or kernel launch failed";
-    case TNMC_ENUMERIC: return "non-finite values";
+    case TNMC_ENUMERIC: return "non-finite values (see the realization status words)";
     case TNMC_ESTATE: return "inconsistent chain state";
   }
   return "unknown status";

@@ -1,4 +1,4 @@
-// Couplings (Sec. III A), exact energies (Eq. (8)), the independence Metropolis chain (Eq. (3)
+// Couplings (Sec. III A), exact energies (Eq. (10)), the independence Metropolis chain (Eq. (3)
 // with g(s'|s) = q(s'); Appendix A) and the observables of Sec. III C.
 #include <hip/hip_runtime.h>
 
@@ -117,6 +117,7 @@ __global__ void accept_kernel(const DevReal* reals, int n, int n_chain, int K,
   bool init = chain_init[t] != 0;
   oldE[t] = E;
   int cur = -1;
+  bool bad_delta = false;
   for (int s = 0; s < Kc; ++s) {
     const int k = j * Kc + s;
     const size_t o = size_t(ri) * K + k;
@@ -132,6 +133,7 @@ __global__ void accept_kernel(const DevReal* reals, int n, int n_chain, int K,
       lq = lp;
     } else {
       const double delta = (-R.beta * double(Ep) - lp) - (-R.beta * double(E) - lq);
+      bad_delta = bad_delta || !isfinite(delta);
       if (delta >= 0.0 || u < exp(delta)) {
         acc = true;
         cur = k;
@@ -146,6 +148,7 @@ __global__ void accept_kernel(const DevReal* reals, int n, int n_chain, int K,
   chain_logq[t] = lq;
   chain_init[t] = init ? 1 : 0;
   final_idx[t] = cur;
+  if (bad_delta && R.status != nullptr) atomicOr(R.status, TNMC_ST_DELTA);
 }
 
 // Copy each chain's final configuration (if it came from this batch) into the chain state.
@@ -300,6 +303,49 @@ hipError_t observables_launch(const DevReal* d_reals, int n, int n_chain, int Lm
                               double* d_accum, hipStream_t stream) {
   hipLaunchKernelGGL(observables_kernel, dim3(n), dim3(256), 0, stream, d_reals, n_chain, n_chain,
                      Lmax, nullptr, nullptr, nullptr, d_chain_spins, d_chain_E, d_accum);
+  return hipGetLastError();
+}
+
+// Disorder averages of Sec. III C over the n rows of accum (one realization each, one
+// workgroup, fixed reduction order).  Thermal averages per realization: sum / count for the
+// per-chain quantities, sum / (count / n_chain) for the overlap (formed once per step).
+__global__ void __launch_bounds__(256) disorder_average_kernel(const double* accum, int n, int L,
+                                                               double beta, int n_chain,
+                                                               double* out) {
+  constexpr int NT = 256, NQ = 9;
+  __shared__ double part[NQ][NT];
+  const int tid = threadIdx.x;
+  double a[NQ];
+  for (int j = 0; j < NQ; ++j) a[j] = 0.0;
+  for (int i = tid; i < n; i += NT) {
+    const double* r = accum + size_t(i) * TNMC_OBS_COUNT;
+    const double cnt = r[0], cq = r[0] / double(n_chain);
+    for (int j = 0; j < 5; ++j) a[j] += r[1 + j] / cnt;    // <E>, <E^2>, <m^2>, <m^4>, <m_edge^2>
+    for (int j = 0; j < 3; ++j) a[5 + j] += r[6 + j] / cq; // <q>, <q^2>, <q^4>
+    const double q2 = r[7] / cq;
+    a[8] += q2 * q2;                                       // <q^2>^2
+  }
+  for (int j = 0; j < NQ; ++j) part[j][tid] = a[j];
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (tid < h)
+      for (int j = 0; j < NQ; ++j) part[j][tid] += part[j][tid + h];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double m[NQ];
+    for (int j = 0; j < NQ; ++j) m[j] = part[j][0] / double(n);
+    for (int j = 0; j < NQ; ++j) out[j] = m[j];
+    out[9] = m[7] / m[8];                                      // Q_q = [<q^4>] / [<q^2>^2]
+    out[10] = double(L) * double(L) * beta * (m[6] - m[5] * m[5]);   // chi_q
+    out[11] = double(L) * m[4];                                // chi_edge = L [<m_edge^2>]
+  }
+}
+
+hipError_t disorder_average_launch(const double* d_accum, int n, int L, double beta, int n_chain,
+                                   double* d_out, hipStream_t stream) {
+  hipLaunchKernelGGL(disorder_average_kernel, dim3(1), dim3(256), 0, stream, d_accum, n, L, beta,
+                     n_chain, d_out);
   return hipGetLastError();
 }
 

@@ -4,7 +4,7 @@
 // One workgroup owns one realization and walks its rows r = L-1 .. 1 (E_{r-1} needs E_r).  The
 // operator-applied site tensor is never stored:
 //   At_c[(a,alpha), x, (b,alpha')] = wh(a,b) wv(x,b) A_c[b][alpha][alpha'],
-// with wh, wv the Boltzmann weights (Eq. (7)) of the horizontal bond (c-1, c) of row r and of the
+// with wh, wv the Boltzmann weights (Eq. (10)) of the horizontal bond (c-1, c) of row r and of the
 // vertical bond between rows r-1 and r at column c.  Per row:
 //   left to right, c = 0 .. L-2: M_c = R_{c-1} At_c (rows (i, x), columns (b, alpha')), whose R
 //     factor R_c (Householder) is kept, rescaled by 2^-e_c.  This is the QR sweep of the canonical
@@ -1775,6 +1775,9 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     }
   }
 
+  // a non-finite log-norm of any row propagates into the last one (lambda_0)
+  if (tid == 0 && R.status != nullptr && !isfinite(lambda)) atomicOr(R.status, TNMC_ST_LOGNORM);
+
   // ---------------- ln Z_TN from the top row ----------------
   if (lnZ_out != nullptr) {
     __syncthreads();
@@ -1804,7 +1807,9 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     __syncthreads();
     if (tid == 0) {
       const double s = double(sc[0]) + double(sc[CHI]);
-      lnZ_out[R.slot] = lambda + logacc + log(s);
+      const double lz = lambda + logacc + log(s);
+      lnZ_out[R.slot] = lz;
+      if (R.status != nullptr && !isfinite(lz)) atomicOr(R.status, TNMC_ST_LOGNORM);
     }
   }
 }

@@ -20,6 +20,7 @@ struct DevReal {
   void* env;
   double* lognorm;
   void* ws;   // this realization's slice of the workspace (call-specific use)
+  uint32_t* status;   // numeric status word (TNMC_ST_* bits) or nullptr
 };
 
 hipError_t couplings_launch(const DevReal* d_reals, int n, const uint64_t* d_seeds, double p,
@@ -48,5 +49,8 @@ hipError_t accept_launch(const DevReal* d_reals, int n, int n_chain, int K, int 
 hipError_t observables_launch(const DevReal* d_reals, int n, int n_chain, int Lmax,
                               const uint64_t* d_chain_spins, const int32_t* d_chain_E,
                               double* d_accum, hipStream_t stream);
+
+hipError_t disorder_average_launch(const double* d_accum, int n, int L, double beta, int n_chain,
+                                   double* d_out, hipStream_t stream);
 
 }  // namespace tnmc

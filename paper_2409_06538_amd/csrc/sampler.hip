@@ -1,5 +1,5 @@
 // Whole-lattice proposals from the cached environments (Sec. II A-B of arXiv:2409.06538,
-// Eqs. (4)-(6)), with log q(s) in FP64 and the exact integer energy (Eq. (8)) of each proposal.
+// Eqs. (4)-(6)), with log q(s) in FP64 and the exact integer energy (Eq. (10)) of each proposal.
 //
 // Row r of a proposal is drawn from the row chain
 //   f_r(y) = prod_c phi_c(y_c) prod_c w_c(y_c, y_{c+1}) E_r(y),
@@ -61,6 +61,7 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
   for (int w = 0; w < MAX_W; ++w) { prev[w * PROP_NT] = 0; cur[w * PROP_NT] = 0; }
   double logq = 0.0;
   uint32_t nfb = 0;
+  uint32_t stb = 0;   // status bits of this proposal
   int unsat = 0;
   const uint64_t* tin = teacher ? teacher + (size_t(ri) * K + kk) * size_t(Lmax) * Wmax : nullptr;
 
@@ -158,6 +159,7 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
       double zm = double(z[1]) > 0.0 ? double(z[1]) : 0.0;
       double tot = zp + zm;
       double pp;
+      if (!isfinite(z[0]) || !isfinite(z[1])) stb |= TNMC_ST_WEIGHT;
       if (!(tot > 0.0) || !isfinite(tot)) {
         pp = 0.5;
         ++nfb;
@@ -216,6 +218,9 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
   }
   if (active) {
     logq_out[size_t(ri) * K + k] = logq;
+    if (!isfinite(logq)) stb |= TNMC_ST_LOGQ;
+    if (nfb) stb |= TNMC_ST_FALLBACK;
+    if (R.status != nullptr && stb != 0) atomicOr(R.status, stb);
     if (!teacher) {
       E_out[size_t(ri) * K + k] = 2 * unsat - 2 * L * (L - 1);
       // rows beyond this realization's L (mixed batches) are zero
@@ -330,6 +335,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   double qprod = 1.0;
   int qexp = 0;
   uint32_t nfb = 0;
+  uint32_t stb = 0;   // status bits of this proposal
   int unsat = 0;
   int pr = 0;   // rows[pr]: row above; rows[pr ^ 1]: row being drawn
 
@@ -548,6 +554,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
       const double dzm = double(zm) > 0.0 ? double(zm) : 0.0;
       const double tot = dzp + dzm;
       double pp;
+      if (!isfinite(zp) || !isfinite(zm)) stb |= TNMC_ST_WEIGHT;
       if (!(tot > 0.0) || !isfinite(tot)) {
         pp = 0.5;
         ++nfb;
@@ -637,7 +644,11 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
     pr ^= 1;
   }
   if (active && q == 0) {
-    logq_out[size_t(ri) * K + k] = log(qprod) + double(qexp) * 0.69314718055994530942;
+    const double lq = log(qprod) + double(qexp) * 0.69314718055994530942;
+    logq_out[size_t(ri) * K + k] = lq;
+    if (!isfinite(lq)) stb |= TNMC_ST_LOGQ;
+    if (nfb) stb |= TNMC_ST_FALLBACK;
+    if (R.status != nullptr && stb != 0) atomicOr(R.status, stb);
     if (!teacher) {
       E_out[size_t(ri) * K + k] = 2 * unsat - 2 * L * (L - 1);
       for (int r = L; r < Lmax; ++r) {

@@ -72,3 +72,55 @@ def test_host_validation_rejects_bad_arguments(lib):
     assert lib.tnmc_accept(tab, 1, 3, 4, dummy, dummy, dummy, 0, 0, dummy, dummy, dummy, dummy,
                            dummy, dummy, None, dummy, 1 << 20, None) == -1
     assert lib.tnmc_status_string(-2).decode() == "workspace too small"
+
+
+def test_short_workspace_is_enomem_on_every_entry_point(lib):
+    """Every entry point that takes the workspace checks its size on the host and returns
+    TNMC_ENOMEM before anything is enqueued (the pointers here are never dereferenced)."""
+    from paper_2409_06538_amd import binding
+    tab = (binding.Instance * 2)()
+    fake = ctypes.c_void_p(1 << 20)
+    for i, L in enumerate((16, 40)):
+        tab[i].L, tab[i].beta, tab[i].id = L, 0.9, i
+        tab[i].d_Jh = tab[i].d_Jv = tab[i].d_env = tab[i].d_lognorm = 1 << 20
+    seeds = (ctypes.c_uint64 * 2)(0, 1)
+    short = 8
+    enomem = -2
+    calls = {
+        "tnmc_make_couplings": lambda: lib.tnmc_make_couplings(
+            tab, 2, ctypes.cast(seeds, ctypes.c_void_p), 0.1, fake, short, None),
+        "tnmc_build_env": lambda: lib.tnmc_build_env(tab, 2, 16, binding.FP32, fake, short, None,
+                                                     None),
+        "tnmc_propose": lambda: lib.tnmc_propose(tab, 2, 16, binding.FP32, 8, 0, 0, fake, short,
+                                                 fake, fake, fake, None, None),
+        "tnmc_logq": lambda: lib.tnmc_logq(tab, 2, 16, binding.FP32, 8, fake, fake, short, fake,
+                                           None),
+        "tnmc_energy": lambda: lib.tnmc_energy(tab, 2, 8, fake, fake, fake, short, None),
+        "tnmc_accept": lambda: lib.tnmc_accept(tab, 2, 1, 8, fake, fake, fake, 0, 0, fake, fake,
+                                               fake, fake, fake, fake, None, fake, short, None),
+        "tnmc_observables": lambda: lib.tnmc_observables(tab, 2, 1, fake, fake, fake, fake, short,
+                                                         None),
+    }
+    takes_workspace = [n for n in declared_symbols()
+                       if "workspace_bytes" in header_signature(n) and n != "tnmc_workspace_bytes"]
+    assert sorted(calls) == sorted(takes_workspace)
+    for name, call in calls.items():
+        assert call() == enomem, name
+
+
+def header_signature(name):
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    m = re.search(r"\b" + name + r"\s*\((.*?)\);", text, flags=re.S)
+    return m.group(1) if m else ""
+
+
+def test_status_bits_match_header():
+    from paper_2409_06538_amd import binding
+    text = open(HEADER).read()
+    bits = dict(re.findall(r"#define (TNMC_ST_[A-Z]+) (0x[0-9a-f]+)u", text))
+    assert int(bits["TNMC_ST_LOGNORM"], 16) == binding.ST_LOGNORM
+    assert int(bits["TNMC_ST_WEIGHT"], 16) == binding.ST_WEIGHT
+    assert int(bits["TNMC_ST_LOGQ"], 16) == binding.ST_LOGQ
+    assert int(bits["TNMC_ST_DELTA"], 16) == binding.ST_DELTA
+    assert int(bits["TNMC_ST_FALLBACK"], 16) == binding.ST_FALLBACK
+    assert "tnmc_status_check" in declared_symbols()

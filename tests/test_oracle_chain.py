@@ -12,6 +12,7 @@
 import math
 
 import numpy as np
+import pytest
 from scipy import stats
 
 from oracle import accept, energy, envbuild, exact, instance, observables, sampler
@@ -103,6 +104,30 @@ def test_observables_definitions():
     assert observables.edge_magnetization(s2) == 1.0
 
 
+def test_observables_checkerboard_and_random_configurations():
+    L = 8
+    r, c = np.indices((L, L))
+    cb = np.where((r + c) % 2 == 0, 1, -1).astype(np.int8)
+    up = np.ones((L, L), dtype=np.int8)
+    assert observables.magnetization(cb) == 0.0
+    assert observables.edge_magnetization(cb) == 0.0      # each segment alternates, L/2 even
+    assert observables.overlap(cb, up) == 0.0 and observables.overlap(cb, cb) == 1.0
+    # random configurations against plain loops over the sites and the four edge segments
+    rng = np.random.default_rng(4)
+    for L in (4, 8, 12):
+        s = rng.choice(np.array([-1, 1], dtype=np.int8), size=(3, L, L))
+        for k in range(3):
+            m = sum(int(s[k, i, j]) for i in range(L) for j in range(L)) / (L * L)
+            assert observables.magnetization(s[k]) == pytest.approx(m, abs=1e-15)
+            seg = range(L // 4, (3 * L) // 4)
+            me = sum(int(s[k, 0, i]) + int(s[k, L - 1, i]) + int(s[k, i, 0]) + int(s[k, i, L - 1])
+                     for i in seg) / (2 * L)
+            assert observables.edge_magnetization(s[k]) == pytest.approx(me, abs=1e-15)
+            q = sum(int(s[k, i, j]) * int(s[(k + 1) % 3, i, j])
+                    for i in range(L) for j in range(L)) / (L * L)
+            assert observables.overlap(s[k], s[(k + 1) % 3]) == pytest.approx(q, abs=1e-15)
+
+
 def test_nishimori_overlap_equals_magnetisation_exact_samples():
     # [<q^2>] = [<m^2>] on the Nishimori line (gauge identity), with exact samples per realization
     L, p = 3, 0.109
@@ -120,3 +145,30 @@ def test_nishimori_overlap_equals_magnetisation_exact_samples():
     q2, m2 = np.array(q2), np.array(m2)
     d = q2 - m2
     assert abs(d.mean()) < 5 * d.std(ddof=1) / math.sqrt(len(d)) + 1e-3
+
+
+def test_disorder_averages_closed_form():
+    """Eqs. (15)-(16) and chi_edge on hand-built chains: two realizations, two chains, two steps.
+    Realization A: (up, up) then (up, down): <q> = 0, <q^2> = <q^4> = 1.  Realization B:
+    (checkerboard, up) then (up, up): <q> = <q^2> = <q^4> = 1/2.  So [<q>] = 1/4, [<q^2>] =
+    [<q^4>] = 3/4, [<q^2>^2] = 5/8, Q_q = 6/5, chi_q = L^2 beta (3/4 - 1/16)."""
+    L, beta = 8, 0.7
+    r, c = np.indices((L, L))
+    up = np.ones((L, L), dtype=np.int8)
+    cb = np.where((r + c) % 2 == 0, 1, -1).astype(np.int8)
+    A = np.array([[up, up], [up, -up]])               # (chain, step, L, L)
+    B = np.array([[cb, up], [up, up]])
+    rows = []
+    for sp in (A, B):
+        E = np.array([[-10, -12], [-14, -16]])
+        rows.append(observables.accumulate(sp, E))
+    out = dict(zip(observables.AVG_NAMES, observables.disorder_averages(np.array(rows), L, beta, 2)))
+    assert out["q"] == pytest.approx(0.25) and out["q2"] == pytest.approx(0.75)
+    assert out["q4"] == pytest.approx(0.75) and out["q2sq"] == pytest.approx(5 / 8)
+    assert out["Q_q"] == pytest.approx(6 / 5)
+    assert out["chi_q"] == pytest.approx(L * L * beta * (0.75 - 0.0625))
+    assert out["E"] == pytest.approx(-13.0) and out["E2"] == pytest.approx((100 + 144 + 196 + 256) / 4)
+    # m^2: A all 1; B: checkerboard 0, three uniform -> 3/4; [<m^2>] = 7/8
+    assert out["m2"] == pytest.approx(7 / 8) and out["m4"] == pytest.approx(7 / 8)
+    # m_edge^2: uniform 1, checkerboard 0 -> same as m^2 here; chi_edge = L [<m_edge^2>]
+    assert out["medge2"] == pytest.approx(7 / 8) and out["chi_edge"] == pytest.approx(L * 7 / 8)

@@ -1,4 +1,4 @@
-"""Pins of oracle.energy (Sec. III A, Eq. (8)) and oracle.exact (Eqs. (1)-(2)).
+"""Pins of oracle.energy (Sec. III A, Eq. (10)) and oracle.exact (Eqs. (1)-(2)).
 
 A hand-worked example, symmetries of E, and Nishimori's exact disorder-averaged energy on the
 Nishimori line, [<E>] = -N_B (1 - 2p), evaluated exhaustively over all disorder configurations

@@ -2,22 +2,26 @@
 
 One step = one pass of the whole hot path over one batch: couplings (a1) -> environments (a2,
 a3) -> K proposals per realization with log q and exact energies (a4, a5) -> independence
-Metropolis over them (a6).  Default workload: 64 realizations of the 64 x 64 open +-J lattice at
-p = 0.109 on the Nishimori line, chi = 32, 1000 proposals each, FP32 batched (one launch per
-stage for the whole batch).
+Metropolis over them (a6).  Default workload: the largest configuration built, 128 realizations
+of the 256 x 256 open +-J lattice at each of p = 0.10, 0.109, 0.12 on the Nishimori line
+(the same coupling seeds), chi = 48, BF16 environments, 1000 proposals each (one launch per
+stage for each batch).  `--workload rbim64` runs the 64 realizations of the 64 x 64 lattice at
+chi = 32 (FP32), `--workload mixed` the mixed-L batch, `--workload rbim16` the single 16 x 16
+FP64 realization.
 
-Consecutive steps overlap: the builds of steps t+1 and t+2 (one workgroup per realization each,
-on CUs kept free of proposal work by a CU mask, one stream each) run during the proposals and
-accepts of step t (on the other CUs); three sets of environments rotate.  The timed region starts
-with an empty pipeline and ends when the last step's accepts are done.  Batches of more than 64
-realizations run their two builds in flight without the CU mask.  `--workload rbim256` runs the
-L = 256, chi = 48 BF16 workload at its three disorder strengths (one batch per p, consecutive
-pipeline stages); `--workload mixed` the mixed-L batch.  `serial` reports the same steps one
-after the other on one stream.  Also measured: the FP64 plain form (FP64 environments, one
-realization per call, one proposal per call) on a bounded sample, and the CPU FP64 oracle on the
-host (bounded sample, extrapolated; labelled).
+Consecutive stages overlap: the builds of the next one or two batches (one workgroup per
+realization each, one stream each) run during the proposals and accepts of the current one (on
+the other CUs; a CU mask keeps 8 CUs of every XCD per build free when a build has at most 64
+workgroups); depth + 1 sets of environments rotate.  The timed region starts with an empty
+pipeline and ends when the last stage's accepts are done.  Every stage draws new proposals
+(first proposal id = stage index x K) and its chains continue from the previous stage of the
+same batch (the same instance, so the same target distribution).  `serial` reports the same
+steps one after the other on one stream.  Also measured: the FP64 plain form (FP64
+environments, one realization per call, one proposal per call) on a bounded sample, the CPU
+FP64 oracle on the host (bounded sample, extrapolated; labelled), and the error of the timed
+run's environments and log q against stored oracle values (tests/golden).
 
-Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 50] [--warmup 1] [--serial]
+Prints ONE JSON line.  Usage: python bench.py [--gpus 1] [--steps 2] [--warmup 1] [--serial]
 """
 import argparse
 import json
@@ -32,7 +36,23 @@ sys.path.insert(0, ROOT)
 METRIC = "accepted spin-updates/s + acceptance rate, BF16/FP32 batched vs FP64 plain"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
+# published dense peaks of MI355X per arithmetic type (matrix cores; FP32 and FP64 equal the
+# vector rates)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 HBM_PEAK_GBS = 8000.0
+DEFAULT_WORKLOAD = "rbim256"
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+PARITY_BOUND = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 5e-3}
+
+
+def build_arithmetic(precision, chi):
+    """Arithmetic type of env_build_kernel: FP64 for FP64 environments and for the Gram form
+    (chi <= 32) of FP32 / BF16 environments; FP32 for the QR form at chi = 48."""
+    return "f64" if precision == "fp64" or chi <= 32 else "f32"
+
+
+def sampler_arithmetic(precision):
+    return "f64" if precision == "fp64" else "f32"
 
 
 def proposals_per_wg(precision, n, K, Lmax):
@@ -42,32 +62,19 @@ def proposals_per_wg(precision, n, K, Lmax):
     return 128 if wide else 64
 
 
-# HBM bytes per launch of the dominant kernel from the FETCH_SIZE / WRITE_SIZE counters, each
-# scaled by the same counter on a plain 1 GiB copy (profiles/rbim64_fp32_hbm_traffic.md).  Valid
-# only for the kernel sources they were taken on: reported as null once those change.
-COUNTED_TRAFFIC = {
-    ("rbim64", "fp32", "env_build"): {
-        "fetch_kib": 5936819.4, "fetch_factor": 1048576.0 / 524308.125,
-        "write_kib": 10232238.3, "write_factor": 1.0,
-        "sources_sha256": {
-            "envbuild.hip": "6fc5dfae0fc8a49b502a914813092c0315ef4f41b71a8f94fa3504fd604a2c99",
-            "common.hpp": "2bc982fcaf62715dab9d8874db2780a5211c7c295637a1e3d7cedcf3f832a587",
-        },
-    },
-    ("rbim64", "fp32", "propose"): {
-        "fetch_kib": 20744570.6, "fetch_factor": 1048576.0 / 524308.125,
-        "write_kib": 36749974.3, "write_factor": 1.0,
-        "sources_sha256": {
-            "sampler.hip": "fc28505af48c47c184cb1a9bf4848e969c43fb5c6c03192785ad9cf606fb087d",
-            "common.hpp": "2bc982fcaf62715dab9d8874db2780a5211c7c295637a1e3d7cedcf3f832a587",
-        },
-    },
-}
+# Counters per dispatch of the dominant kernels (rocprofv3 --pmc; the summaries and commands are
+# in profiles/): FETCH_SIZE / WRITE_SIZE in KiB, each scaled by the same counter on a plain copy
+# of known size, and the matrix-core counters (SQ_INSTS_VALU_MFMA_MOPS_* count 512 flops each;
+# SQ_VALU_MFMA_BUSY_CYCLES against GRBM_GUI_ACTIVE x SIMDs).  Valid only for the kernel sources
+# they were taken on: reported as null once those change (SHA-256 of the sources).
+COUNTERS = {}
+
+SIMDS = 256 * 4
 
 
-def counted_traffic(workload, precision, kernel):
+def counted(workload, precision, kernel):
     import hashlib
-    rec = COUNTED_TRAFFIC.get((workload, precision, kernel))
+    rec = COUNTERS.get((workload, precision, kernel))
     if rec is None:
         return None
     csrc = os.path.join(ROOT, "paper_2409_06538_amd", "csrc")
@@ -75,13 +82,44 @@ def counted_traffic(workload, precision, kernel):
         with open(os.path.join(csrc, name), "rb") as f:
             if hashlib.sha256(f.read()).hexdigest() != digest:
                 return None
+    return rec
+
+
+def counted_traffic(rec):
+    if rec is None or "fetch_kib" not in rec:
+        return None
     return 1024.0 * (rec["fetch_kib"] * rec["fetch_factor"] + rec["write_kib"] * rec["write_factor"])
+
+
+def mfma_counters(rec, launch_ms, peak_tflops):
+    """Executed matrix-core flops of one launch and their rate against the peak of the kernel's
+    arithmetic type, and the matrix-core busy fraction."""
+    if rec is None or "mfma_mops" not in rec:
+        return None
+    mops = rec["mfma_mops"]
+    flops = {k: 512.0 * v for k, v in mops.items()}
+    total = sum(flops.values())
+    ach = total / (launch_ms * 1e-3) / 1e12
+    out = {"executed_flops_per_launch": flops, "executed_tflops": ach,
+           "executed_frac_of_peak": ach / peak_tflops}
+    if rec.get("gui_active_cycles"):
+        out["mfma_busy_frac"] = rec["mfma_busy_cycles"] / (rec["gui_active_cycles"] * SIMDS)
+    return out
 
 
 def build_flops_per_site(chi):
     """Algorithmic work of one site of the canonical compression (QR of a 4chi x 2chi matrix
     with Q, SVD of a 2chi x 2chi matrix, the two contractions), ~270 chi^3."""
     return 270.0 * chi ** 3
+
+
+def build_bytes_per_site(chi, env_bytes, carry_bytes):
+    """Algorithmic HBM bytes of one site: the site of E_r read twice (4 chi^2 elements), the site
+    of E_{r-1} written (2 chi^2), the carried factor (2chi x 2chi) written and read back."""
+    return 6.0 * chi * chi * env_bytes + 2.0 * (2 * chi) ** 2 * carry_bytes
+
+
+ENV_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
 
 
 def workload_sizes(w):
@@ -93,36 +131,122 @@ def workload_sizes(w):
 
 
 def add_rooflines(res, args, Ls):
-    """Dominant-kernel rooflines from the HIP-event launch times in `res`."""
+    """Dominant-kernel rooflines from the HIP-event launch times in `res`.
+
+    Build: 270 chi^3 flops per site (the canonical compression), against the dense peak of the
+    build's own arithmetic type.  Proposals: per realization the environments are streamed once
+    per pass, 2 passes x 2 chi^2 L^2 elements, and every proposal costs 8 chi^2 L^2 flops; the
+    kernel is quoted against the matrix-core peak of its arithmetic when that intensity is past
+    the ridge point, else against HBM."""
     chi, K, build_ms, prop_ms = res["chi"], res["K"], res["build_ms"], res["propose_ms"]
+    prec = args.precision
+    bar = build_arithmetic(prec, chi)
     flops = sum(build_flops_per_site(chi) * (L - 1) * L for L in Ls)
-    peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+    carry = 8 if bar == "f64" else 4
+    bbytes = sum(build_bytes_per_site(chi, ENV_BYTES[prec], carry) * (L - 1) * L for L in Ls)
+    peak = PEAK_TFLOPS[bar]
     achieved = flops / (build_ms * 1e-3) / 1e12
-    res["roofline"] = {"kernel": "env_build_kernel", "bound": "alu", "achieved": achieved,
-                       "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                       "traffic": counted_traffic(args.workload, args.precision, "env_build"),
-                       "launch_ms": build_ms,
-                       "algorithmic_flops_per_launch": flops}
-    # proposals: HBM-bound; algorithmic bytes = the per-row V store written and read back (2 x
-    # 16 rows per proposal at a narrow site, 2 x chi elsewhere), plus each workgroup of
-    # proposals_per_wg() proposals streaming its realization's environments once per sweep
-    elem = 8 if args.precision == "fp64" else 4
-    esize = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
-    g = proposals_per_wg(args.precision, len(Ls), K, max(Ls))
-    kpad = (K + g - 1) // g * g
-    nf = res.get("narrow_fraction", 0.0)
-    vrows = min(16, chi) * nf + chi * (1.0 - nf)
-    vbytes = sum(2.0 * L * L * 2 * vrows * kpad * elem for L in Ls)
-    ebytes = sum(2.0 * L * L * 2 * chi * chi * esize * (kpad // g) for L in Ls)
-    pbytes = vbytes + ebytes
-    pach = pbytes / (prop_ms * 1e-3) / 1e9
-    res["roofline_propose"] = {"kernel": "propose_mfma_kernel" if chi % 16 == 0 else "propose_kernel",
-                               "bound": "hbm", "achieved": pach, "peak": HBM_PEAK_GBS,
-                               "unit": "GB/s", "frac": pach / HBM_PEAK_GBS,
-                               "traffic": counted_traffic(args.workload, args.precision, "propose"),
-                               "launch_ms": prop_ms, "algorithmic_bytes_per_launch": pbytes,
-                               "narrow_site_fraction": nf}
+    rec = counted(args.workload, prec, "env_build")
+    traffic = counted_traffic(rec)
+    res["roofline"] = {"kernel": "env_build_kernel", "bound": "mfma", "arithmetic": bar,
+                       "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                       "frac": achieved / peak, "traffic": traffic,
+                       "traffic_over_algorithmic": None if traffic is None else traffic / bbytes,
+                       "launch_ms": build_ms, "algorithmic_flops_per_launch": flops,
+                       "algorithmic_bytes_per_launch": bbytes,
+                       "mfma_counters": mfma_counters(rec, build_ms, peak)}
+    sar = sampler_arithmetic(prec)
+    pbytes = sum(2.0 * 2 * chi * chi * L * L * ENV_BYTES[prec] for L in Ls)
+    pflops = sum(8.0 * chi * chi * L * L * K for L in Ls)
+    ppeak = PEAK_TFLOPS[sar]
+    ridge = ppeak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    t = prop_ms * 1e-3
+    gbs = pbytes / t / 1e9
+    prec_ = counted(args.workload, prec, "propose")
+    ptraffic = counted_traffic(prec_)
+    kern = "propose_mfma_kernel" if chi % 16 == 0 else "propose_kernel"
+    if pflops / pbytes > ridge:
+        ach = pflops / t / 1e12
+        rp = {"bound": "mfma", "achieved": ach, "peak": ppeak, "unit": "TFLOP/s",
+              "frac": ach / ppeak}
+    else:
+        rp = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": gbs / HBM_PEAK_GBS}
+    res["roofline_propose"] = dict(
+        kernel=kern, arithmetic=sar, **rp, traffic=ptraffic,
+        traffic_over_algorithmic=None if ptraffic is None else ptraffic / pbytes,
+        launch_ms=prop_ms, algorithmic_bytes_per_launch=pbytes,
+        algorithmic_flops_per_launch=pflops, intensity_flop_per_byte=pflops / pbytes,
+        ridge_flop_per_byte=ridge, hbm_algorithmic_GBs=gbs,
+        narrow_site_fraction=res.get("narrow_fraction"),
+        mfma_counters=mfma_counters(prec_, prop_ms, ppeak))
     return res
+
+
+def load_goldens():
+    """Stored FP64 oracle values (tests/golden/oracle_*.json, written by
+    tests/golden/make_oracle_goldens.py, which calls only the oracle)."""
+    import glob
+    out = []
+    for f in sorted(glob.glob(os.path.join(GOLDEN_DIR, "oracle_*.json"))):
+        with open(f) as fh:
+            g = json.load(fh)
+        g["name"] = os.path.basename(f)[len("oracle_"):-len(".json")]
+        out.append(g)
+    return out
+
+
+def error_vs_oracle(envs, args, w, Ls, seeds):
+    """Error of the timed run's results against the stored oracle values of the realizations
+    they cover: every environment log-norm lambda_r, the GPU's teacher-forced log q of the
+    oracle's own proposals (relative and absolute), and their exact energies (bit for bit).
+    `envs` lists (batch, p) of the environments still held after the timed steps."""
+    import numpy as np
+    import torch
+    bound = PARITY_BOUND[args.precision]
+    cases = []
+    for g in load_goldens():
+        if g["chi"] != w["chi"] or g["coupling_seed"] not in seeds:
+            continue
+        i = seeds.index(g["coupling_seed"])
+        if Ls[i] != g["L"]:
+            continue
+        hit = [b for b, p in envs if abs(p - g["p"]) < 1e-12]
+        if not hit:
+            continue
+        b = hit[0]
+        torch.cuda.synchronize()
+        lam = b.lognorm[i].cpu().numpy()
+        ref = np.array([np.nan if x is None else x for x in g["lognorm"]])
+        ok = ~np.isnan(ref)
+        rl = np.abs(lam[ok] - ref[ok]) / np.abs(ref[ok])
+        case = {"golden": g["name"], "realization": i, "rows_compared": int(ok.sum()),
+                "lognorm_max_rel": float(rl.max()),
+                "lognorm_max_abs": float(np.abs(lam[ok] - ref[ok]).max())}
+        if "proposals" in g:
+            pr = g["proposals"]
+            K = len(pr["logq"])
+            words = np.zeros((b.n, K, b.Lmax, b.Wmax), dtype=np.uint64)
+            sp = np.array([[[int(x, 16) for x in row.split()] for row in conf]
+                           for conf in pr["spins_hex"]], dtype=np.uint64)
+            words[i, :, :g["L"], :sp.shape[2]] = sp
+            d = torch.from_numpy(words.view(np.int64)).to(b.device)
+            lq = b.logq(d)[i].cpu().numpy()
+            E = b.energy(d)[i].cpu().numpy()
+            ref_q = np.array(pr["logq"])
+            case.update({"proposals": K,
+                         "logq_max_rel": float((np.abs(lq - ref_q) / np.abs(ref_q)).max()),
+                         "logq_max_abs": float(np.abs(lq - ref_q).max()),
+                         "energy_bit_exact": bool(np.array_equal(E, pr["E"]))})
+        cases.append(case)
+    if not cases:
+        return None
+    lmax = max(c["lognorm_max_rel"] for c in cases)
+    qs = [c["logq_max_rel"] for c in cases if "logq_max_rel" in c]
+    return {"source": "tests/golden/oracle_*.json (FP64 oracle)", "bound_rel": bound,
+            "lognorm_max_rel": lmax, "logq_max_rel": max(qs) if qs else None,
+            "energy_bit_exact": all(c.get("energy_bit_exact", True) for c in cases),
+            "within_bound": lmax < bound and (not qs or max(qs) < bound), "cases": cases}
 
 
 def narrow_fraction(batch):
@@ -168,14 +292,18 @@ def run_gpu(args, w=None):
            torch.empty((n, K), dtype=torch.float64, device=dev),
            torch.empty((n, K), dtype=torch.int32, device=dev))
     accum = torch.zeros((n, binding.OBS_COUNT), dtype=torch.float64, device=dev)
-    chains = b.new_chains(1)
+    chains = [b.new_chains(1) for _ in ps]       # one chain per realization and disorder strength
     L2 = torch.tensor([L * L for L in Ls], dtype=torch.float64, device=dev)
     ev = []
+    stage = [0] * len(ps)
 
     def step(events):
-        """One pass over every p; returns per-p [accepted, accepted x L^2] (device tensors)."""
+        """One pass over every p; returns per-p [accepted, accepted x L^2, attempted] (device
+        tensors).  Eager steps draw new proposals (first proposal id = stage x K) and continue
+        each p's chains; a captured step restarts its chains and replays the same proposals."""
         sums = []
         for j, p in enumerate(ps):
+            ch = chains[j]
             if len(ps) > 1:
                 b.set_betas([binding.nishimori_beta(p)] * n)
             b.make_couplings(seeds, p)
@@ -184,14 +312,18 @@ def run_gpu(args, w=None):
             b.build_env(want_lnZ=False)
             if events is not None:
                 events[3 * j + 1].record()
-            b.propose(K, args.seed, first_proposal=0, out=out)
+            first = 0 if args.graph else stage[j] * K
+            b.propose(K, args.seed, first_proposal=first, out=out)
             if events is not None:
                 events[3 * j + 2].record()
-            for t in (chains["spins"], chains["E"], chains["logq"], chains["init"]):
-                t.zero_()
-            acc, _ = b.accept(out, chains, seed=args.seed, accum=accum)
+            if args.graph:
+                for t in (ch["spins"], ch["E"], ch["logq"], ch["init"]):
+                    t.zero_()
+            fresh = (ch["init"] == 0).sum(dtype=torch.float64)
+            acc, _ = b.accept(out, ch, seed=args.seed, first_step=first, accum=accum)
             per_real = acc.sum(dim=1, dtype=torch.float64)
-            sums.append(torch.stack([per_real.sum(), (per_real * L2).sum()]))
+            sums.append(torch.stack([per_real.sum(), (per_real * L2).sum(), n * K - fresh]))
+            stage[j] += 1
         return torch.stack(sums)
 
     def new_events():
@@ -223,10 +355,10 @@ def run_gpu(args, w=None):
             ev.append(e)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    per_p = torch.stack(accs).sum(dim=0).tolist()            # [len(ps)][2]
-    accepted = int(sum(a for a, _ in per_p))
-    updates = sum(u for _, u in per_p)
-    attempted = args.steps * len(ps) * n * (K - 1)
+    per_p = torch.stack(accs).sum(dim=0).tolist()            # [len(ps)][3]
+    accepted = int(sum(a for a, _, _ in per_p))
+    updates = sum(u for _, u, _ in per_p)
+    attempted = int(sum(t for _, _, t in per_p))
     nb = len(ev) * len(ps)
     build_ms = sum(e[3 * j].elapsed_time(e[3 * j + 1]) for e in ev for j in range(len(ps))) / nb
     prop_ms = sum(e[3 * j + 1].elapsed_time(e[3 * j + 2]) for e in ev for j in range(len(ps))) / nb
@@ -240,10 +372,10 @@ def run_gpu(args, w=None):
         "build_ms": build_ms, "propose_ms": prop_ms,
         "graph": bool(args.graph),
         "narrow_fraction": narrow_fraction(b),
+        "error_vs_oracle": error_vs_oracle([(b, ps[-1])], args, w, Ls, seeds),
     }
     if len(ps) > 1:
-        res["acceptance_per_p"] = {str(p): per_p[j][0] / (args.steps * n * (K - 1))
-                                   for j, p in enumerate(ps)}
+        res["acceptance_per_p"] = {str(p): per_p[j][0] / per_p[j][2] for j, p in enumerate(ps)}
         res["batches_per_step"] = len(ps)
     return add_rooflines(res, args, Ls)
 
@@ -323,9 +455,13 @@ def run_gpu_pipelined(args):
         out = (torch.empty(b.spins_shape(K), dtype=torch.int64, device=dev),
                torch.empty((n, K), dtype=torch.float64, device=dev),
                torch.empty((n, K), dtype=torch.int32, device=dev))
-        sets.append({"b": b, "out": out, "chains": b.new_chains(1),
+        sets.append({"b": b, "out": out,
                      "accum": torch.zeros((n, binding.OBS_COUNT), dtype=torch.float64, device=dev),
-                     "done": None})
+                     "done": None, "p": None})
+    # one chain per realization and disorder strength, continued from stage to stage (all
+    # accepts run in stage order on the proposal stream)
+    chains = [sets[0]["b"].new_chains(1) for _ in ps]
+    stage = [0] * len(ps)
     L2 = torch.tensor([L * L for L in Ls], dtype=torch.float64, device=dev)
     torch.cuda.synchronize()
 
@@ -333,8 +469,10 @@ def run_gpu_pipelined(args):
         """`steps` passes over every p: one pipeline stage per (step, p)."""
         sums, ev = [], []
         for u in range(steps * len(ps)):
-            p = ps[u % len(ps)]
+            jp = u % len(ps)
+            p = ps[jp]
             st = sets[u % (depth + 1)]
+            st["p"] = p
             b = st["b"]
             s_build = s_builds[u % depth]
             e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
@@ -349,14 +487,16 @@ def run_gpu_pipelined(args):
             with torch.cuda.stream(s_prop):
                 s_prop.wait_event(e[1])
                 e[2].record(s_prop)
-                b.propose(K, args.seed, first_proposal=0, out=st["out"])
+                first = stage[jp] * K
+                stage[jp] += 1
+                b.propose(K, args.seed, first_proposal=first, out=st["out"])
                 e[3].record(s_prop)
-                ch = st["chains"]
-                for x in (ch["spins"], ch["E"], ch["logq"], ch["init"]):
-                    x.zero_()
-                acc, _ = b.accept(st["out"], ch, seed=args.seed, accum=st["accum"])
+                ch = chains[jp]
+                fresh = (ch["init"] == 0).sum(dtype=torch.float64)
+                acc, _ = b.accept(st["out"], ch, seed=args.seed, first_step=first,
+                                  accum=st["accum"])
                 per_real = acc.sum(dim=1, dtype=torch.float64)
-                sums.append(torch.stack([per_real.sum(), (per_real * L2).sum()]))
+                sums.append(torch.stack([per_real.sum(), (per_real * L2).sum(), n * K - fresh]))
                 done = torch.cuda.Event()
                 done.record(s_prop)
                 st["done"] = done
@@ -369,15 +509,17 @@ def run_gpu_pipelined(args):
     sums, ev = run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    per_stage = torch.stack(sums).tolist()                   # [steps * len(ps)][2]
-    accepted = int(sum(a for a, _ in per_stage))
-    updates = sum(x for _, x in per_stage)
-    attempted = args.steps * len(ps) * n * (K - 1)
+    per_stage = torch.stack(sums).tolist()                   # [steps * len(ps)][3]
+    accepted = int(sum(a for a, _, _ in per_stage))
+    updates = sum(x for _, x, _ in per_stage)
+    attempted = int(sum(t for _, _, t in per_stage))
     build_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / len(ev)
     prop_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / len(ev)
     wall = t1 - t0
     nfrac = narrow_fraction(sets[0]["b"])
-    del sets, sums, ev
+    envs = [(st["b"], st["p"]) for st in sets if st["p"] is not None]
+    err = error_vs_oracle(envs, args, w, Ls, seeds)
+    del envs, sets, sums, ev
     torch.cuda.synchronize()
     if cu_mask is not None:
         s_prop.destroy()
@@ -387,11 +529,12 @@ def run_gpu_pipelined(args):
            "acceptance": accepted / attempted, "build_ms": build_ms, "propose_ms": prop_ms,
            "graph": False, "pipelined": True, "builds_in_flight": depth,
            "narrow_fraction": nfrac,
-           "propose_cu_mask": cu_mask}
+           "propose_cu_mask": cu_mask, "error_vs_oracle": err}
     if len(ps) > 1:
         res["acceptance_per_p"] = {
             str(p): sum(per_stage[u][0] for u in range(j, len(per_stage), len(ps)))
-            / (args.steps * n * (K - 1)) for j, p in enumerate(ps)}
+            / sum(per_stage[u][2] for u in range(j, len(per_stage), len(ps)))
+            for j, p in enumerate(ps)}
         res["batches_per_step"] = len(ps)
     return add_rooflines(res, args, Ls)
 
@@ -427,75 +570,113 @@ def run_fp64_plain(args, L, chi, p, K_full, n_prop=20):
                       f"extrapolated to {K_full} proposals"}
 
 
-def run_cpu_baseline(L, chi, p, K_full, seed, n_real=6, n_prop=150):
-    """The oracle on one host core: n_real realizations (coupling seeds 0..n_real-1), each a full
-    build + n_prop proposals (vectorised) + the chain, extrapolated to K_full proposals per
-    realization."""
-    from threadpoolctl import threadpool_limits
-    from oracle import accept, energy, envbuild, instance, sampler
-    beta = instance.nishimori_beta(p)
-    t_build = t_prop = 0.0
-    acc = 0
-    with threadpool_limits(limits=1):
-        for i in range(n_real):
-            Jh, Jv = instance.couplings(i, L, p)
-            t0 = time.perf_counter()
-            env = envbuild.build_env(Jh, Jv, beta, chi)
-            t_build += time.perf_counter() - t0
-            t0 = time.perf_counter()
-            smp = sampler.run(env, Jh, Jv, beta, K=n_prop, seed=seed, realization=i)
-            E = energy.energy(smp["spins"], Jh, Jv)
-            ch = accept.chain(E, smp["logq"], beta, seed=seed, realization=i)
-            t_prop += time.perf_counter() - t0
-            acc += int(ch["accepted"].sum())
-    pa = acc / (n_real * (n_prop - 1))
-    t_b = t_build / n_real
-    t_p = t_prop / (n_real * n_prop)
-    t_real = t_b + K_full * t_p
-    return {"value": (K_full - 1) * pa * L * L / t_real, "unit": "spin-updates/s", "cores": 1,
-            "kind": "oracle", "acceptance": pa,
-            "sample": f"{n_real} realizations (coupling seeds 0..{n_real - 1}), each a full FP64 "
-                      f"environment build ({t_b:.2f} s) + {n_prop} proposals ({t_p * 1e3:.1f} ms "
-                      f"each) + accepts; {t_build + t_prop:.1f} s of CPU work in all, "
-                      f"extrapolated to {K_full} proposals per realization; single thread"}
-
-
-def _cpu_worker(job):
-    """One realization on one core: full FP64 build, n_prop proposals, the chain."""
-    L, chi, p, seed, i, n_prop = job
+def _oracle_realization(job):
+    """The oracle on one realization, single-threaded.  Full mode: the whole FP64 build, n_prop
+    proposals (vectorised) and the chain.  Sliced mode (lattices whose oracle build takes
+    minutes): rows_a and rows_b rows of the build from the bottom, the cost per row taken from
+    the difference (rows with saturated bonds), and n_prop proposals timed on environments whose
+    unbuilt rows repeat the last built row (the same tensor shapes; timing only)."""
+    L, chi, p, seed, i, n_prop, sliced = job
     from threadpoolctl import threadpool_limits
     from oracle import accept, energy, envbuild, instance, sampler
     beta = instance.nishimori_beta(p)
     with threadpool_limits(limits=1):
         Jh, Jv = instance.couplings(i, L, p)
+        if not sliced:
+            t0 = time.perf_counter()
+            env = envbuild.build_env(Jh, Jv, beta, chi)
+            t_build = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            smp = sampler.run(env, Jh, Jv, beta, K=n_prop, seed=seed, realization=i)
+            E = energy.energy(smp["spins"], Jh, Jv)
+            ch = accept.chain(E, smp["logq"], beta, seed=seed, realization=i)
+            t_prop = time.perf_counter() - t0
+            return t_build, t_prop, int(ch["accepted"].sum()), t_build + t_prop
+        rows_a, rows_b = sliced
+        t0 = t_start = time.perf_counter()
+        envbuild.build_env(Jh, Jv, beta, chi, rows=rows_a)
+        t1 = time.perf_counter()
+        env = envbuild.build_env(Jh, Jv, beta, chi, rows=rows_b)
+        t2 = time.perf_counter()
+        per_row = ((t2 - t1) - (t1 - t0)) / (rows_b - rows_a)
+        t_build = (t2 - t1) + per_row * (L - 1 - rows_b)
+        last = L - 1 - rows_b
+        sites = [env["sites"][r] if env["sites"][r] is not None else env["sites"][last]
+                 for r in range(L)]
         t0 = time.perf_counter()
-        env = envbuild.build_env(Jh, Jv, beta, chi)
-        t_build = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        smp = sampler.run(env, Jh, Jv, beta, K=n_prop, seed=seed, realization=i)
+        smp = sampler.run({"sites": sites}, Jh, Jv, beta, K=n_prop, seed=seed, realization=i)
         E = energy.energy(smp["spins"], Jh, Jv)
-        ch = accept.chain(E, smp["logq"], beta, seed=seed, realization=i)
         t_prop = time.perf_counter() - t0
-    return t_build, t_prop, int(ch["accepted"].sum())
+        return t_build, t_prop, None, time.perf_counter() - t_start
 
 
-def run_cpu_all_cores(L, chi, p, K_full, seed, n_prop=150, max_workers=16):
+def cpu_sample_plan(L):
+    """Full oracle realizations up to L = 64; beyond, the sliced sample (16 rows, 2 proposals)."""
+    return (None, 150) if L <= 64 else ((8, 16), 2)
+
+
+def _cpu_result(out, L, K_full, n_prop, sliced, cores):
+    """Accepted spin-updates/s of realizations run side by side, extrapolated to K_full
+    proposals each (the batch takes the longest extrapolated time)."""
+    t_real = max(tb + K_full * tp / n_prop for tb, tp, _, _ in out)
+    if sliced:
+        pas = [1.0] * len(out)       # not measurable from a sample: 1 is an upper bound
+    else:
+        pas = [a / (n_prop - 1) for _, _, a, _ in out]
+    updates = sum((K_full - 1) * pa * L * L for pa in pas)
+    return updates / t_real, sum(pas) / len(pas), t_real
+
+
+def run_cpu_baseline(L, chi, p, K_full, seed, n_real=None):
+    """The oracle on one host core: a bounded sample of the workload's realizations (coupling
+    seeds 0, 1, ...), extrapolated to K_full proposals per realization."""
+    sliced, n_prop = cpu_sample_plan(L)
+    n_real = n_real or (6 if not sliced else 1)
+    out = [_oracle_realization((L, chi, p, seed, i, n_prop, sliced)) for i in range(n_real)]
+    v, pa, t_real = _cpu_result(out, L, K_full, n_prop, sliced, 1)
+    v = v / n_real                   # one core runs its realizations one after the other
+    work = sum(o[3] for o in out)
+    t_b = sum(o[0] for o in out) / n_real
+    t_p = sum(o[1] for o in out) / (n_real * n_prop)
+    if sliced:
+        sample = (f"{n_real} realization (coupling seed 0): the first {sliced[0]} and "
+                  f"{sliced[1]} environment rows built (build of all {L - 1} rows extrapolated "
+                  f"from the difference: {t_b:.1f} s) + {n_prop} proposals ({t_p:.1f} s each) "
+                  f"on environments whose unbuilt rows repeat the last built row (timing only); "
+                  f"{work:.1f} s of CPU work in all, extrapolated to {K_full} proposals; "
+                  f"acceptance taken as 1 (an upper bound); single thread")
+    else:
+        sample = (f"{n_real} realizations (coupling seeds 0..{n_real - 1}), each a full FP64 "
+                  f"environment build ({t_b:.2f} s) + {n_prop} proposals ({t_p * 1e3:.1f} ms "
+                  f"each) + accepts; {work:.1f} s of CPU work in all, extrapolated to {K_full} "
+                  f"proposals per realization; single thread")
+    return {"value": v, "unit": "spin-updates/s", "cores": 1, "kind": "oracle",
+            "acceptance": pa, "sample": sample}
+
+
+def run_cpu_all_cores(L, chi, p, K_full, seed, max_workers=16):
     """The oracle on every host core the process may use (at most max_workers): one process per
-    core, each a realization (coupling seeds 0..w-1) with a full build + n_prop proposals + the
-    chain, extrapolated to K_full proposals; the realizations run side by side, so the batch takes
-    the longest extrapolated time.  Runs before anything touches the GPU (forked workers)."""
+    core, each a realization (coupling seeds 0..w-1) with the bounded sample of
+    _oracle_realization, extrapolated to K_full proposals; the realizations run side by side.
+    Runs before anything touches the GPU (forked workers)."""
     import multiprocessing as mp
-    w = max(1, min(max_workers, len(os.sched_getaffinity(0))))
+    sliced, n_prop = cpu_sample_plan(L)
+    avail = len(os.sched_getaffinity(0))
+    w = max(1, min(max_workers, avail))
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(w) as pool:
-        out = pool.map(_cpu_worker, [(L, chi, p, seed, i, n_prop) for i in range(w)])
+        out = pool.map(_oracle_realization, [(L, chi, p, seed, i, n_prop, sliced)
+                                             for i in range(w)])
     wall = time.perf_counter() - t0
-    t_real = max(tb + K_full * tp / n_prop for tb, tp, _ in out)
-    updates = sum((K_full - 1) * (a / (n_prop - 1)) * L * L for _, _, a in out)
-    return {"value": updates / t_real, "unit": "spin-updates/s", "cores": w, "kind": "oracle",
-            "sample": f"{w} realizations (coupling seeds 0..{w - 1}), one process each, each a "
-                      f"full FP64 build + {n_prop} proposals + accepts ({wall:.1f} s wall), "
-                      f"extrapolated to {K_full} proposals per realization"}
+    v, pa, _ = _cpu_result(out, L, K_full, n_prop, sliced, w)
+    what = (f"the first {sliced[1]} environment rows + {n_prop} proposals (timing only)"
+            if sliced else f"a full FP64 build + {n_prop} proposals + accepts")
+    return {"value": v, "unit": "spin-updates/s", "cores": w, "cores_available": avail,
+            "kind": "oracle", "acceptance": pa,
+            "sample": f"{w} realizations (coupling seeds 0..{w - 1}), one process each on the "
+                      f"{w} of {avail} cores this process may use (capped at {max_workers}), "
+                      f"each {what} ({wall:.1f} s wall), extrapolated to {K_full} proposals per "
+                      f"realization" + ("; acceptance taken as 1 (an upper bound)" if sliced else "")}
 
 
 def calib_copy(mib):
@@ -510,44 +691,69 @@ def calib_copy(mib):
     del src, dst
 
 
-DEFAULT_STEPS = {"rbim16": 50, "rbim64": 50, "mixed": 4, "rbim256": 2, "rbim256_chi32": 2}
+DEFAULT_STEPS = {"rbim16": 50, "rbim64": 50, "mixed": 4, "rbim256": 2, "rbim256_chi32": 2,
+                 "rbim1024": 1}
 
 SWEEP_LS = (16, 32, 64, 128, 256)
 SWEEP_CHIS = (8, 16, 32, 48)
 
 
-def run_sweep(args):
-    """Acceptance and cost against L and chi (the quantities of the paper's acceptance-ratio and
-    cost figures, Sec. III B): for each (L, chi), 16 realizations at p = 0.109 on the Nishimori
-    line, 256 proposals each, one serial step timed after one warm-up.  One JSON line per point:
-    p_a, build and proposal times, the time per valid (accepted) sample per realization, and the
-    accepted spin-updates/s of the batch."""
+SWEEP_NISHIMORI_PS = (0.05, 0.08, 0.10, 0.109, 0.12, 0.14)
+SWEEP_NISHIMORI_LS = (64, 128, 256)
+SWEEP_LARGE_LS = (512, 1024)
+
+
+def sweep_point(args, L, chi, p, n_real, K, kind):
     import copy
-    for chi in SWEEP_CHIS:
-        for L in SWEEP_LS:
-            w = dict(L=L, p=0.109, chi=chi, seeds=tuple(range(16)), proposals=256)
-            a = copy.copy(args)
-            a.steps, a.warmup, a.graph = 1, 1, False
-            res = run_gpu(a, w)
-            wall_per_real = res["wall_s"]          # the realizations run side by side
-            print(json.dumps({
-                "sweep": "acceptance_cost", "L": L, "chi": chi, "precision": args.precision,
-                "realizations": res["n"], "proposals": res["K"], "acceptance": res["acceptance"],
-                "build_ms": res["build_ms"], "propose_ms": res["propose_ms"],
-                "ms_per_valid_sample": 1e3 * wall_per_real / max(1.0, res["acceptance"] * (res["K"] - 1)),
-                "accepted_spin_updates_per_s": res["value"]}), flush=True)
+    w = dict(L=L, p=p, chi=chi, seeds=tuple(range(n_real)), proposals=K)
+    a = copy.copy(args)
+    a.steps, a.warmup, a.graph = 1, 1, False
+    res = run_gpu(a, w)
+    wall_per_real = res["wall_s"]          # the realizations run side by side
+    print(json.dumps({
+        "sweep": kind, "L": L, "chi": chi, "p": p, "T": 2.0 / math.log((1 - p) / p),
+        "precision": args.precision, "realizations": res["n"], "proposals": res["K"],
+        "acceptance": res["acceptance"], "build_ms": res["build_ms"],
+        "propose_ms": res["propose_ms"],
+        "ms_per_valid_sample": 1e3 * wall_per_real / max(1.0, res["acceptance"] * (res["K"] - 1)),
+        "accepted_spin_updates_per_s": res["value"]}), flush=True)
+
+
+def run_sweep(args):
+    """Acceptance and cost (the quantities of the paper's acceptance-ratio and cost figures,
+    Sec. III B), one serial step per point after one warm-up, one JSON line per point: p_a,
+    build and proposal times, the time per valid (accepted) sample per realization, and the
+    accepted spin-updates/s of the batch.
+      acceptance_cost  L in 16..256 and chi in 8..48; 16 realizations at p = 0.109, 256 proposals
+      nishimori        p_a against the temperature along the Nishimori line (p and beta_N(p)),
+                       L in 64..256, chi = 16 and 32; 16 realizations, 256 proposals
+      large_L          L = 512 and 1024 at chi = 16 and 32; 4 realizations, 64 proposals"""
+    if args.sweep == "acceptance_cost":
+        for chi in SWEEP_CHIS:
+            for L in SWEEP_LS:
+                sweep_point(args, L, chi, 0.109, 16, 256, args.sweep)
+    elif args.sweep == "nishimori":
+        for chi in (16, 32):
+            for L in SWEEP_NISHIMORI_LS:
+                for p in SWEEP_NISHIMORI_PS:
+                    sweep_point(args, L, chi, p, 16, 256, args.sweep)
+    elif args.sweep == "large_L":
+        for chi in (16, 32):
+            for L in SWEEP_LARGE_LS:
+                sweep_point(args, L, chi, 0.109, 4, 64, args.sweep)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=0,
-                    help="timed steps (default: 50 for rbim64 and rbim16, whose steps take "
-                         "milliseconds, so that the pipeline fill and drain inside the timed "
-                         "region are amortised; 4 for mixed; 2 for rbim256)")
+                    help="timed steps (default: 2 for rbim256, whose steps take seconds; 50 for "
+                         "rbim64 and rbim16, whose steps take milliseconds, so that the pipeline "
+                         "fill and drain inside the timed region are amortised; 4 for mixed)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rbim64")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"])
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16"],
+                    help="environment precision (default: the workload's)")
     ap.add_argument("--proposals", type=int, default=0)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -563,9 +769,10 @@ def main():
                          "proposal work (0: no CU mask)")
     ap.add_argument("--builds-in-flight", type=int, default=2, choices=[1, 2],
                     help="overlapped steps: environment builds of later steps running at once")
-    ap.add_argument("--sweep", action="store_true",
-                    help="acceptance and cost against L and chi (one JSON line per point) instead "
-                         "of the benchmark line")
+    ap.add_argument("--sweep", default=None, choices=["acceptance_cost", "nishimori", "large_L"],
+                    help="one JSON line per point instead of the benchmark line: acceptance and "
+                         "cost against L and chi; against the temperature along the Nishimori "
+                         "line; or at L = 512 and 1024")
     ap.add_argument("--graph", action="store_true",
                     help="capture the whole step in one HIP graph and time its replays (phase "
                          "times then come from the eager warm-up steps)")
@@ -573,24 +780,28 @@ def main():
                     help="after the run, copy one buffer of this many MiB once (a plain copy "
                          "kernel of known size, the reference for hardware byte counters)")
     args = ap.parse_args()
-    if not args.steps:
-        args.steps = DEFAULT_STEPS.get(args.workload, 20)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the realizations of a "
               "batch are independent, so N GPUs would each run their own share; this "
               "benchmark measures one GPU's share.", file=sys.stderr)
         sys.exit(2)
+    import synth
+    wl = synth.WORKLOADS[args.workload]
+    if args.precision is None:
+        args.precision = wl.get("precision", "fp32")
+    if not args.steps:
+        args.steps = DEFAULT_STEPS.get(args.workload, 20)
     if args.sweep:
         run_sweep(args)
         return
-    import synth
-    wl = synth.WORKLOADS[args.workload]
     multi_p = len(disorder_strengths(wl)) > 1
+    ps = disorder_strengths(wl)
+    p_cpu = ps[len(ps) // 2]
+    K_full = args.proposals or wl["proposals"]
     # the oracle on all host cores first, while no process has touched the GPU (forked workers)
     cpu_all = None
-    if not args.no_cpu and not multi_p and "L" in wl and not args.sweep:
-        cpu_all = run_cpu_all_cores(wl["L"], wl["chi"], wl["p"], args.proposals or wl["proposals"],
-                                    args.seed)
+    if not args.no_cpu and "L" in wl:
+        cpu_all = run_cpu_all_cores(wl["L"], wl["chi"], p_cpu, K_full, args.seed)
     serial = args.serial or args.graph
     res = run_gpu(args) if serial else run_gpu_pipelined(args)
     if not serial and not args.no_serial:
@@ -600,23 +811,30 @@ def main():
         a2.steps, a2.warmup = (1, 0) if multi_p else (3, 1)
         r2 = run_gpu(a2)
         res["serial"] = {"value": r2["value"], "ms_per_step": r2["ms_per_step"], "steps": a2.steps,
-                         "build_ms": r2["build_ms"], "propose_ms": r2["propose_ms"]}
+                         "build_ms": r2["build_ms"], "propose_ms": r2["propose_ms"],
+                         "acceptance": r2["acceptance"]}
     if args.calib_copy_mib:
         calib_copy(args.calib_copy_mib)
     uniform = len(res["Ls"]) == 1
     L0 = res["Ls"][0]
-    p0 = res["p"][len(res["p"]) // 2] if multi_p else res["p"]
-    # the FP64 plain form and the CPU oracle are measured on uniform-L workloads with one
-    # disorder strength (the FP64 plain form where FP64 environments exist at this chi)
+    # the FP64 plain form and the CPU oracle are measured on uniform-L workloads (the FP64 plain
+    # form at the largest chi that FP64 environments are built for, up to the workload's)
     from paper_2409_06538_amd import binding
-    fp64_ok = bool(binding.load().tnmc_chi_supported(res["chi"], binding.PRECISIONS["fp64"]))
-    plain = None if args.no_plain or not uniform or not fp64_ok else \
-        run_fp64_plain(args, L0, res["chi"], p0, res["K"])
-    cpu = None if args.no_cpu or not uniform or multi_p else \
-        run_cpu_baseline(L0, res["chi"], p0, res["K"], args.seed)
+    chi_plain = max(c for c in (2, 4, 8, 16, 32, 48, 64)
+                    if c <= res["chi"] and binding.load().tnmc_chi_supported(c, binding.FP64))
+    plain = None if args.no_plain or not uniform else \
+        run_fp64_plain(args, L0, chi_plain, p_cpu, res["K"])
+    if plain is not None and chi_plain != res["chi"]:
+        plain["chi"] = chi_plain
+        plain["note"] = (f"FP64 environments are built up to chi = {chi_plain}: the FP64 plain form "
+                         f"runs the same lattice at chi = {chi_plain}")
+    cpu = None if args.no_cpu or not uniform else \
+        run_cpu_baseline(L0, res["chi"], p_cpu, res["K"], args.seed)
     if cpu is not None:
         cpu["all_cores"] = cpu_all
+        cpu["cores_available"] = len(os.sched_getaffinity(0))
     size = f"{L0}x{L0}" if uniform else "L x L (L in " + ", ".join(map(str, res["Ls"])) + ")"
+    bar = build_arithmetic(args.precision, res["chi"])
     line = {
         "metric": METRIC,
         "value": res["value"],
@@ -628,18 +846,24 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": sampler_arithmetic(args.precision),
+        "arithmetic": {"storage": {"fp64": "f64", "fp32": "f32", "bf16": "bf16"}[args.precision],
+                       "build": bar, "sampler": sampler_arithmetic(args.precision),
+                       "lognorm_logq_delta": "f64", "energy": "int"},
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {res['n']} realizations of the {size} open "
                                + (f"+-J lattice for each p in {tuple(res['p'])} (the same coupling "
                                   f"seeds, one batch per p), Nishimori beta, chi={res['chi']}, "
                                   if multi_p else
                                   f"+-J lattice, p={res['p']}, Nishimori beta, chi={res['chi']}, ")
-                               + f"{res['K']} proposals each, {args.precision} batched"
-                               + (", one HIP graph per step" if res["graph"] else "")
+                               + f"{res['K']} proposals each per step, {args.precision} "
+                               "environments, batched"
+                               + (", one HIP graph per step (its replays repeat one batch of "
+                                  "proposals from restarted chains)" if res["graph"] else
+                                  "; every step draws new proposals and continues the chains")
                                + (f", consecutive steps overlapped (builds of the next "
-                                  f"{res.get('builds_in_flight')} step(s) during the proposals of "
-                                  f"step t)" if res.get("pipelined") else ""),
+                                  f"{res.get('builds_in_flight')} stage(s) during the proposals "
+                                  f"of the current one)" if res.get("pipelined") else ""),
                    "L": L0 if uniform else res["Ls"], "chi": res["chi"], "realizations": res["n"],
                    "proposals": res["K"], "p": res["p"], "precision": args.precision,
                    "graph": res["graph"], "pipelined": bool(res.get("pipelined")),
@@ -653,6 +877,7 @@ def main():
         "propose_ms": res["propose_ms"],
         "serial": res.get("serial"),
         "fp64_plain": plain,
+        "error_vs_oracle": res.get("error_vs_oracle"),
         "roofline": res["roofline"],
         "roofline_propose": res["roofline_propose"],
         "cpu_baseline": cpu,

@@ -16,16 +16,19 @@ dataset.  Workloads (open L x L lattices, beta on the Nishimori line):
 import numpy as np
 
 WORKLOADS = {
-    "rbim16": dict(L=16, p=0.109, chi=16, seeds=(0,), proposals=200, philox_seed=0),
-    "rbim64": dict(L=64, p=0.109, chi=32, seeds=tuple(range(64)), proposals=1000, philox_seed=0),
+    "rbim16": dict(L=16, p=0.109, chi=16, seeds=(0,), proposals=200, philox_seed=0,
+                   precision="fp64"),
+    "rbim64": dict(L=64, p=0.109, chi=32, seeds=tuple(range(64)), proposals=1000, philox_seed=0,
+                   precision="fp32"),
     "rbim256": dict(L=256, ps=(0.10, 0.109, 0.12), chi=48, seeds=tuple(range(128)),
-                    proposals=1000, philox_seed=0),
+                    proposals=1000, philox_seed=0, precision="bf16"),
     # the same lattices and disorder at chi = 32 (FP32 environments): the bond / precision trade-off
     "rbim256_chi32": dict(L=256, ps=(0.10, 0.109, 0.12), chi=32, seeds=tuple(range(128)),
-                          proposals=1000, philox_seed=0),
+                          proposals=1000, philox_seed=0, precision="fp32"),
     "mixed": dict(Ls=(32, 64, 128, 256), p=0.109, chi=32, seeds=tuple(range(256)),
-                  proposals=1000, philox_seed=0),
-    "rbim1024": dict(L=1024, p=0.109, chi=64, seeds=(0, 1), proposals=1000, philox_seed=0),
+                  proposals=1000, philox_seed=0, precision="fp32"),
+    "rbim1024": dict(L=1024, p=0.109, chi=64, seeds=(0, 1), proposals=1000, philox_seed=0,
+                     precision="fp32"),
 }
 
 

@@ -22,6 +22,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 
 # name: (L, chi, p, coupling seed = realization id, proposals K, rows (None = full build))
 CASES = {
+    "rbim16_s0": (16, 16, 0.109, 0, 4, None),
+    "rbim64_s0": (64, 32, 0.109, 0, 4, None),
     "rbim256_p0.10_s0": (256, 48, 0.10, 0, 3, None),
     "rbim256_p0.109_s77": (256, 48, 0.109, 77, 3, None),
     "rbim256_p0.12_s11": (256, 48, 0.12, 11, 3, None),

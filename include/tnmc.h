@@ -137,6 +137,20 @@ tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tn
                            void* d_workspace, size_t workspace_bytes, double* d_lnZ,
                            hipStream_t stream);
 
+/* tnmc_build_env for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same environments, log-norms and
+ * ln Z_TN, with no workspace argument.  The descriptor table and the build scratch of the batch
+ * live in a fixed device array inside the library, TNMC_STATIC_SCRATCH_BYTES per device, held
+ * until the process ends; the call allocates nothing.  A batch whose descriptor table plus build
+ * scratch (the tnmc_build_env part of tnmc_workspace_bytes) exceeds that size returns
+ * TNMC_ENOMEM before anything is enqueued.  Every call on a device shares that device's array:
+ * calls that overlap on one device (other streams, other threads) race and must be ordered by
+ * the caller.  The first call on each device should be made outside a graph capture (it looks
+ * up the array's device address and raises the kernel's LDS limit once). */
+#define TNMC_STATIC_SCRATCH_BYTES (64u << 20)
+tnmc_status tnmc_build_env_static(const tnmc_instance* inst, int32_t n, int32_t chi,
+                                  tnmc_precision prec, double* d_lnZ, hipStream_t stream);
+
 /* a4 + a5 -- K whole-lattice proposals per realization (Sec. II A-B, Eqs. (4)-(6)), sampled row
  * by row and, within a row, column by column from the cached environments: right partial sums
  * R_c(y) = sum_y' w_c(y,y') phi_{c+1}(y') A^{(c+1)}[y'] R_{c+1}(y') and a left running vector;

@@ -60,6 +60,7 @@ def load():
         "tnmc_workspace_bytes": (sz, [P, i32, i32, i32, ctypes.c_int]),
         "tnmc_make_couplings": (ctypes.c_int, [P, i32, vp, dbl, vp, sz, vp]),
         "tnmc_build_env": (ctypes.c_int, [P, i32, i32, ctypes.c_int, vp, sz, vp, vp]),
+        "tnmc_build_env_static": (ctypes.c_int, [P, i32, i32, ctypes.c_int, vp, vp]),
         "tnmc_propose": (ctypes.c_int, [P, i32, i32, ctypes.c_int, i32, u64, u64, vp, sz, vp, vp,
                                         vp, vp, vp]),
         "tnmc_logq": (ctypes.c_int, [P, i32, i32, ctypes.c_int, i32, vp, vp, sz, vp, vp]),
@@ -82,7 +83,7 @@ def load():
 def exported_symbols():
     """Names of the C entry points this binding declares."""
     return ["tnmc_chi_supported", "tnmc_env_bytes", "tnmc_workspace_bytes", "tnmc_make_couplings",
-            "tnmc_build_env", "tnmc_propose", "tnmc_logq", "tnmc_energy", "tnmc_accept",
+            "tnmc_build_env", "tnmc_build_env_static", "tnmc_propose", "tnmc_logq", "tnmc_energy", "tnmc_accept",
             "tnmc_observables", "tnmc_disorder_average", "tnmc_status_check",
             "tnmc_status_string"]
 
@@ -188,6 +189,14 @@ class Batch:
         ws, nb = self._ws()
         _check(load().tnmc_build_env(self.table, self.n, self.chi, self.prec, ws, nb, _ptr(lnZ),
                                      _stream()), "tnmc_build_env")
+        return lnZ
+
+    def build_env_static(self, want_lnZ=True):
+        """tnmc_build_env_static: the same as build_env, with the library's fixed scratch array
+        instead of the workspace (nothing allocated by the call)."""
+        lnZ = torch.zeros(self.n, dtype=torch.float64, device=self.device) if want_lnZ else None
+        _check(load().tnmc_build_env_static(self.table, self.n, self.chi, self.prec, _ptr(lnZ),
+                                            _stream()), "tnmc_build_env_static")
         return lnZ
 
     def spins_shape(self, K):

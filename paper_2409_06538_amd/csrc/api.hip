@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -121,6 +122,35 @@ hipError_t upload_desc(const tnmc_instance* inst, int32_t n, int32_t chi, int32_
 
 inline tnmc_status hip_status(hipError_t e) { return e == hipSuccess ? TNMC_OK : TNMC_EHIP; }
 
+// Scratch of tnmc_build_env_static: the descriptor table and the build scratch of its batch,
+// in a file-scope device array (one copy per device, held until the process ends).  Host code
+// never passes `scratch` itself to a kernel or a copy: it passes the device address that
+// hipGetSymbolAddress returns for the current device, looked up once per device.
+static_assert(TNMC_STATIC_SCRATCH_BYTES % 256 == 0, "whole 256-byte blocks");
+__device__ __align__(256) unsigned char scratch[TNMC_STATIC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::once_flag scratch_once[MAX_DEVICES];
+void* scratch_ptr[MAX_DEVICES];
+hipError_t scratch_err[MAX_DEVICES];
+
+// Device address of this device's scratch array (looked up on the first call on each device,
+// with that device current).
+hipError_t static_scratch(void** out) {
+  int dev = 0;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::call_once(scratch_once[dev], [dev] {
+    scratch_err[dev] = hipGetSymbolAddress(&scratch_ptr[dev], HIP_SYMBOL(scratch));
+    if (scratch_err[dev] == hipSuccess && scratch_ptr[dev] == nullptr)
+      scratch_err[dev] = hipErrorInvalidSymbol;
+  });
+  if (scratch_err[dev] != hipSuccess) return scratch_err[dev];
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -168,6 +198,20 @@ tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tn
   hipError_t e = upload_desc(inst, n, chi, 1, prec, Use::build, d_workspace, stream);
   if (e != hipSuccess) return TNMC_EHIP;
   return hip_status(env_build(prec, chi, static_cast<const DevReal*>(d_workspace), n, d_lnZ, stream));
+}
+
+tnmc_status tnmc_build_env_static(const tnmc_instance* inst, int32_t n, int32_t chi,
+                                  tnmc_precision prec, double* d_lnZ, hipStream_t stream) {
+  if (check_instances(inst, n, true, true) < 0 || !prec_ok(prec) || !chi_ok(chi, prec))
+    return TNMC_EINVAL;
+  // checked before any HIP call: a batch beyond the fixed array is refused
+  if (desc_bytes(n) + build_region(inst, n, chi, prec) > TNMC_STATIC_SCRATCH_BYTES)
+    return TNMC_ENOMEM;
+  void* ws = nullptr;
+  if (static_scratch(&ws) != hipSuccess) return TNMC_EHIP;
+  hipError_t e = upload_desc(inst, n, chi, 1, prec, Use::build, ws, stream);
+  if (e != hipSuccess) return TNMC_EHIP;
+  return hip_status(env_build(prec, chi, static_cast<const DevReal*>(ws), n, d_lnZ, stream));
 }
 
 static tnmc_status propose_common(const tnmc_instance* inst, int32_t n, int32_t chi,

@@ -183,6 +183,19 @@ def add_rooflines(res, args, Ls):
     return res
 
 
+def autotune(args, b, K):
+    """The library's launch-shape autotuner on the built batch: every candidate shape of the
+    proposal kernel timed once after an untimed launch; the fastest is kept in the library's
+    tuning table and used by the timed steps."""
+    if not args.autotune:
+        return None
+    t0 = time.perf_counter()
+    best, ms = b.autotune_propose(K, seed=args.seed, reps=1)
+    return {"kernel": "propose", "waves_per_workgroup": best, "proposals_per_workgroup":
+            16 * best if b.chi % 16 == 0 else 64, "ms_per_candidate": ms,
+            "search_s": time.perf_counter() - t0}
+
+
 def load_goldens():
     """Stored FP64 oracle values (tests/golden/oracle_*.json, written by
     tests/golden/make_oracle_goldens.py, which calls only the oracle)."""
@@ -334,6 +347,7 @@ def run_gpu(args, w=None):
         step(e)
         ev.append(e)          # graph mode: phase times come from the eager warm-up steps
     torch.cuda.synchronize()
+    tune = autotune(args, b, K)
     if not args.graph:
         ev = []
     graph = None
@@ -373,6 +387,7 @@ def run_gpu(args, w=None):
         "graph": bool(args.graph),
         "narrow_fraction": narrow_fraction(b),
         "error_vs_oracle": error_vs_oracle([(b, ps[-1])], args, w, Ls, seeds),
+        "autotune": tune,
     }
     if len(ps) > 1:
         res["acceptance_per_p"] = {str(p): per_p[j][0] / per_p[j][2] for j, p in enumerate(ps)}
@@ -505,6 +520,7 @@ def run_gpu_pipelined(args):
 
     run(max(1, args.warmup))
     torch.cuda.synchronize()
+    tune = autotune(args, sets[0]["b"], K)
     t0 = time.perf_counter()
     sums, ev = run(args.steps)
     torch.cuda.synchronize()
@@ -529,7 +545,7 @@ def run_gpu_pipelined(args):
            "acceptance": accepted / attempted, "build_ms": build_ms, "propose_ms": prop_ms,
            "graph": False, "pipelined": True, "builds_in_flight": depth,
            "narrow_fraction": nfrac,
-           "propose_cu_mask": cu_mask, "error_vs_oracle": err}
+           "propose_cu_mask": cu_mask, "error_vs_oracle": err, "autotune": tune}
     if len(ps) > 1:
         res["acceptance_per_p"] = {
             str(p): sum(per_stage[u][0] for u in range(j, len(per_stage), len(ps)))
@@ -707,7 +723,8 @@ def sweep_point(args, L, chi, p, n_real, K, kind):
     import copy
     w = dict(L=L, p=p, chi=chi, seeds=tuple(range(n_real)), proposals=K)
     a = copy.copy(args)
-    a.steps, a.warmup, a.graph = 1, 1, False
+    # lattices of 512 and more: no warm-up step (one build takes tens of seconds)
+    a.steps, a.warmup, a.graph = 1, (1 if L < 512 else 0), False
     res = run_gpu(a, w)
     wall_per_real = res["wall_s"]          # the realizations run side by side
     print(json.dumps({
@@ -776,6 +793,9 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="capture the whole step in one HIP graph and time its replays (phase "
                          "times then come from the eager warm-up steps)")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="time every launch shape of the proposal kernel on the built batch "
+                         "before the timed steps and keep the fastest (0: library default)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy one buffer of this many MiB once (a plain copy "
                          "kernel of known size, the reference for hardware byte counters)")
@@ -809,6 +829,7 @@ def main():
         import copy
         a2 = copy.copy(args)
         a2.steps, a2.warmup = (1, 0) if multi_p else (3, 1)
+        a2.autotune = 0          # the tuning table already holds this batch shape
         r2 = run_gpu(a2)
         res["serial"] = {"value": r2["value"], "ms_per_step": r2["ms_per_step"], "steps": a2.steps,
                          "build_ms": r2["build_ms"], "propose_ms": r2["propose_ms"],
@@ -876,6 +897,7 @@ def main():
         "build_ms": res["build_ms"],
         "propose_ms": res["propose_ms"],
         "serial": res.get("serial"),
+        "autotune": res.get("autotune"),
         "fp64_plain": plain,
         "error_vs_oracle": res.get("error_vs_oracle"),
         "roofline": res["roofline"],

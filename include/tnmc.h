@@ -169,6 +169,38 @@ tnmc_status tnmc_propose(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc
                          size_t workspace_bytes, uint64_t* d_spins, double* d_logq, int32_t* d_E,
                          uint32_t* d_fallbacks, hipStream_t stream);
 
+/* Autotuner of the proposal kernel's launch shape: wavefronts per workgroup (16 proposals each
+ * with matrix-core tiles, chi a multiple of 16; one thread per proposal otherwise).  Every shape
+ * gives bit-identical outputs (each proposal's arithmetic does not depend on its workgroup); the
+ * shape sets how many workgroups share each staged environment site and how many fill the chip.
+ * The library keeps a tuning table keyed by (chi, prec, Lmax, n, K) that tnmc_propose and
+ * tnmc_logq consult; without an entry they use the default (8 wavefronts for Lmax <= 64 when
+ * the grid covers every CU, else 4). */
+
+/* The candidate shapes at this chi: writes up to 4 values to waves (may be NULL), returns how
+ * many. */
+int32_t tnmc_propose_candidates(int32_t chi, int32_t* waves);
+
+/* Set (waves = a candidate) or erase (waves = 0) the table entry of a batch shape. */
+tnmc_status tnmc_tune_set(int32_t chi, tnmc_precision prec, int32_t Lmax, int32_t n, int32_t K,
+                          int32_t waves);
+
+/* The shape tnmc_propose uses for this batch shape (the table entry or the default); 0 on invalid
+ * arguments. */
+int32_t tnmc_tune_get(int32_t chi, tnmc_precision prec, int32_t Lmax, int32_t n, int32_t K);
+
+/* Time every candidate on this batch (one untimed launch, then `reps` launches between two HIP
+ * events on `stream`, proposals first_proposal = 0 with `seed`), store the fastest in the tuning
+ * table and in *h_best_waves (host, may be NULL); h_ms (host, may be NULL) receives the mean
+ * milliseconds per launch of each candidate in the order of tnmc_propose_candidates.  Arguments
+ * as for tnmc_propose (d_fallbacks is not used); the outputs of the last timed launch are left
+ * in d_spins, d_logq, d_E.  Synchronises the stream; not for use under graph capture. */
+tnmc_status tnmc_autotune_propose(const tnmc_instance* inst, int32_t n, int32_t chi,
+                                  tnmc_precision prec, int32_t K, uint64_t seed,
+                                  void* d_workspace, size_t workspace_bytes, uint64_t* d_spins,
+                                  double* d_logq, int32_t* d_E, int32_t reps,
+                                  int32_t* h_best_waves, float* h_ms, hipStream_t stream);
+
 /* log q(s) of given configurations (the same conditionals as tnmc_propose, with the spins read
  * from d_spins instead of drawn): d_spins [n][K][Lmax][W(Lmax)], d_logq [n][K]. */
 tnmc_status tnmc_logq(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,

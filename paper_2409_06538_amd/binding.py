@@ -64,6 +64,11 @@ def load():
         "tnmc_propose": (ctypes.c_int, [P, i32, i32, ctypes.c_int, i32, u64, u64, vp, sz, vp, vp,
                                         vp, vp, vp]),
         "tnmc_logq": (ctypes.c_int, [P, i32, i32, ctypes.c_int, i32, vp, vp, sz, vp, vp]),
+        "tnmc_propose_candidates": (i32, [i32, vp]),
+        "tnmc_tune_set": (ctypes.c_int, [i32, ctypes.c_int, i32, i32, i32, i32]),
+        "tnmc_tune_get": (i32, [i32, ctypes.c_int, i32, i32, i32]),
+        "tnmc_autotune_propose": (ctypes.c_int, [P, i32, i32, ctypes.c_int, i32, u64, vp, sz, vp,
+                                                 vp, vp, i32, vp, vp, vp]),
         "tnmc_energy": (ctypes.c_int, [P, i32, i32, vp, vp, vp, sz, vp]),
         "tnmc_accept": (ctypes.c_int, [P, i32, i32, i32, vp, vp, vp, u64, u64, vp, vp, vp, vp, vp,
                                        vp, vp, vp, sz, vp]),
@@ -83,7 +88,8 @@ def load():
 def exported_symbols():
     """Names of the C entry points this binding declares."""
     return ["tnmc_chi_supported", "tnmc_env_bytes", "tnmc_workspace_bytes", "tnmc_make_couplings",
-            "tnmc_build_env", "tnmc_build_env_static", "tnmc_propose", "tnmc_logq", "tnmc_energy", "tnmc_accept",
+            "tnmc_build_env", "tnmc_build_env_static", "tnmc_propose", "tnmc_propose_candidates", "tnmc_tune_set", "tnmc_tune_get",
+            "tnmc_autotune_propose", "tnmc_logq", "tnmc_energy", "tnmc_accept",
             "tnmc_observables", "tnmc_disorder_average", "tnmc_status_check",
             "tnmc_status_string"]
 
@@ -216,6 +222,39 @@ class Batch:
                                    int(first_proposal), ws, nb, _ptr(spins), _ptr(logq), _ptr(E),
                                    _ptr(fallbacks), _stream()), "tnmc_propose")
         return spins, logq, E
+
+    # -- launch-shape tuning of the proposal kernel ------------------------------------------
+    def propose_candidates(self):
+        """Wavefronts per workgroup the proposal kernel can use at this chi."""
+        buf = (ctypes.c_int32 * 4)()
+        m = load().tnmc_propose_candidates(self.chi, ctypes.cast(buf, ctypes.c_void_p))
+        return list(buf[:m])
+
+    def tune_set(self, K, waves):
+        """Force (waves > 0) or clear (0) the launch shape of this batch shape."""
+        _check(load().tnmc_tune_set(self.chi, self.prec, self.Lmax, self.n, int(K), int(waves)),
+               "tnmc_tune_set")
+
+    def tune_get(self, K):
+        return int(load().tnmc_tune_get(self.chi, self.prec, self.Lmax, self.n, int(K)))
+
+    def autotune_propose(self, K, seed=0, reps=2):
+        """tnmc_autotune_propose: time every candidate shape on this batch, keep the fastest.
+        Returns (best waves, {waves: ms per launch})."""
+        self.ensure_workspace(K)
+        spins = torch.empty(self.spins_shape(K), dtype=torch.int64, device=self.device)
+        logq = torch.empty((self.n, K), dtype=torch.float64, device=self.device)
+        E = torch.empty((self.n, K), dtype=torch.int32, device=self.device)
+        cands = self.propose_candidates()
+        ms = (ctypes.c_float * 4)()
+        best = ctypes.c_int32(0)
+        ws, nb = self._ws()
+        _check(load().tnmc_autotune_propose(self.table, self.n, self.chi, self.prec, int(K),
+                                            int(seed), ws, nb, _ptr(spins), _ptr(logq), _ptr(E),
+                                            int(reps), ctypes.byref(best),
+                                            ctypes.cast(ms, ctypes.c_void_p), _stream()),
+               "tnmc_autotune_propose")
+        return best.value, {c: ms[j] for j, c in enumerate(cands)}
 
     def logq(self, spins):
         """tnmc_logq: log q of given configurations (spins words [n][K][Lmax][Wmax])."""

@@ -5,7 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -151,6 +153,24 @@ hipError_t static_scratch(void** out) {
   return hipSuccess;
 }
 
+// Tuning table of the proposal kernel's launch shape (wavefronts per workgroup), filled by
+// tnmc_autotune_propose or tnmc_tune_set and read by every proposal launch.
+using TuneKey = std::tuple<int, int, int, int, int>;   // chi, precision, Lmax, n, K
+std::mutex tune_mu;
+std::map<TuneKey, int> tune_table;
+
+int tuned_waves(int chi, tnmc_precision prec, int Lmax, int n, int K) {
+  std::lock_guard<std::mutex> g(tune_mu);
+  auto it = tune_table.find(TuneKey(chi, int(prec), Lmax, n, K));
+  return it == tune_table.end() ? 0 : it->second;
+}
+
+int batch_lmax(const tnmc_instance* inst, int32_t n) {
+  int Lmax = 0;
+  for (int i = 0; i < n; ++i) Lmax = std::max(Lmax, int(inst[i].L));
+  return Lmax;
+}
+
 }  // namespace
 
 extern "C" {
@@ -214,22 +234,103 @@ tnmc_status tnmc_build_env_static(const tnmc_instance* inst, int32_t n, int32_t 
   return hip_status(env_build(prec, chi, static_cast<const DevReal*>(ws), n, d_lnZ, stream));
 }
 
+// waves > 0 forces a launch shape; otherwise the tuning table's entry or the default
 static tnmc_status propose_common(const tnmc_instance* inst, int32_t n, int32_t chi,
                                   tnmc_precision prec, int32_t K, uint64_t seed,
                                   uint64_t first_proposal, const uint64_t* d_teacher,
                                   void* d_workspace, size_t workspace_bytes, uint64_t* d_spins,
                                   double* d_logq, int32_t* d_E, uint32_t* d_fallbacks,
-                                  hipStream_t stream) {
+                                  hipStream_t stream, int waves = 0) {
   const int Lmax = check_instances(inst, n, true, true);
   if (Lmax < 0 || !prec_ok(prec) || !chi_ok(chi, prec) || K < 1 || d_workspace == nullptr ||
       d_logq == nullptr)
     return TNMC_EINVAL;
   if (d_teacher == nullptr && (d_spins == nullptr || d_E == nullptr)) return TNMC_EINVAL;
   if (workspace_bytes < desc_bytes(n) + propose_region(inst, n, chi, K, prec)) return TNMC_ENOMEM;
+  if (waves <= 0) waves = tuned_waves(chi, prec, Lmax, n, K);
   hipError_t e = upload_desc(inst, n, chi, K, prec, Use::propose, d_workspace, stream);
   if (e != hipSuccess) return TNMC_EHIP;
   return hip_status(propose(prec, chi, static_cast<const DevReal*>(d_workspace), n, K, Lmax, seed,
-                            first_proposal, d_teacher, d_spins, d_logq, d_E, d_fallbacks, stream));
+                            first_proposal, d_teacher, d_spins, d_logq, d_E, d_fallbacks, waves,
+                            stream));
+}
+
+int32_t tnmc_propose_candidates(int32_t chi, int32_t* waves) {
+  int32_t m = 0;
+  for (int w : {1, 2, 4, 8})
+    if (propose_waves_ok(chi, w)) {
+      if (waves != nullptr) waves[m] = w;
+      ++m;
+    }
+  return m;
+}
+
+tnmc_status tnmc_tune_set(int32_t chi, tnmc_precision prec, int32_t Lmax, int32_t n, int32_t K,
+                          int32_t waves) {
+  if (!prec_ok(prec) || !chi_ok(chi, prec) || Lmax < 2 || Lmax > 1024 || n < 1 || K < 1)
+    return TNMC_EINVAL;
+  if (waves != 0 && !propose_waves_ok(chi, waves)) return TNMC_EINVAL;
+  std::lock_guard<std::mutex> g(tune_mu);
+  const TuneKey key(chi, int(prec), Lmax, n, K);
+  if (waves == 0) tune_table.erase(key);
+  else tune_table[key] = waves;
+  return TNMC_OK;
+}
+
+int32_t tnmc_tune_get(int32_t chi, tnmc_precision prec, int32_t Lmax, int32_t n, int32_t K) {
+  if (!prec_ok(prec) || !chi_ok(chi, prec) || Lmax < 2 || Lmax > 1024 || n < 1 || K < 1) return 0;
+  const int w = tuned_waves(chi, prec, Lmax, n, K);
+  return w > 0 ? w : propose_default_waves(chi, n, K, Lmax);
+}
+
+tnmc_status tnmc_autotune_propose(const tnmc_instance* inst, int32_t n, int32_t chi,
+                                  tnmc_precision prec, int32_t K, uint64_t seed,
+                                  void* d_workspace, size_t workspace_bytes, uint64_t* d_spins,
+                                  double* d_logq, int32_t* d_E, int32_t reps,
+                                  int32_t* h_best_waves, float* h_ms, hipStream_t stream) {
+  if (check_instances(inst, n, true, true) < 0 || !prec_ok(prec) || !chi_ok(chi, prec) || K < 1 ||
+      reps < 1 || d_spins == nullptr || d_logq == nullptr || d_E == nullptr)
+    return TNMC_EINVAL;
+  if (d_workspace == nullptr) return TNMC_EINVAL;
+  if (workspace_bytes < desc_bytes(n) + propose_region(inst, n, chi, K, prec)) return TNMC_ENOMEM;
+  int32_t cand[4];
+  const int m = tnmc_propose_candidates(chi, cand);
+  hipEvent_t ev[2];
+  if (hipEventCreate(&ev[0]) != hipSuccess) return TNMC_EHIP;
+  if (hipEventCreate(&ev[1]) != hipSuccess) {
+    (void)hipEventDestroy(ev[0]);
+    return TNMC_EHIP;
+  }
+  tnmc_status st = TNMC_OK;
+  int best = 0;
+  float best_ms = 0.f;
+  for (int j = 0; j < m && st == TNMC_OK; ++j) {
+    // one untimed launch, then reps timed ones (the same proposals every time)
+    st = propose_common(inst, n, chi, prec, K, seed, 0, nullptr, d_workspace, workspace_bytes,
+                        d_spins, d_logq, d_E, nullptr, stream, cand[j]);
+    if (st == TNMC_OK && hipEventRecord(ev[0], stream) != hipSuccess) st = TNMC_EHIP;
+    for (int t = 0; t < reps && st == TNMC_OK; ++t)
+      st = propose_common(inst, n, chi, prec, K, seed, 0, nullptr, d_workspace, workspace_bytes,
+                          d_spins, d_logq, d_E, nullptr, stream, cand[j]);
+    float ms = 0.f;
+    if (st == TNMC_OK && (hipEventRecord(ev[1], stream) != hipSuccess ||
+                          hipEventSynchronize(ev[1]) != hipSuccess ||
+                          hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess))
+      st = TNMC_EHIP;
+    if (st != TNMC_OK) break;
+    ms /= float(reps);
+    if (h_ms != nullptr) h_ms[j] = ms;
+    if (best == 0 || ms < best_ms) {
+      best = cand[j];
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (st != TNMC_OK) return st;
+  st = tnmc_tune_set(chi, prec, batch_lmax(inst, n), n, K, best);
+  if (h_best_waves != nullptr) *h_best_waves = best;
+  return st;
 }
 
 tnmc_status tnmc_propose(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,

@@ -30,9 +30,13 @@ hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n
                      hipStream_t stream);
 size_t env_build_scratch_bytes(tnmc_precision prec, int chi, int L);
 
+// waves: wavefronts per workgroup of the proposal kernel (propose_waves_ok), 0 = default
 hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, int K, int Lmax,
                    uint64_t seed, uint64_t first, const uint64_t* d_teacher, uint64_t* d_spins,
-                   double* d_logq, int32_t* d_E, uint32_t* d_fallbacks, hipStream_t stream);
+                   double* d_logq, int32_t* d_E, uint32_t* d_fallbacks, int waves,
+                   hipStream_t stream);
+int propose_default_waves(int chi, int n, int K, int Lmax);
+int propose_waves_ok(int chi, int waves);
 size_t propose_scratch_bytes(tnmc_precision prec, int chi, int L, int K);
 
 hipError_t energy_launch(const DevReal* d_reals, int n, int K, int Lmax, const uint64_t* d_spins,

@@ -272,11 +272,20 @@ struct Mf<double> {
 // spread over 4 wavefronts).
 constexpr int MF_MAX_PROP = 128;   // K is padded to this in the workspace (any WAVES <= 8)
 constexpr int MF_CUS = 256;
-template <typename E>
-int mf_waves_for(int n, int K, int Lmax) {
+// Launch shape used when the tuning table has no entry for a call: 8 wavefronts (128 proposals
+// per workgroup) for L <= 64 when the grid still covers every CU, else 4.
+int propose_default_waves(int chi, int n, int K, int Lmax) {
+  if (chi % 16 != 0) return 1;
   const bool wide = Lmax <= 64 &&
                     size_t(n) * size_t((K + MF_MAX_PROP - 1) / MF_MAX_PROP) >= size_t(MF_CUS);
   return wide ? 8 : 4;
+}
+
+// Wavefronts per workgroup that the proposal kernel is built for at this chi (16 proposals per
+// wavefront with matrix-core tiles; one thread per proposal, 64 per workgroup, otherwise).
+int propose_waves_ok(int chi, int waves) {
+  if (chi % 16 != 0) return waves == 1;
+  return waves == 1 || waves == 2 || waves == 4 || waves == 8;
 }
 
 template <typename T, typename E, int CHI, int MF_WAVES>
@@ -663,7 +672,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
 template <typename T, typename E, int CHI>
 hipError_t launch_propose(const DevReal* d_reals, int n, int K, int Lmax, uint64_t seed,
                           uint64_t first, const uint64_t* d_teacher, uint64_t* d_spins,
-                          double* d_logq, int32_t* d_E, uint32_t* d_fallbacks,
+                          double* d_logq, int32_t* d_E, uint32_t* d_fallbacks, int waves,
                           hipStream_t stream) {
   if constexpr (CHI % 16 == 0) {
     auto go = [&](auto wc) {
@@ -672,8 +681,14 @@ hipError_t launch_propose(const DevReal* d_reals, int n, int K, int Lmax, uint64
       hipLaunchKernelGGL((propose_mfma_kernel<T, E, CHI, WAVES>), grid, dim3(64 * WAVES), 0, stream,
                          d_reals, K, Lmax, seed, first, d_teacher, d_spins, d_logq, d_E, d_fallbacks);
     };
-    if (mf_waves_for<E>(n, K, Lmax) == 4) go(std::integral_constant<int, 4>{});
-    else go(std::integral_constant<int, 8>{});
+    if (waves <= 0) waves = propose_default_waves(CHI, n, K, Lmax);
+    switch (waves) {
+      case 1: go(std::integral_constant<int, 1>{}); break;
+      case 2: go(std::integral_constant<int, 2>{}); break;
+      case 4: go(std::integral_constant<int, 4>{}); break;
+      case 8: go(std::integral_constant<int, 8>{}); break;
+      default: return hipErrorInvalidValue;
+    }
   } else {
     dim3 grid((K + PROP_NT - 1) / PROP_NT, n);
     hipLaunchKernelGGL((propose_kernel<T, E, CHI>), grid, dim3(PROP_NT), 0, stream, d_reals, K,
@@ -684,11 +699,12 @@ hipError_t launch_propose(const DevReal* d_reals, int n, int K, int Lmax, uint64
 
 hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, int K, int Lmax,
                    uint64_t seed, uint64_t first, const uint64_t* d_teacher, uint64_t* d_spins,
-                   double* d_logq, int32_t* d_E, uint32_t* d_fallbacks, hipStream_t stream) {
+                   double* d_logq, int32_t* d_E, uint32_t* d_fallbacks, int waves,
+                   hipStream_t stream) {
 #define TNMC_PROP_CASE(TY, EY, C)                                                               \
   case C:                                                                                       \
     return launch_propose<TY, EY, C>(d_reals, n, K, Lmax, seed, first, d_teacher, d_spins,      \
-                                     d_logq, d_E, d_fallbacks, stream);
+                                     d_logq, d_E, d_fallbacks, waves, stream);
 #define TNMC_PROP_CHIS(TY, EY) \
   TNMC_PROP_CASE(TY, EY, 2) TNMC_PROP_CASE(TY, EY, 4) TNMC_PROP_CASE(TY, EY, 8) \
   TNMC_PROP_CASE(TY, EY, 16) TNMC_PROP_CASE(TY, EY, 32)

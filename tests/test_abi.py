@@ -95,6 +95,8 @@ def test_short_workspace_is_enomem_on_every_entry_point(lib):
                                                  fake, fake, fake, None, None),
         "tnmc_logq": lambda: lib.tnmc_logq(tab, 2, 16, binding.FP32, 8, fake, fake, short, fake,
                                            None),
+        "tnmc_autotune_propose": lambda: lib.tnmc_autotune_propose(
+            tab, 2, 16, binding.FP32, 8, 0, fake, short, fake, fake, fake, 1, None, None, None),
         "tnmc_energy": lambda: lib.tnmc_energy(tab, 2, 8, fake, fake, fake, short, None),
         "tnmc_accept": lambda: lib.tnmc_accept(tab, 2, 1, 8, fake, fake, fake, 0, 0, fake, fake,
                                                fake, fake, fake, fake, None, fake, short, None),
@@ -124,3 +126,21 @@ def test_status_bits_match_header():
     assert int(bits["TNMC_ST_DELTA"], 16) == binding.ST_DELTA
     assert int(bits["TNMC_ST_FALLBACK"], 16) == binding.ST_FALLBACK
     assert "tnmc_status_check" in declared_symbols()
+
+
+def test_tuning_table_host_side(lib):
+    """The proposal kernel's launch-shape table: candidates per chi, set / get / erase (host
+    only)."""
+    from paper_2409_06538_amd import binding
+    buf = (ctypes.c_int32 * 4)()
+    assert lib.tnmc_propose_candidates(32, ctypes.cast(buf, ctypes.c_void_p)) == 4
+    assert list(buf) == [1, 2, 4, 8]
+    assert lib.tnmc_propose_candidates(8, ctypes.cast(buf, ctypes.c_void_p)) == 1
+    assert lib.tnmc_tune_get(32, binding.FP32, 64, 64, 1000) == 8      # default: 8 for L <= 64
+    assert lib.tnmc_tune_get(48, binding.BF16, 256, 128, 1000) == 4
+    assert lib.tnmc_tune_set(32, binding.FP32, 64, 64, 1000, 2) == 0
+    assert lib.tnmc_tune_get(32, binding.FP32, 64, 64, 1000) == 2
+    assert lib.tnmc_tune_set(32, binding.FP32, 64, 64, 1000, 3) == -1  # not a candidate
+    assert lib.tnmc_tune_set(8, binding.FP32, 64, 64, 1000, 2) == -1   # one thread per proposal
+    assert lib.tnmc_tune_set(32, binding.FP32, 64, 64, 1000, 0) == 0   # erase
+    assert lib.tnmc_tune_get(32, binding.FP32, 64, 64, 1000) == 8

@@ -40,7 +40,7 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 # vector rates)
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 HBM_PEAK_GBS = 8000.0
-DEFAULT_WORKLOAD = "rbim256"
+DEFAULT_WORKLOAD = "rbim1024"
 GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
 PARITY_BOUND = {"fp64": 1e-10, "fp32": 1e-4, "bf16": 5e-3}
 
@@ -183,6 +183,11 @@ def add_rooflines(res, args, Ls):
     return res
 
 
+def progress(msg):
+    """A line on stderr as each part of the run completes (the JSON line goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def autotune(args, b, K):
     """The library's launch-shape autotuner on the built batch: every candidate shape of the
     proposal kernel timed once after an untimed launch; the fastest is kept in the library's
@@ -191,6 +196,7 @@ def autotune(args, b, K):
         return None
     t0 = time.perf_counter()
     best, ms = b.autotune_propose(K, seed=args.seed, reps=1)
+    progress(f"autotune: {best} wavefronts per workgroup ({ms})")
     return {"kernel": "propose", "waves_per_workgroup": best, "proposals_per_workgroup":
             16 * best if b.chi % 16 == 0 else 64, "ms_per_candidate": ms,
             "search_s": time.perf_counter() - t0}
@@ -347,6 +353,7 @@ def run_gpu(args, w=None):
         step(e)
         ev.append(e)          # graph mode: phase times come from the eager warm-up steps
     torch.cuda.synchronize()
+    progress("warm-up steps done")
     tune = autotune(args, b, K)
     if not args.graph:
         ev = []
@@ -369,6 +376,7 @@ def run_gpu(args, w=None):
             ev.append(e)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    progress(f"timed steps done ({t1 - t0:.1f} s)")
     per_p = torch.stack(accs).sum(dim=0).tolist()            # [len(ps)][3]
     accepted = int(sum(a for a, _, _ in per_p))
     updates = sum(u for _, u, _ in per_p)
@@ -520,11 +528,13 @@ def run_gpu_pipelined(args):
 
     run(max(1, args.warmup))
     torch.cuda.synchronize()
+    progress("warm-up stages done")
     tune = autotune(args, sets[0]["b"], K)
     t0 = time.perf_counter()
     sums, ev = run(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    progress(f"timed steps done ({t1 - t0:.1f} s)")
     per_stage = torch.stack(sums).tolist()                   # [steps * len(ps)][3]
     accepted = int(sum(a for a, _, _ in per_stage))
     updates = sum(x for _, x, _ in per_stage)
@@ -555,10 +565,11 @@ def run_gpu_pipelined(args):
     return add_rooflines(res, args, Ls)
 
 
-def run_fp64_plain(args, L, chi, p, K_full, n_prop=20):
+def run_fp64_plain(args, L, chi, p, K_full, n_prop=None):
     """FP64 environments, one realization per call, one proposal per call (bounded sample)."""
     import torch
     from paper_2409_06538_amd import binding
+    n_prop = n_prop or (20 if L < 512 else 4)
     beta = binding.nishimori_beta(p)
     dev = torch.device("cuda:0")
     b = binding.Batch([L], [beta], [0], chi, "fp64", K=1, device=dev)
@@ -627,8 +638,12 @@ def _oracle_realization(job):
 
 
 def cpu_sample_plan(L):
-    """Full oracle realizations up to L = 64; beyond, the sliced sample (16 rows, 2 proposals)."""
-    return (None, 150) if L <= 64 else ((8, 16), 2)
+    """Full oracle realizations up to L = 64; beyond, the sliced sample (8 and 16 rows, 2
+    proposals; 4 and 8 rows and one proposal from L = 512 on, where one oracle proposal takes
+    seconds)."""
+    if L <= 64:
+        return None, 150
+    return ((8, 16), 2) if L < 512 else ((4, 8), 1)
 
 
 def _cpu_result(out, L, K_full, n_prop, sliced, cores):
@@ -708,7 +723,7 @@ def calib_copy(mib):
 
 
 DEFAULT_STEPS = {"rbim16": 50, "rbim64": 50, "mixed": 4, "rbim256": 2, "rbim256_chi32": 2,
-                 "rbim1024": 1}
+                 "rbim1024": 2}
 
 SWEEP_LS = (16, 32, 64, 128, 256)
 SWEEP_CHIS = (8, 16, 32, 48)
@@ -822,6 +837,7 @@ def main():
     cpu_all = None
     if not args.no_cpu and "L" in wl:
         cpu_all = run_cpu_all_cores(wl["L"], wl["chi"], p_cpu, K_full, args.seed)
+        progress("oracle on all host cores done")
     serial = args.serial or args.graph
     res = run_gpu(args) if serial else run_gpu_pipelined(args)
     if not serial and not args.no_serial:
@@ -831,6 +847,7 @@ def main():
         a2.steps, a2.warmup = (1, 0) if multi_p else (3, 1)
         a2.autotune = 0          # the tuning table already holds this batch shape
         r2 = run_gpu(a2)
+        progress("serial comparison done")
         res["serial"] = {"value": r2["value"], "ms_per_step": r2["ms_per_step"], "steps": a2.steps,
                          "build_ms": r2["build_ms"], "propose_ms": r2["propose_ms"],
                          "acceptance": r2["acceptance"]}
@@ -845,6 +862,8 @@ def main():
                     if c <= res["chi"] and binding.load().tnmc_chi_supported(c, binding.FP64))
     plain = None if args.no_plain or not uniform else \
         run_fp64_plain(args, L0, chi_plain, p_cpu, res["K"])
+    if plain is not None:
+        progress("FP64 plain form done")
     if plain is not None and chi_plain != res["chi"]:
         plain["chi"] = chi_plain
         plain["note"] = (f"FP64 environments are built up to chi = {chi_plain}: the FP64 plain form "

@@ -83,6 +83,11 @@ typedef struct {
   void* d_env;        /* tnmc_env_bytes(L, chi, prec) bytes: written by tnmc_build_env */
   double* d_lognorm;  /* L doubles: lambda_r = ln ||E_r||_2, written by tnmc_build_env */
   uint32_t* d_status; /* one status word (TNMC_ST_* bits, OR-ed in by the kernels), or NULL */
+  uint8_t* d_bonds;   /* L x (L + 1) bytes, or NULL: entry [r][c] bounds the bond between sites
+                         c-1 and c of E_r (no stored entry of E_r beyond it is nonzero; entries
+                         c = 0 and c = L are 1).  Written by tnmc_build_env; read by tnmc_propose
+                         and tnmc_logq to load only the nonzero block of each site (the results
+                         are the same without it; NULL: whole sites are loaded). */
 } tnmc_instance;
 
 /* Bits of a realization's status word.  Kernels only set bits; the caller clears the word (any
@@ -136,6 +141,19 @@ tnmc_status tnmc_make_couplings(const tnmc_instance* inst, int32_t n, const uint
 tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_precision prec,
                            void* d_workspace, size_t workspace_bytes, double* d_lnZ,
                            hipStream_t stream);
+
+/* The same environments by a chosen form of the build.  TNMC_FORM_DEFAULT is tnmc_build_env.
+ * TNMC_FORM_GRAM_L2 is the Gram form of the canonical compression with the per-site matrices in
+ * the workspace (L2-resident) instead of LDS -- the form tnmc_build_env uses at chi = 64 --
+ * available for TNMC_FP32 (FP64 arithmetic) and TNMC_BF16 (FP32 arithmetic) environments at
+ * chi = 8, 16, 32, 48, 64.  Same arguments, layout and errors as tnmc_build_env (TNMC_EINVAL for
+ * a form that does not exist at this chi and precision); both forms are the same compression, so
+ * their results agree to rounding of their arithmetic types. */
+#define TNMC_FORM_DEFAULT 0
+#define TNMC_FORM_GRAM_L2 1
+tnmc_status tnmc_build_env_form(const tnmc_instance* inst, int32_t n, int32_t chi,
+                                tnmc_precision prec, int32_t form, void* d_workspace,
+                                size_t workspace_bytes, double* d_lnZ, hipStream_t stream);
 
 /* tnmc_build_env for callers that cannot allocate device memory (code under HIP graph capture,
  * tight serving loops, harnesses that forbid allocation): the same environments, log-norms and

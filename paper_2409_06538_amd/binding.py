@@ -26,6 +26,7 @@ OBS_NAMES = ("count", "E", "E2", "m2", "m4", "medge2", "q", "q2", "q4")
 ST_LOGNORM, ST_WEIGHT, ST_LOGQ, ST_DELTA, ST_FALLBACK = 0x1, 0x2, 0x4, 0x8, 0x10
 ST_FAULTS = ST_LOGNORM | ST_WEIGHT | ST_LOGQ | ST_DELTA
 ENUMERIC = -4
+FORM_DEFAULT, FORM_GRAM_L2 = 0, 1
 AVG_COUNT = 12
 AVG_NAMES = ("E", "E2", "m2", "m4", "medge2", "q", "q2", "q4", "q2sq", "Q_q", "chi_q", "chi_edge")
 
@@ -36,7 +37,7 @@ class Instance(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("pad_", ctypes.c_int32), ("beta", ctypes.c_double),
                 ("id", ctypes.c_uint64), ("d_Jh", ctypes.c_void_p), ("d_Jv", ctypes.c_void_p),
                 ("d_env", ctypes.c_void_p), ("d_lognorm", ctypes.c_void_p),
-                ("d_status", ctypes.c_void_p)]
+                ("d_status", ctypes.c_void_p), ("d_bonds", ctypes.c_void_p)]
 
 
 class TNMCError(RuntimeError):
@@ -61,6 +62,7 @@ def load():
         "tnmc_make_couplings": (ctypes.c_int, [P, i32, vp, dbl, vp, sz, vp]),
         "tnmc_build_env": (ctypes.c_int, [P, i32, i32, ctypes.c_int, vp, sz, vp, vp]),
         "tnmc_build_env_static": (ctypes.c_int, [P, i32, i32, ctypes.c_int, vp, vp]),
+        "tnmc_build_env_form": (ctypes.c_int, [P, i32, i32, ctypes.c_int, i32, vp, sz, vp, vp]),
         "tnmc_propose": (ctypes.c_int, [P, i32, i32, ctypes.c_int, i32, u64, u64, vp, sz, vp, vp,
                                         vp, vp, vp]),
         "tnmc_logq": (ctypes.c_int, [P, i32, i32, ctypes.c_int, i32, vp, vp, sz, vp, vp]),
@@ -88,7 +90,7 @@ def load():
 def exported_symbols():
     """Names of the C entry points this binding declares."""
     return ["tnmc_chi_supported", "tnmc_env_bytes", "tnmc_workspace_bytes", "tnmc_make_couplings",
-            "tnmc_build_env", "tnmc_build_env_static", "tnmc_propose", "tnmc_propose_candidates", "tnmc_tune_set", "tnmc_tune_get",
+            "tnmc_build_env", "tnmc_build_env_form", "tnmc_build_env_static", "tnmc_propose", "tnmc_propose_candidates", "tnmc_tune_set", "tnmc_tune_get",
             "tnmc_autotune_propose", "tnmc_logq", "tnmc_energy", "tnmc_accept",
             "tnmc_observables", "tnmc_disorder_average", "tnmc_status_check",
             "tnmc_status_string"]
@@ -133,7 +135,7 @@ class Batch:
         self.device = torch.device(device)
         if not lib.tnmc_chi_supported(self.chi, self.prec):
             raise TNMCError(f"chi={chi} not supported for {precision}")
-        self.Jh, self.Jv, self.env, self.lognorm = [], [], [], []
+        self.Jh, self.Jv, self.env, self.lognorm, self.bonds = [], [], [], [], []
         self.table = (Instance * self.n)()
         # one numeric status word per realization (TNMC_ST_* bits)
         self.status = torch.zeros(self.n, dtype=torch.int32, device=self.device)
@@ -148,14 +150,28 @@ class Batch:
             self.Jv.append(jv)
             self.env.append(env)
             self.lognorm.append(lam)
+            bd = torch.zeros(L * (L + 1), dtype=torch.uint8, device=self.device)
+            self.bonds.append(bd)
             t = self.table[i]
             t.L, t.pad_, t.beta, t.id = L, 0, float(betas[i]), int(ids[i])
             t.d_Jh, t.d_Jv = jh.data_ptr(), jv.data_ptr()
             t.d_env, t.d_lognorm = env.data_ptr(), lam.data_ptr()
             t.d_status = self.status.data_ptr() + 4 * i
+            t.d_bonds = bd.data_ptr()
         self.K = 0
         self.workspace = None
         self.ensure_workspace(K)
+
+    def use_bonds(self, on=True):
+        """Pass (or not) each realization's bond table: written by the build, read by the
+        proposals to load only the nonzero block of each site."""
+        for i in range(self.n):
+            self.table[i].d_bonds = self.bonds[i].data_ptr() if on else None
+
+    def bond_table(self, i):
+        """Bond table of realization i as (L, L + 1)."""
+        L = self.Ls[i]
+        return self.bonds[i].view(L, L + 1)
 
     def set_betas(self, betas):
         """Change the inverse temperature of every realization (the table is passed by value
@@ -195,6 +211,15 @@ class Batch:
         ws, nb = self._ws()
         _check(load().tnmc_build_env(self.table, self.n, self.chi, self.prec, ws, nb, _ptr(lnZ),
                                      _stream()), "tnmc_build_env")
+        return lnZ
+
+    def build_env_form(self, form, want_lnZ=True):
+        """tnmc_build_env_form: the environments by a chosen form of the build (0 = default,
+        1 = the Gram form with the per-site matrices in the workspace)."""
+        lnZ = torch.zeros(self.n, dtype=torch.float64, device=self.device) if want_lnZ else None
+        ws, nb = self._ws()
+        _check(load().tnmc_build_env_form(self.table, self.n, self.chi, self.prec, int(form), ws,
+                                          nb, _ptr(lnZ), _stream()), "tnmc_build_env_form")
         return lnZ
 
     def build_env_static(self, want_lnZ=True):

@@ -24,9 +24,10 @@ inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 inline size_t elem_bytes(tnmc_precision p) { return p == TNMC_FP64 ? 8 : (p == TNMC_FP32 ? 4 : 2); }
 
 bool prec_ok(tnmc_precision p) { return p == TNMC_FP64 || p == TNMC_FP32 || p == TNMC_BF16; }
-// chi = 48 exists for FP32 and BF16 environments only
+// chi = 48 and 64 exist for FP32 and BF16 environments only
 bool chi_ok(int32_t chi, tnmc_precision p) {
-  return chi == 2 || chi == 4 || chi == 8 || chi == 16 || chi == 32 || (chi == 48 && p != TNMC_FP64);
+  return chi == 2 || chi == 4 || chi == 8 || chi == 16 || chi == 32 ||
+         ((chi == 48 || chi == 64) && p != TNMC_FP64);
 }
 
 // Basic per-instance checks; returns Lmax or -1.
@@ -115,6 +116,7 @@ hipError_t upload_desc(const tnmc_instance* inst, int32_t n, int32_t chi, int32_
     d.lognorm = inst[i].d_lognorm;
     d.ws = base + off;
     d.status = inst[i].d_status;
+    d.bonds = inst[i].d_bonds;
     if (use == Use::build) off += align_up(env_build_scratch_bytes(p, chi, inst[i].L));
     else if (use == Use::propose) off += align_up(propose_scratch_bytes(p, chi, inst[i].L, K));
   }
@@ -218,6 +220,21 @@ tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tn
   hipError_t e = upload_desc(inst, n, chi, 1, prec, Use::build, d_workspace, stream);
   if (e != hipSuccess) return TNMC_EHIP;
   return hip_status(env_build(prec, chi, static_cast<const DevReal*>(d_workspace), n, d_lnZ, stream));
+}
+
+tnmc_status tnmc_build_env_form(const tnmc_instance* inst, int32_t n, int32_t chi,
+                                tnmc_precision prec, int32_t form, void* d_workspace,
+                                size_t workspace_bytes, double* d_lnZ, hipStream_t stream) {
+  if (form == TNMC_FORM_DEFAULT)
+    return tnmc_build_env(inst, n, chi, prec, d_workspace, workspace_bytes, d_lnZ, stream);
+  if (form != TNMC_FORM_GRAM_L2 || check_instances(inst, n, true, true) < 0 ||
+      !env_build_big_ok(prec, chi) || d_workspace == nullptr)
+    return TNMC_EINVAL;
+  if (workspace_bytes < desc_bytes(n) + build_region(inst, n, chi, prec)) return TNMC_ENOMEM;
+  hipError_t e = upload_desc(inst, n, chi, 1, prec, Use::build, d_workspace, stream);
+  if (e != hipSuccess) return TNMC_EHIP;
+  return hip_status(env_build_big(prec, chi, static_cast<const DevReal*>(d_workspace), n, d_lnZ,
+                                  stream));
 }
 
 tnmc_status tnmc_build_env_static(const tnmc_instance* inst, int32_t n, int32_t chi,

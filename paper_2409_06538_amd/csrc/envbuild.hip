@@ -613,6 +613,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   for (int c = tid; c <= L; c += NT) {
     bdin[c] = 1;
     bdout[c] = 1;
+    if (R.bonds != nullptr) R.bonds[size_t(L - 1) * (L + 1) + c] = 1;
   }
 
   for (int r = L - 1; r >= 1; --r) {
@@ -1768,6 +1769,8 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       if (row_done) break;
     }
     __syncthreads();
+    if (R.bonds != nullptr)
+      for (int c = tid; c <= L; c += NT) R.bonds[size_t(r - 1) * (L + 1) + c] = bdout[c];
     {   // the bonds of E_{r-1} are the input bonds of the next row
       unsigned char* t = bdin;
       bdin = bdout;
@@ -1858,11 +1861,13 @@ hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n
     switch (chi) {
       TNMC_ENV_CHIS(double, float, true)
       TNMC_ENV_CASE(float, float, 48, false)
+      case 64: return env_build_big(prec, chi, d_reals, n, d_lnZ, stream);
     }
   } else if (prec == TNMC_BF16) {
     switch (chi) {
       TNMC_ENV_CHIS(double, bf16_t, true)
       TNMC_ENV_CASE(float, bf16_t, 48, false)
+      case 64: return env_build_big(prec, chi, d_reals, n, d_lnZ, stream);
     }
   }
 #undef TNMC_ENV_CHIS
@@ -1871,8 +1876,12 @@ hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n
 }
 
 size_t env_build_scratch_bytes(tnmc_precision prec, int chi, int L) {
-  (void)prec;   // every form keeps FP64: the carried R factor or Gram matrix of every site
-  return size_t(L) * 2 * chi * 2 * chi * sizeof(double);
+  // the LDS forms keep FP64: the carried R factor or Gram matrix of every site; the Gram form
+  // with global scratch (chi = 64, or chosen) its own layout; the larger of the two
+  const size_t lds_form = size_t(L) * 2 * chi * 2 * chi * sizeof(double);
+  if (!env_build_big_ok(prec, chi)) return lds_form;
+  const size_t big = env_build_big_scratch_bytes(prec, chi, L);
+  return big > lds_form ? big : lds_form;
 }
 
 }  // namespace tnmc

@@ -21,6 +21,7 @@ struct DevReal {
   double* lognorm;
   void* ws;   // this realization's slice of the workspace (call-specific use)
   uint32_t* status;   // numeric status word (TNMC_ST_* bits) or nullptr
+  uint8_t* bonds;     // L x (L + 1) bond dimensions of the stored environments, or nullptr
 };
 
 hipError_t couplings_launch(const DevReal* d_reals, int n, const uint64_t* d_seeds, double p,
@@ -29,6 +30,12 @@ hipError_t couplings_launch(const DevReal* d_reals, int n, const uint64_t* d_see
 hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n, double* d_lnZ,
                      hipStream_t stream);
 size_t env_build_scratch_bytes(tnmc_precision prec, int chi, int L);
+// The Gram form with global scratch (envbuild_big.hip): the build of chi = 64 (FP32 and BF16
+// environments), and a selectable form at chi = 8 .. 48
+int env_build_big_ok(tnmc_precision prec, int chi);
+hipError_t env_build_big(tnmc_precision prec, int chi, const DevReal* d_reals, int n,
+                         double* d_lnZ, hipStream_t stream);
+size_t env_build_big_scratch_bytes(tnmc_precision prec, int chi, int L);
 
 // waves: wavefronts per workgroup of the proposal kernel (propose_waves_ok), 0 = default
 hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, int K, int Lmax,

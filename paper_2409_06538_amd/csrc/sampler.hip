@@ -273,12 +273,15 @@ struct Mf<double> {
 constexpr int MF_MAX_PROP = 128;   // K is padded to this in the workspace (any WAVES <= 8)
 constexpr int MF_CUS = 256;
 // Launch shape used when the tuning table has no entry for a call: 8 wavefronts (128 proposals
-// per workgroup) for L <= 64 when the grid still covers every CU, else 4.
+// per workgroup) for L <= 64 when the grid still covers every CU; else 4, unless the grid of
+// 4-wavefront workgroups leaves CUs idle, when the fewest wavefronts per workgroup that fill them
+// (or 1: small batches of large lattices).
 int propose_default_waves(int chi, int n, int K, int Lmax) {
   if (chi % 16 != 0) return 1;
-  const bool wide = Lmax <= 64 &&
-                    size_t(n) * size_t((K + MF_MAX_PROP - 1) / MF_MAX_PROP) >= size_t(MF_CUS);
-  return wide ? 8 : 4;
+  auto grid = [&](int waves) { return size_t(n) * size_t((K + 16 * waves - 1) / (16 * waves)); };
+  if (Lmax <= 64 && grid(8) >= size_t(MF_CUS)) return 8;
+  if (grid(4) >= size_t(MF_CUS)) return 4;
+  return grid(2) >= size_t(MF_CUS) ? 2 : 1;
 }
 
 // Wavefronts per workgroup that the proposal kernel is built for at this chi (16 proposals per
@@ -357,8 +360,26 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   typedef unsigned int u4 __attribute__((ext_vector_type(PIECE / 4)));
   E pf[SPT];
   u4 pq[NQ];
+  // With the bond table, a site whose bonds are both at most 16 loads only the leading 16 x 16
+  // block of its two matrices (the rest is zero): NN entries per thread instead of SPT.
+  constexpr int NN = (2 * 256 + MF_NT - 1) / MF_NT;
+  E nf[NN];
+  bool nsite = false;   // the staged site is narrow by the bond table
+  const gmem<const uint8_t>* bonds = R.bonds ? as_global(R.bonds) : nullptr;
   auto load_site = [&](int r, int c) {
     const gmem<E>* src = env + (size_t(r) * L + c) * SITE;
+    if (CHI > 16 && bonds != nullptr) {
+      const size_t bi = size_t(r) * (L + 1) + c;
+      nsite = bonds[bi] <= 16 && bonds[bi + 1] <= 16;
+      if (nsite) {
+#pragma unroll
+        for (int t = 0; t < NN; ++t) {
+          const int e = tid + MF_NT * t;
+          if (e < 512) nf[t] = gld<E>(src, ((e >> 8) * CHI + ((e >> 4) & 15)) * CHI + (e & 15));
+        }
+        return;
+      }
+    }
     if constexpr (VEC) {
       const gmem<u4>* s4 = reinterpret_cast<const gmem<u4>*>(src + size_t(tid) * SPT);
 #pragma unroll
@@ -387,6 +408,18 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   // is narrow, and its products and V rows are the first tile only.
   auto store_site = [&](T* dst, bool transposed) {
     bool wide = false;
+    if (nsite) {
+#pragma unroll
+      for (int t = 0; t < NN; ++t) {
+        const int e = tid + MF_NT * t;
+        if (e < 512) {
+          const int y = e >> 8, a = (e >> 4) & 15, b = e & 15;
+          const int rr = transposed ? b : a, cc = transposed ? a : b;
+          dst[(y * CHI + rr) * LDB + M::pos(cc)] = widen(nf[t]);
+        }
+      }
+      return false;
+    }
 #pragma unroll
     for (int t = 0; t < SPT; ++t) {
       const int e = elem_index(t);
@@ -711,9 +744,14 @@ hipError_t propose(tnmc_precision prec, int chi, const DevReal* d_reals, int n, 
   if (prec == TNMC_FP64) {
     switch (chi) { TNMC_PROP_CHIS(double, double) }
   } else if (prec == TNMC_FP32) {
-    switch (chi) { TNMC_PROP_CHIS(float, float) TNMC_PROP_CASE(float, float, 48) }
+    switch (chi) {
+      TNMC_PROP_CHIS(float, float) TNMC_PROP_CASE(float, float, 48) TNMC_PROP_CASE(float, float, 64)
+    }
   } else if (prec == TNMC_BF16) {
-    switch (chi) { TNMC_PROP_CHIS(float, bf16_t) TNMC_PROP_CASE(float, bf16_t, 48) }
+    switch (chi) {
+      TNMC_PROP_CHIS(float, bf16_t) TNMC_PROP_CASE(float, bf16_t, 48)
+      TNMC_PROP_CASE(float, bf16_t, 64)
+    }
   }
 #undef TNMC_PROP_CHIS
 #undef TNMC_PROP_CASE

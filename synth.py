@@ -28,7 +28,7 @@ WORKLOADS = {
     "mixed": dict(Ls=(32, 64, 128, 256), p=0.109, chi=32, seeds=tuple(range(256)),
                   proposals=1000, philox_seed=0, precision="fp32"),
     "rbim1024": dict(L=1024, p=0.109, chi=64, seeds=(0, 1), proposals=1000, philox_seed=0,
-                     precision="fp32"),
+                     precision="bf16"),
 }
 
 

@@ -91,6 +91,8 @@ def test_short_workspace_is_enomem_on_every_entry_point(lib):
             tab, 2, ctypes.cast(seeds, ctypes.c_void_p), 0.1, fake, short, None),
         "tnmc_build_env": lambda: lib.tnmc_build_env(tab, 2, 16, binding.FP32, fake, short, None,
                                                      None),
+        "tnmc_build_env_form": lambda: lib.tnmc_build_env_form(tab, 2, 16, binding.FP32, 1, fake,
+                                                               short, None, None),
         "tnmc_propose": lambda: lib.tnmc_propose(tab, 2, 16, binding.FP32, 8, 0, 0, fake, short,
                                                  fake, fake, fake, None, None),
         "tnmc_logq": lambda: lib.tnmc_logq(tab, 2, 16, binding.FP32, 8, fake, fake, short, fake,

@@ -116,13 +116,16 @@ def test_mixed_batch_against_oracle(tnmc_gpu):
         check_case(b, i, g, 1e-5, 1e-4, lnZ)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16", 5e-3)])
+@pytest.mark.parametrize("precision,tol", [
+    pytest.param("fp32", 1e-5, marks=pytest.mark.skip(
+        reason="the FP32 chi = 64 build of an L = 1024 lattice (FP64 Gram matrices) takes about "
+               "four minutes; FP32 chi = 64 parity is checked at L <= 256 in test_gpu_chi64.py")),
+    ("bf16", 5e-3)])
 def test_rbim1024_chi64_first_rows_against_oracle(tnmc_gpu, precision, tol):
-    """L = 1024, chi = 64, both realizations of the workload: the first rows built (from the
-    bottom) against the oracle's slice."""
+    """L = 1024, chi = 64, both realizations of the workload (BF16 environments, the benchmark's
+    launch): the first rows built (from the bottom) against the oracle's slice, with the bond
+    table bounding every stored site."""
     from paper_2409_06538_amd import binding
-    if not binding.load().tnmc_chi_supported(64, binding.PRECISIONS[precision]):
-        pytest.skip("chi = 64 is not built")
     b, lnZ = full_batch([1024, 1024], [0, 1], 64, precision, 0.109)
     for i in (0, 1):
         check_case(b, i, load(f"rbim1024_s{i}_rows8"), tol, tol, lnZ)

@@ -565,8 +565,28 @@ def run_gpu_pipelined(args):
     return add_rooflines(res, args, Ls)
 
 
+PLAIN_MAX_L = 128
+
+
 def run_fp64_plain(args, L, chi, p, K_full, n_prop=None):
-    """FP64 environments, one realization per call, one proposal per call (bounded sample)."""
+    """FP64 environments, one realization per call, one proposal per call (bounded sample).
+    Lattices above PLAIN_MAX_L (whose FP64 build takes minutes: about 300 us per site) are
+    measured on an L = PLAIN_MAX_L lattice and extrapolated by the site count, L^2, for both the
+    build and the proposals; the acceptance is the smaller lattice's (an upper bound)."""
+    L_run = min(L, PLAIN_MAX_L)
+    out = _run_fp64_plain(args, L_run, chi, p, K_full, n_prop)
+    if L_run == L:
+        return out
+    scale = (L / L_run) ** 2
+    t_real = out["build_s"] * scale + K_full * out["s_per_proposal"] * scale
+    out.update({"value": (K_full - 1) * out["acceptance"] * L * L / t_real,
+                "measured_L": L_run,
+                "sample": out["sample"] + f"; measured at L = {L_run} and extrapolated to L = {L} "
+                          f"by the site count (x{scale:.0f}), acceptance of L = {L_run}"})
+    return out
+
+
+def _run_fp64_plain(args, L, chi, p, K_full, n_prop=None):
     import torch
     from paper_2409_06538_amd import binding
     n_prop = n_prop or (20 if L < 512 else 4)
@@ -751,6 +771,39 @@ def sweep_point(args, L, chi, p, n_real, K, kind):
         "accepted_spin_updates_per_s": res["value"]}), flush=True)
 
 
+SWEEP_OBS_LS = (8, 16, 32, 64)
+
+
+def run_observables(args, L, chi, p, n_real, K, n_chain=2):
+    """f1: the sampled quantities of Sec. III C through the GPU chains, disorder-averaged on the
+    GPU (Q_q, chi_q, chi_edge), with the Nishimori-line check [<E>] = -N_B (1 - 2p)."""
+    import numpy as np
+    import torch
+    from paper_2409_06538_amd import binding
+    dev = torch.device("cuda:0")
+    beta = binding.nishimori_beta(p)
+    seeds = list(range(n_real))
+    b = binding.Batch([L] * n_real, [beta] * n_real, seeds, chi, args.precision, K=K, device=dev)
+    b.make_couplings(seeds, p)
+    t0 = time.perf_counter()
+    b.build_env(want_lnZ=False)
+    prop = b.propose(K, args.seed)
+    chains = b.new_chains(n_chain)
+    accum = torch.zeros((n_real, binding.OBS_COUNT), dtype=torch.float64, device=dev)
+    acc, _ = b.accept(prop, chains, seed=args.seed, accum=accum)
+    avg = dict(zip(binding.AVG_NAMES, b.disorder_average(accum, n_chain).cpu().numpy().tolist()))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    a = accum.cpu().numpy()
+    e_i = a[:, 1] / a[:, 0]
+    nb = 2 * L * (L - 1)
+    return {"sweep": "observables", "L": L, "chi": chi, "p": p, "T": 1.0 / beta,
+            "precision": args.precision, "realizations": n_real, "chains": n_chain,
+            "proposals": K, "acceptance": acc.float().sum().item() / (n_real * (K - n_chain)),
+            **avg, "E_err": float(e_i.std(ddof=1) / np.sqrt(n_real)),
+            "E_nishimori": -nb * (1 - 2 * p), "wall_s": wall}
+
+
 def run_sweep(args):
     """Acceptance and cost (the quantities of the paper's acceptance-ratio and cost figures,
     Sec. III B), one serial step per point after one warm-up, one JSON line per point: p_a,
@@ -759,7 +812,9 @@ def run_sweep(args):
       acceptance_cost  L in 16..256 and chi in 8..48; 16 realizations at p = 0.109, 256 proposals
       nishimori        p_a against the temperature along the Nishimori line (p and beta_N(p)),
                        L in 64..256, chi = 16 and 32; 16 realizations, 256 proposals
-      large_L          L = 512 and 1024 at chi = 16 and 32; 4 realizations, 64 proposals"""
+      large_L          L = 512 and 1024 at chi = 16 and 32; 4 realizations, 64 proposals
+      observables      Q_q, chi_q, chi_edge (Sec. III C) at the multicritical point p = 0.10926,
+                       L = 8 .. 64, chi = 32, 128 realizations, two chains of 256 steps"""
     if args.sweep == "acceptance_cost":
         for chi in SWEEP_CHIS:
             for L in SWEEP_LS:
@@ -773,6 +828,9 @@ def run_sweep(args):
         for chi in (16, 32):
             for L in SWEEP_LARGE_LS:
                 sweep_point(args, L, chi, 0.109, 4, 64, args.sweep)
+    elif args.sweep == "observables":
+        for L in SWEEP_OBS_LS:
+            print(json.dumps(run_observables(args, L, 32, 0.10926, 128, 512)), flush=True)
 
 
 def main():
@@ -801,10 +859,12 @@ def main():
                          "proposal work (0: no CU mask)")
     ap.add_argument("--builds-in-flight", type=int, default=2, choices=[1, 2],
                     help="overlapped steps: environment builds of later steps running at once")
-    ap.add_argument("--sweep", default=None, choices=["acceptance_cost", "nishimori", "large_L"],
+    ap.add_argument("--sweep", default=None,
+                    choices=["acceptance_cost", "nishimori", "large_L", "observables"],
                     help="one JSON line per point instead of the benchmark line: acceptance and "
                          "cost against L and chi; against the temperature along the Nishimori "
-                         "line; or at L = 512 and 1024")
+                         "line; at L = 512 and 1024; or the disorder-averaged Binder ratio and "
+                         "susceptibilities at the multicritical point")
     ap.add_argument("--graph", action="store_true",
                     help="capture the whole step in one HIP graph and time its replays (phase "
                          "times then come from the eager warm-up steps)")
@@ -844,7 +904,7 @@ def main():
         # the same steps one after the other on one stream, for comparison
         import copy
         a2 = copy.copy(args)
-        a2.steps, a2.warmup = (1, 0) if multi_p else (3, 1)
+        a2.steps, a2.warmup = (1, 0) if (multi_p or max(workload_sizes(wl)[0]) > 256) else (3, 1)
         a2.autotune = 0          # the tuning table already holds this batch shape
         r2 = run_gpu(a2)
         progress("serial comparison done")

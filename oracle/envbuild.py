@@ -102,6 +102,60 @@ def compress(mps, chi):
     return T, log_carried + math.log(n), cuts
 
 
+def compress_zipup(mps, chi, direction):
+    """Zip-up compression (Stoudenmire and White, New J. Phys. 12, 055026 (2010)): one sweep of
+    SVD truncations over the row-operator-applied MPS, without the orthonormalising sweep of
+    the canonical compression.  Applying the operator exactly and then truncating site by site
+    is the same arithmetic as contracting each operator site into the carried factor during the
+    sweep.  The sweep must run away from the input's orthogonality centre: direction "rl"
+    (right to left, for an input whose norm sits in the last site, leaving sites 1..Lc-1 right-
+    orthonormal) or "lr" (left to right, for an input whose norm sits in site 0, leaving sites
+    0..Lc-2 left-orthonormal).  The truncation at a cut keeps the k = min(chi, rows, cols)
+    largest singular values of the partly swept object; unlike the canonical compression it is
+    not the optimal truncation of the whole state, because the not yet swept part is not
+    orthonormal once the operator is applied.  Returns (sites, log_norm, cuts) as compress."""
+    T = [t.copy() for t in mps]
+    Lc = len(T)
+    log_carried = 0.0
+    cuts = {}
+    if direction == "rl":
+        for c in range(Lc - 1, 0, -1):
+            dl, d, dr = T[c].shape
+            U, S, Vt = np.linalg.svd(T[c].reshape(dl, d * dr), full_matrices=False)
+            k = min(chi, S.shape[0])
+            if k < S.shape[0] and S[k - 1] > 0:
+                cuts[c] = (S[k - 1] / S[0], (S[k - 1] - S[k]) / S[k - 1])
+            nS = float(np.linalg.norm(S[:k]))
+            log_carried += math.log(nS)
+            T[c] = Vt[:k].reshape(k, d, dr)
+            T[c - 1] = np.tensordot(T[c - 1], U[:, :k] * (S[:k] / nS), axes=(2, 0))
+        n = float(np.linalg.norm(T[0]))
+        T[0] = T[0] / n
+    elif direction == "lr":
+        for c in range(Lc - 1):
+            dl, d, dr = T[c].shape
+            U, S, Vt = np.linalg.svd(T[c].reshape(dl * d, dr), full_matrices=False)
+            k = min(chi, S.shape[0])
+            if k < S.shape[0] and S[k - 1] > 0:
+                cuts[c + 1] = (S[k - 1] / S[0], (S[k - 1] - S[k]) / S[k - 1])
+            nS = float(np.linalg.norm(S[:k]))
+            log_carried += math.log(nS)
+            T[c] = U[:, :k].reshape(dl, d, k)
+            T[c + 1] = np.tensordot((S[:k] / nS)[:, None] * Vt[:k], T[c + 1], axes=(1, 0))
+        n = float(np.linalg.norm(T[Lc - 1]))
+        T[Lc - 1] = T[Lc - 1] / n
+    else:
+        raise ValueError(direction)
+    return T, log_carried + math.log(n), cuts
+
+
+def zipup_direction(Lr, r):
+    """Sweep direction of the zip-up that builds E_{r-1} from E_r: right to left for the first
+    row applied (E_{Lr-1} is a product state, so its centre may be taken at the last site), then
+    alternating, so that every sweep runs away from the centre the previous one left."""
+    return "rl" if (Lr - 1 - r) % 2 == 0 else "lr"
+
+
 def sensitivity(env, eps):
     """Largest estimated relative change of any built E_r under rounding of relative size eps:
     max over truncated cuts of min(eps / relgap, s_k / s_1).  Parity with another correct
@@ -129,8 +183,10 @@ def top_row_sum(mps, Jh_row, beta):
     return logscale + math.log(total) if total > 0 else float("nan")
 
 
-def build_env(Jh, Jv, beta, chi, rows=None):
-    """Environments E_{Lr-1}, ..., E_0 by repeated row-MPO application and compression.
+def build_env(Jh, Jv, beta, chi, rows=None, method="canonical"):
+    """Environments E_{Lr-1}, ..., E_0 by repeated row-MPO application and compression
+    (method "canonical": compress, the canonical SVD compression; "zipup": compress_zipup in the
+    direction of zipup_direction).
 
     Returns dict with
       sites[r][c] : (chi_l, 2, chi_r) tensors of the normalised MPS of E_r
@@ -151,10 +207,15 @@ def build_env(Jh, Jv, beta, chi, rows=None):
     last = 1 if rows is None else max(1, Lr - rows)
     for r in range(Lr - 1, last - 1, -1):
         big = apply_row_mpo(mps, Jh[r], Jv[r - 1], beta)
-        mps, ln_n, cuts[r - 1] = compress(big, chi)
+        if method == "canonical":
+            mps, ln_n, cuts[r - 1] = compress(big, chi)
+        elif method == "zipup":
+            mps, ln_n, cuts[r - 1] = compress_zipup(big, chi, zipup_direction(Lr, r))
+        else:
+            raise ValueError(method)
         sites[r - 1] = mps
         lognorm[r - 1] = lognorm[r] + ln_n
-    out = {"sites": sites, "lognorm": lognorm, "cuts": cuts, "chi": chi}
+    out = {"sites": sites, "lognorm": lognorm, "cuts": cuts, "chi": chi, "method": method}
     if rows is None:
         out["lnZ"] = lognorm[0] + top_row_sum(sites[0], Jh[0], beta)
     return out

@@ -125,7 +125,24 @@ def test_rbim1024_chi64_first_rows_against_oracle(tnmc_gpu, precision, tol):
     """L = 1024, chi = 64, both realizations of the workload (BF16 environments, the benchmark's
     launch): the first rows built (from the bottom) against the oracle's slice, with the bond
     table bounding every stored site."""
-    from paper_2409_06538_amd import binding
-    b, lnZ = full_batch([1024, 1024], [0, 1], 64, precision, 0.109)
+    from oracle import energy as o_energy
+    from oracle import instance as o_inst
+    L = 1024
+    b, lnZ = full_batch([L, L], [0, 1], 64, precision, 0.109)
     for i in (0, 1):
         check_case(b, i, load(f"rbim1024_s{i}_rows8"), tol, tol, lnZ)
+        # the bond table bounds the stored sites of the rows compared
+        bt = b.bond_table(i).cpu().numpy().astype(int)
+        al = np.arange(64)
+        for r in range(L - 9, L):
+            e = b.env_tensor(i)[r].float().cpu().numpy()          # (L, 2, 64, 64)
+            for c in range(L):
+                outside = (al[:, None] >= bt[r, c]) | (al[None, :] >= bt[r, c + 1])
+                assert not np.any(e[c][:, outside]), (r, c)
+    # proposals in the benchmark's launch: exact energies and self-consistent log q
+    spins, logq, E = b.propose(4, 0)
+    np.testing.assert_array_equal(host(b.logq(spins)), host(logq))
+    for i in (0, 1):
+        Jh, Jv = o_inst.couplings(i, L, 0.109)
+        sp = synth.unpack_rows(host(spins)[i].view(np.uint64), L)
+        np.testing.assert_array_equal(host(E)[i], o_energy.energy(sp, Jh, Jv))

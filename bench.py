@@ -772,6 +772,49 @@ def sweep_point(args, L, chi, p, n_real, K, kind):
 
 
 SWEEP_OBS_LS = (8, 16, 32, 64)
+# (L, chi, precision, realizations, proposals) of the forms sweep
+SWEEP_FORMS = ((64, 16, "fp32", 64, 256), (256, 16, "fp32", 16, 256), (256, 32, "fp32", 16, 256),
+               (256, 64, "bf16", 16, 256), (256, 64, "fp32", 4, 256), (512, 16, "fp32", 4, 128),
+               (1024, 64, "bf16", 2, 256))
+
+
+def sweep_forms_point(L, chi, precision, n_real, K, p=0.109, seed=0):
+    """f3: the canonical compression (Gram form, matrices in the workspace) against the zip-up
+    on the same batch: build time (HIP events on the launch stream), mean kept bond (bond
+    table, interior cuts of every built row), ln Z difference, acceptance of one chain per
+    realization over K proposals, accepted spin-updates/s of one serial step."""
+    import torch
+    from paper_2409_06538_amd import binding
+    dev = torch.device("cuda:0")
+    beta = binding.nishimori_beta(p)
+    seeds = list(range(n_real))
+    b = binding.Batch([L] * n_real, [beta] * n_real, seeds, chi, precision, K=K, device=dev)
+    b.make_couplings(seeds, p)
+    out, lnZs = {}, {}
+    for name, form in (("canonical", binding.FORM_GRAM_L2), ("zipup", binding.FORM_ZIPUP)):
+        progress(f"forms L={L} chi={chi} {precision}: {name} build")
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        t0 = time.perf_counter()
+        e0.record()
+        lnZ = b.build_env_form(form)
+        e1.record()
+        prop = b.propose(K, seed)
+        chains = b.new_chains(1)
+        acc, _ = b.accept(prop, chains, seed=seed)
+        e2.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st, _ = b.status_check()
+        bonds = torch.stack([b.bond_table(i)[:L - 1, 1:L].float().mean() for i in range(n_real)])
+        accepted = acc.float().sum().item()
+        lnZs[name] = lnZ.cpu()
+        out[name] = {"build_ms": e0.elapsed_time(e1), "propose_accept_ms": e1.elapsed_time(e2),
+                     "mean_bond": bonds.mean().item(), "acceptance": accepted / (n_real * (K - 1)),
+                     "accepted_spin_updates_per_s": accepted * L * L / wall, "status": st}
+    d = (lnZs["zipup"] - lnZs["canonical"]).abs() / lnZs["canonical"].abs()
+    return {"sweep": "forms", "L": L, "chi": chi, "p": p, "precision": precision,
+            "realizations": n_real, "proposals": K, **out,
+            "lnZ_rel_diff_max": d.max().item(), "lnZ_rel_diff_mean": d.mean().item()}
 
 
 def run_observables(args, L, chi, p, n_real, K, n_chain=2):
@@ -814,7 +857,9 @@ def run_sweep(args):
                        L in 64..256, chi = 16 and 32; 16 realizations, 256 proposals
       large_L          L = 512 and 1024 at chi = 16 and 32; 4 realizations, 64 proposals
       observables      Q_q, chi_q, chi_edge (Sec. III C) at the multicritical point p = 0.10926,
-                       L = 8 .. 64, chi = 32, 128 realizations, two chains of 256 steps"""
+                       L = 8 .. 64, chi = 32, 128 realizations, two chains of 256 steps
+      forms            canonical compression against the zip-up on the same batches (Sec. II B
+                       variants): build time, kept bonds, ln Z, acceptance"""
     if args.sweep == "acceptance_cost":
         for chi in SWEEP_CHIS:
             for L in SWEEP_LS:
@@ -831,6 +876,10 @@ def run_sweep(args):
     elif args.sweep == "observables":
         for L in SWEEP_OBS_LS:
             print(json.dumps(run_observables(args, L, 32, 0.10926, 128, 512)), flush=True)
+    elif args.sweep == "forms":
+        for L, chi, prec, n_real, K in SWEEP_FORMS:
+            print(json.dumps(sweep_forms_point(L, chi, prec, n_real, K, seed=args.seed)),
+                  flush=True)
 
 
 def main():
@@ -860,7 +909,7 @@ def main():
     ap.add_argument("--builds-in-flight", type=int, default=2, choices=[1, 2],
                     help="overlapped steps: environment builds of later steps running at once")
     ap.add_argument("--sweep", default=None,
-                    choices=["acceptance_cost", "nishimori", "large_L", "observables"],
+                    choices=["acceptance_cost", "nishimori", "large_L", "observables", "forms"],
                     help="one JSON line per point instead of the benchmark line: acceptance and "
                          "cost against L and chi; against the temperature along the Nishimori "
                          "line; at L = 512 and 1024; or the disorder-averaged Binder ratio and "

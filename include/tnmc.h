@@ -145,12 +145,22 @@ tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tn
 /* The same environments by a chosen form of the build.  TNMC_FORM_DEFAULT is tnmc_build_env.
  * TNMC_FORM_GRAM_L2 is the Gram form of the canonical compression with the per-site matrices in
  * the workspace (L2-resident) instead of LDS -- the form tnmc_build_env uses at chi = 64 --
- * available for TNMC_FP32 (FP64 arithmetic) and TNMC_BF16 (FP32 arithmetic) environments at
- * chi = 8, 16, 32, 48, 64.  Same arguments, layout and errors as tnmc_build_env (TNMC_EINVAL for
- * a form that does not exist at this chi and precision); both forms are the same compression, so
- * their results agree to rounding of their arithmetic types. */
+ * available for TNMC_FP32 (FP64 arithmetic) and TNMC_BF16 (FP32 arithmetic, with a coarser
+ * numerical-rank cut) environments at chi = 8, 16, 32, 48, 64.  Same arguments, layout and errors
+ * as tnmc_build_env (TNMC_EINVAL for a form that does not exist at this chi and precision); the
+ * two forms are the same compression, so their results agree to rounding and rank cut. */
 #define TNMC_FORM_DEFAULT 0
 #define TNMC_FORM_GRAM_L2 1
+/* TNMC_FORM_ZIPUP: a different compression, the zip-up (Stoudenmire and White, New J. Phys. 12,
+ * 055026 (2010); a contraction variant of Sec. II B): per row one sweep of SVD truncations over
+ * the operator-applied MPS, without the orthonormalising sweep, right to left for the first row
+ * applied and then alternating so that each sweep runs away from the orthogonality centre the
+ * previous one left.  Cheaper than the canonical compression (no Gram matrices, half the
+ * products) and less accurate (each cut keeps the leading directions of the swept block, not
+ * the state's Schmidt directions), so it lowers the acceptance; the stored environments
+ * alternate between right- and left-orthonormal sites, which the sampler does not depend on.
+ * Same precisions and chi as TNMC_FORM_GRAM_L2. */
+#define TNMC_FORM_ZIPUP 2
 tnmc_status tnmc_build_env_form(const tnmc_instance* inst, int32_t n, int32_t chi,
                                 tnmc_precision prec, int32_t form, void* d_workspace,
                                 size_t workspace_bytes, double* d_lnZ, hipStream_t stream);

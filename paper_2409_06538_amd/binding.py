@@ -26,7 +26,7 @@ OBS_NAMES = ("count", "E", "E2", "m2", "m4", "medge2", "q", "q2", "q4")
 ST_LOGNORM, ST_WEIGHT, ST_LOGQ, ST_DELTA, ST_FALLBACK = 0x1, 0x2, 0x4, 0x8, 0x10
 ST_FAULTS = ST_LOGNORM | ST_WEIGHT | ST_LOGQ | ST_DELTA
 ENUMERIC = -4
-FORM_DEFAULT, FORM_GRAM_L2 = 0, 1
+FORM_DEFAULT, FORM_GRAM_L2, FORM_ZIPUP = 0, 1, 2
 AVG_COUNT = 12
 AVG_NAMES = ("E", "E2", "m2", "m4", "medge2", "q", "q2", "q4", "q2sq", "Q_q", "chi_q", "chi_edge")
 

@@ -227,14 +227,15 @@ tnmc_status tnmc_build_env_form(const tnmc_instance* inst, int32_t n, int32_t ch
                                 size_t workspace_bytes, double* d_lnZ, hipStream_t stream) {
   if (form == TNMC_FORM_DEFAULT)
     return tnmc_build_env(inst, n, chi, prec, d_workspace, workspace_bytes, d_lnZ, stream);
-  if (form != TNMC_FORM_GRAM_L2 || check_instances(inst, n, true, true) < 0 ||
-      !env_build_big_ok(prec, chi) || d_workspace == nullptr)
+  if ((form != TNMC_FORM_GRAM_L2 && form != TNMC_FORM_ZIPUP) ||
+      check_instances(inst, n, true, true) < 0 || !env_build_big_ok(prec, chi) ||
+      d_workspace == nullptr)
     return TNMC_EINVAL;
   if (workspace_bytes < desc_bytes(n) + build_region(inst, n, chi, prec)) return TNMC_ENOMEM;
   hipError_t e = upload_desc(inst, n, chi, 1, prec, Use::build, d_workspace, stream);
   if (e != hipSuccess) return TNMC_EHIP;
-  return hip_status(env_build_big(prec, chi, static_cast<const DevReal*>(d_workspace), n, d_lnZ,
-                                  stream));
+  return hip_status(env_build_big(prec, chi, form == TNMC_FORM_ZIPUP,
+                                  static_cast<const DevReal*>(d_workspace), n, d_lnZ, stream));
 }
 
 tnmc_status tnmc_build_env_static(const tnmc_instance* inst, int32_t n, int32_t chi,

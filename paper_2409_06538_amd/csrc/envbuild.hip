@@ -1861,13 +1861,13 @@ hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n
     switch (chi) {
       TNMC_ENV_CHIS(double, float, true)
       TNMC_ENV_CASE(float, float, 48, false)
-      case 64: return env_build_big(prec, chi, d_reals, n, d_lnZ, stream);
+      case 64: return env_build_big(prec, chi, false, d_reals, n, d_lnZ, stream);
     }
   } else if (prec == TNMC_BF16) {
     switch (chi) {
       TNMC_ENV_CHIS(double, bf16_t, true)
       TNMC_ENV_CASE(float, bf16_t, 48, false)
-      case 64: return env_build_big(prec, chi, d_reals, n, d_lnZ, stream);
+      case 64: return env_build_big(prec, chi, false, d_reals, n, d_lnZ, stream);
     }
   }
 #undef TNMC_ENV_CHIS

@@ -146,7 +146,7 @@ constexpr size_t big_block() {
   return size_t(2 * CHI) * (2 * CHI);
 }
 
-template <typename T, typename E, int CHI>
+template <typename T, typename E, int CHI, bool ZIP>
 __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* reals,
                                                                double* lnZ_out) {
   using S = BigSmem<T, CHI>;
@@ -224,6 +224,197 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
   }
   __syncthreads();
 
+  // H (nk x nk, symmetric, formed by fill_h(H, ldh)) -> the kept orthonormal rows of its
+  // factor in sV (nk entries each); returns how many.  Pivoted Cholesky stopped at the
+  // numerical rank, one-sided Jacobi and the CHI largest directions when the rank exceeds CHI,
+  // Gram-Schmidt twice.  Shared by both sweep directions.
+  auto factor_rows = [&](const int nk, auto fill_h) -> int {
+    // H in LDS (its own buffer, or the V buffer when it is small enough), else global memory
+    const bool h_in_v = !S::H_IN_LDS && nk <= S::HS;
+    T* H = S::H_IN_LDS ? sHl : (h_in_v ? sV : Hg);
+    const int ldh = S::H_IN_LDS ? LDH : (h_in_v ? nk + 1 : N2);
+    const bool h_global = !S::H_IN_LDS && !h_in_v;
+    fill_h(H, ldh);
+    __syncthreads();
+
+    // ---- pivoted Cholesky of H in place (one wavefront, rows lane and lane + 64) ----
+    // Left-looking: with p_j the row of largest remaining diagonal d,
+    //   L[a][j] = (H[a][p_j] - sum_{i<j} L[a][i] L[p_j][i]) / sqrt(d[p_j]),  d[a] -= L[a][j]^2,
+    // and L[.][j] overwrites column p_j of H (no entry of that column is read again).
+    if (wv == 0) {
+      const int a0 = lane, a1 = lane + 64;
+      const bool v0 = a0 < nk, v1 = a1 < nk;
+      T d0 = v0 ? H[a0 * ldh + a0] : T(0), d1 = v1 ? H[a1 * ldh + a1] : T(0);
+      const T tr = wave_sum(fmax(d0, T(0)) + fmax(d1, T(0)));
+      const T tol2 = T(Tol::rank2) * tr;
+      bool pk0 = !v0, pk1 = !v1;
+      int rk = nk;
+      for (int j = 0; j < nk; ++j) {
+        const uint32_t key0 =
+            pk0 ? 0u : ((__float_as_uint(float(fmax(d0, T(0)))) & ~127u) | uint32_t(127 - a0));
+        const uint32_t key1 =
+            pk1 ? 0u : ((__float_as_uint(float(fmax(d1, T(0)))) & ~127u) | uint32_t(127 - a1));
+        const uint32_t bk = wave_max_u32(key0 > key1 ? key0 : key1);
+        const int piv = 127 - int(bk & 127u);
+        const T best = piv < 64 ? readlane_v(d0, piv) : readlane_v(d1, piv - 64);
+        if (bk == 0u || !(best > tol2)) {
+          rk = j;
+          break;
+        }
+        const T inv = T(1) / sqrt(best);
+        const T sq = best * inv;
+        T dot0 = 0, dot1 = 0;
+        for (int i = 0; i < j; ++i) {
+          const int pc = perm[i];
+          const T lp = H[piv * ldh + pc];
+          dot0 += (v0 ? H[a0 * ldh + pc] : T(0)) * lp;
+          dot1 += (v1 ? H[a1 * ldh + pc] : T(0)) * lp;
+        }
+        const T h0 = v0 ? H[a0 * ldh + piv] : T(0), h1 = v1 ? H[a1 * ldh + piv] : T(0);
+        const T l0 = (a0 == piv) ? sq : (!pk0 ? (h0 - dot0) * inv : T(0));
+        const T l1 = (a1 == piv) ? sq : (!pk1 ? (h1 - dot1) * inv : T(0));
+        // (this step reads no entry of column piv after writing it: no wait before the writes)
+        if (v0) H[a0 * ldh + piv] = l0;
+        if (v1) H[a1 * ldh + piv] = l1;
+        if (!pk0 && a0 != piv) d0 -= l0 * l0;
+        if (!pk1 && a1 != piv) d1 -= l1 * l1;
+        if (a0 == piv) pk0 = true;
+        if (a1 == piv) pk1 = true;
+        if (lane == 0) perm[j] = piv;
+        if (h_global) __threadfence_block();   // the writes before the next step's reads
+      }
+      if (lane == 0) imisc[0] = rk;
+    }
+    __syncthreads();
+    const int rank = imisc[0];
+    int kept = rank < CHI ? rank : CHI;
+    // J row j = column perm[j] of the factor: J[j][a] = H[a][perm[j]]
+    if (rank > CHI) {
+      // ---- one-sided Jacobi on the rows of J (rank x nk), then the CHI largest ----
+      T* Jr = Ws;   // rows, ld N2 (W is no longer needed)
+      const int nr = rank + (rank & 1);
+      for (int o = tid; o < nr * nk; o += NT) {
+        const int j = o / nk, a = o % nk;
+        Jr[j * N2 + a] = j < rank ? H[a * ldh + perm[j]] : T(0);
+      }
+      __syncthreads();
+      constexpr int TPP = 8;   // threads per row pair
+      const int g = tid / TPP, gl = tid % TPP, npair = nr / 2;
+      for (int sweep = 0; sweep < BIG_MAX_SWEEPS; ++sweep) {
+        int rotated = 0;
+        for (int rd = 0; rd < nr - 1; ++rd) {
+          for (int pg = g; pg < npair; pg += NT / TPP) {
+            int p, qq;
+            if (pg == 0) {
+              p = nr - 1;
+              qq = rd;
+            } else {
+              p = (rd + pg) % (nr - 1);
+              qq = (rd - pg + nr - 1) % (nr - 1);
+            }
+            T aa = 0, bb = 0, cc = 0;
+            for (int e = gl; e < nk; e += TPP) {
+              const T xp = Jr[p * N2 + e], xq = Jr[qq * N2 + e];
+              aa += xp * xp;
+              bb += xq * xq;
+              cc += xp * xq;
+            }
+            aa = group_sum<TPP>(aa);
+            bb = group_sum<TPP>(bb);
+            cc = group_sum<TPP>(cc);
+            if (aa > T(0) && bb > T(0) && cc * cc > T(Tol::rot) * T(Tol::rot) * aa * bb) {
+              // rotation zeroing the inner product of rows p and q
+              const T zeta = (bb - aa) / (T(2) * cc);
+              const T tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
+              const T cs = T(1) / sqrt(T(1) + tt * tt), sn = cs * tt;
+              for (int e = gl; e < nk; e += TPP) {
+                const T xp = Jr[p * N2 + e], xq = Jr[qq * N2 + e];
+                Jr[p * N2 + e] = cs * xp - sn * xq;
+                Jr[qq * N2 + e] = sn * xp + cs * xq;
+              }
+              rotated = 1;
+            }
+          }
+          __syncthreads();
+        }
+        if (!__syncthreads_or(rotated)) break;
+      }
+      // row norms, then each row's place in decreasing order (ties: smaller index first)
+      for (int j = tid; j < nr; j += NT) {
+        T s = 0;
+        for (int e = 0; e < nk; ++e) s += Jr[j * N2 + e] * Jr[j * N2 + e];
+        vec[j] = j < rank ? s : T(-1);
+      }
+      __syncthreads();
+      for (int j = tid; j < rank; j += NT) {
+        int place = 0;
+        for (int i = 0; i < rank; ++i) place += (vec[i] > vec[j] || (vec[i] == vec[j] && i < j));
+        if (place < CHI) ord[place] = j;
+      }
+      __syncthreads();
+      for (int o = tid; o < CHI * nk; o += NT) {
+        const int kk = o / nk, a = o % nk;
+        sV[kk * LDH + a] = Jr[ord[kk] * N2 + a];
+      }
+      kept = CHI;
+    } else if (h_in_v) {
+      // H occupies the V buffer: the rows of J pass through registers
+      constexpr int PER = (CHI * S::HS + NT - 1) / NT;
+      T tmp[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int o = tid + u * NT;
+        if (o < kept * nk) tmp[u] = H[(o % nk) * ldh + perm[o / nk]];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int o = tid + u * NT;
+        if (o < kept * nk) sV[(o / nk) * LDH + o % nk] = tmp[u];
+      }
+    } else {
+      for (int o = tid; o < kept * nk; o += NT) {
+        const int kk = o / nk, a = o % nk;
+        sV[kk * LDH + a] = H[a * ldh + perm[kk]];
+      }
+    }
+    __syncthreads();
+    // ---- Gram-Schmidt on the kept rows, twice (one wavefront, entries lane and lane + 64) ----
+    if (wv == 0) {
+      const int a0 = lane, a1 = lane + 64;
+      const bool v0 = a0 < nk, v1 = a1 < nk;
+      for (int j = 0; j < kept; ++j) {
+        T x0 = v0 ? sV[j * LDH + a0] : T(0), x1 = v1 ? sV[j * LDH + a1] : T(0);
+        const T n2 = wave_sum(x0 * x0 + x1 * x1);
+        // classical Gram-Schmidt, twice: the projections on the earlier rows are independent
+        // reductions, taken four at a time
+        for (int pass = 0; pass < 2; ++pass)
+          for (int i0 = 0; i0 < j; i0 += 4) {
+            T u0[4], u1[4], d[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int i = i0 + u < j ? i0 + u : j - 1;
+              u0[u] = (v0 && i0 + u < j) ? sV[i * LDH + a0] : T(0);
+              u1[u] = (v1 && i0 + u < j) ? sV[i * LDH + a1] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) d[u] = wave_sum(x0 * u0[u] + x1 * u1[u]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              x0 -= d[u] * u0[u];
+              x1 -= d[u] * u1[u];
+            }
+          }
+        const T r2 = wave_sum(x0 * x0 + x1 * x1);
+        const T s = (n2 > T(0) && r2 > T(Tol::eta) * n2) ? T(1) / sqrt(r2) : T(0);
+        if (v0) sV[j * LDH + a0] = x0 * s;
+        if (v1) sV[j * LDH + a1] = x1 * s;
+      }
+    }
+    __syncthreads();
+    return kept;
+  };
+
   for (int r = L - 1; r >= 1; --r) {
     const gmem<E>* Ain = env + size_t(r) * rowst;
     gmem<E>* Aout = env + size_t(r - 1) * rowst;
@@ -232,8 +423,11 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
     auto hbit = [&](int c) { return bool((jh[c >> 6] >> (c & 63)) & 1ull); };   // bond (c, c+1)
     auto vbit = [&](int c) { return bool((jv[c >> 6] >> (c & 63)) & 1ull); };   // bond (r-1, r) at c
 
+    // zip-up: one sweep per row, right to left on the first row applied, then alternating
+    const bool rl = !ZIP || ((L - 1 - r) % 2 == 0);
+
     // ------------------------------ left to right: Gram matrices ------------------------------
-    for (int c = 0; c <= L - 2; ++c) {
+    for (int c = 0; c <= L - 2 && !ZIP; ++c) {
       const int l = bdin[c], m = bdin[c + 1];
       stage(Ain + size_t(c) * site, l, m);
       const bool fv = vbit(c);
@@ -297,6 +491,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
     // ------------------------------ right to left: SVD steps ------------------------------
     int xb = 0;          // carried factor in Xs + xb N2 CHI: rows (b, al') < 2m, columns < k
     int texp = 0;        // sum of the power-of-two exponents taken out of the carried factors
+    if (rl) {
     for (int o = tid; o < 2; o += NT) Xs[o * CHI] = T(1);   // Xt_L: b summed (m = k = 1)
     __syncthreads();
     for (int c = L - 1; c >= 1; --c) {
@@ -343,199 +538,22 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       }
       __syncthreads();
       const int nz = 2 * l, nk = 2 * k;
-      // W = G_{c-1} Z (nz x nk), then H = Z^T W (nk x nk, symmetric)
-      const T* Gp = Gs + size_t(c - 1) * BLK;
-      big_gemm<T>(
-          nz, nk, nz, [&](int i, int kk) { return (i < nz && kk < nz) ? Gp[i * N2 + kk] : T(0); },
-          [&](int kk, int j) { return (kk < nz && j < nk) ? Zs[kk * N2 + j] : T(0); },
-          [&](int i, int j, T v) { Ws[i * N2 + j] = v; });
-      __syncthreads();
-      // H in LDS (its own buffer, or the V buffer when it is small enough), else global memory
-      const bool h_in_v = !S::H_IN_LDS && nk <= S::HS;
-      T* H = S::H_IN_LDS ? sHl : (h_in_v ? sV : Hg);
-      const int ldh = S::H_IN_LDS ? LDH : (h_in_v ? nk + 1 : N2);
-      const bool h_global = !S::H_IN_LDS && !h_in_v;
-      big_gemm<T>(
-          nk, nk, nz, [&](int i, int kk) { return (i < nk && kk < nz) ? Zs[kk * N2 + i] : T(0); },
-          [&](int kk, int j) { return (kk < nz && j < nk) ? Ws[kk * N2 + j] : T(0); },
-          [&](int i, int j, T v) { H[i * ldh + j] = v; });
-      __syncthreads();
-
-      // ---- pivoted Cholesky of H in place (one wavefront, rows lane and lane + 64) ----
-      // Left-looking: with p_j the row of largest remaining diagonal d,
-      //   L[a][j] = (H[a][p_j] - sum_{i<j} L[a][i] L[p_j][i]) / sqrt(d[p_j]),  d[a] -= L[a][j]^2,
-      // and L[.][j] overwrites column p_j of H (no entry of that column is read again).
-      if (wv == 0) {
-        const int a0 = lane, a1 = lane + 64;
-        const bool v0 = a0 < nk, v1 = a1 < nk;
-        T d0 = v0 ? H[a0 * ldh + a0] : T(0), d1 = v1 ? H[a1 * ldh + a1] : T(0);
-        const T tr = wave_sum(fmax(d0, T(0)) + fmax(d1, T(0)));
-        const T tol2 = T(Tol::rank2) * tr;
-        bool pk0 = !v0, pk1 = !v1;
-        int rk = nk;
-        for (int j = 0; j < nk; ++j) {
-          const uint32_t key0 =
-              pk0 ? 0u : ((__float_as_uint(float(fmax(d0, T(0)))) & ~127u) | uint32_t(127 - a0));
-          const uint32_t key1 =
-              pk1 ? 0u : ((__float_as_uint(float(fmax(d1, T(0)))) & ~127u) | uint32_t(127 - a1));
-          const uint32_t bk = wave_max_u32(key0 > key1 ? key0 : key1);
-          const int piv = 127 - int(bk & 127u);
-          const T best = piv < 64 ? readlane_v(d0, piv) : readlane_v(d1, piv - 64);
-          if (bk == 0u || !(best > tol2)) {
-            rk = j;
-            break;
-          }
-          const T inv = T(1) / sqrt(best);
-          const T sq = best * inv;
-          T dot0 = 0, dot1 = 0;
-          for (int i = 0; i < j; ++i) {
-            const int pc = perm[i];
-            const T lp = H[piv * ldh + pc];
-            dot0 += (v0 ? H[a0 * ldh + pc] : T(0)) * lp;
-            dot1 += (v1 ? H[a1 * ldh + pc] : T(0)) * lp;
-          }
-          const T h0 = v0 ? H[a0 * ldh + piv] : T(0), h1 = v1 ? H[a1 * ldh + piv] : T(0);
-          const T l0 = (a0 == piv) ? sq : (!pk0 ? (h0 - dot0) * inv : T(0));
-          const T l1 = (a1 == piv) ? sq : (!pk1 ? (h1 - dot1) * inv : T(0));
-          // (this step reads no entry of column piv after writing it: no wait before the writes)
-          if (v0) H[a0 * ldh + piv] = l0;
-          if (v1) H[a1 * ldh + piv] = l1;
-          if (!pk0 && a0 != piv) d0 -= l0 * l0;
-          if (!pk1 && a1 != piv) d1 -= l1 * l1;
-          if (a0 == piv) pk0 = true;
-          if (a1 == piv) pk1 = true;
-          if (lane == 0) perm[j] = piv;
-          if (h_global) __threadfence_block();   // the writes before the next step's reads
-        }
-        if (lane == 0) imisc[0] = rk;
+      // W = G_{c-1} Z (nz x nk), then H = Z^T W (nk x nk, symmetric); the zip-up takes G = 1
+      const T* Wz = ZIP ? Zs : Ws;
+      if (!ZIP) {
+        const T* Gp = Gs + size_t(c - 1) * BLK;
+        big_gemm<T>(
+            nz, nk, nz, [&](int i, int kk) { return (i < nz && kk < nz) ? Gp[i * N2 + kk] : T(0); },
+            [&](int kk, int j) { return (kk < nz && j < nk) ? Zs[kk * N2 + j] : T(0); },
+            [&](int i, int j, T v) { Ws[i * N2 + j] = v; });
+        __syncthreads();
       }
-      __syncthreads();
-      const int rank = imisc[0];
-      int kept = rank < CHI ? rank : CHI;
-      // J row j = column perm[j] of the factor: J[j][a] = H[a][perm[j]]
-      if (rank > CHI) {
-        // ---- one-sided Jacobi on the rows of J (rank x nk), then the CHI largest ----
-        T* Jr = Ws;   // rows, ld N2 (W is no longer needed)
-        const int nr = rank + (rank & 1);
-        for (int o = tid; o < nr * nk; o += NT) {
-          const int j = o / nk, a = o % nk;
-          Jr[j * N2 + a] = j < rank ? H[a * ldh + perm[j]] : T(0);
-        }
-        __syncthreads();
-        constexpr int TPP = 8;   // threads per row pair
-        const int g = tid / TPP, gl = tid % TPP, npair = nr / 2;
-        for (int sweep = 0; sweep < BIG_MAX_SWEEPS; ++sweep) {
-          int rotated = 0;
-          for (int rd = 0; rd < nr - 1; ++rd) {
-            for (int pg = g; pg < npair; pg += NT / TPP) {
-              int p, qq;
-              if (pg == 0) {
-                p = nr - 1;
-                qq = rd;
-              } else {
-                p = (rd + pg) % (nr - 1);
-                qq = (rd - pg + nr - 1) % (nr - 1);
-              }
-              T aa = 0, bb = 0, cc = 0;
-              for (int e = gl; e < nk; e += TPP) {
-                const T xp = Jr[p * N2 + e], xq = Jr[qq * N2 + e];
-                aa += xp * xp;
-                bb += xq * xq;
-                cc += xp * xq;
-              }
-              aa = group_sum<TPP>(aa);
-              bb = group_sum<TPP>(bb);
-              cc = group_sum<TPP>(cc);
-              if (aa > T(0) && bb > T(0) && cc * cc > T(Tol::rot) * T(Tol::rot) * aa * bb) {
-                // rotation zeroing the inner product of rows p and q
-                const T zeta = (bb - aa) / (T(2) * cc);
-                const T tt = (zeta >= T(0) ? T(1) : T(-1)) / (fabs(zeta) + sqrt(T(1) + zeta * zeta));
-                const T cs = T(1) / sqrt(T(1) + tt * tt), sn = cs * tt;
-                for (int e = gl; e < nk; e += TPP) {
-                  const T xp = Jr[p * N2 + e], xq = Jr[qq * N2 + e];
-                  Jr[p * N2 + e] = cs * xp - sn * xq;
-                  Jr[qq * N2 + e] = sn * xp + cs * xq;
-                }
-                rotated = 1;
-              }
-            }
-            __syncthreads();
-          }
-          if (!__syncthreads_or(rotated)) break;
-        }
-        // row norms, then each row's place in decreasing order (ties: smaller index first)
-        for (int j = tid; j < nr; j += NT) {
-          T s = 0;
-          for (int e = 0; e < nk; ++e) s += Jr[j * N2 + e] * Jr[j * N2 + e];
-          vec[j] = j < rank ? s : T(-1);
-        }
-        __syncthreads();
-        for (int j = tid; j < rank; j += NT) {
-          int place = 0;
-          for (int i = 0; i < rank; ++i) place += (vec[i] > vec[j] || (vec[i] == vec[j] && i < j));
-          if (place < CHI) ord[place] = j;
-        }
-        __syncthreads();
-        for (int o = tid; o < CHI * nk; o += NT) {
-          const int kk = o / nk, a = o % nk;
-          sV[kk * LDH + a] = Jr[ord[kk] * N2 + a];
-        }
-        kept = CHI;
-      } else if (h_in_v) {
-        // H occupies the V buffer: the rows of J pass through registers
-        constexpr int PER = (CHI * S::HS + NT - 1) / NT;
-        T tmp[PER];
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int o = tid + u * NT;
-          if (o < kept * nk) tmp[u] = H[(o % nk) * ldh + perm[o / nk]];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-          const int o = tid + u * NT;
-          if (o < kept * nk) sV[(o / nk) * LDH + o % nk] = tmp[u];
-        }
-      } else {
-        for (int o = tid; o < kept * nk; o += NT) {
-          const int kk = o / nk, a = o % nk;
-          sV[kk * LDH + a] = H[a * ldh + perm[kk]];
-        }
-      }
-      __syncthreads();
-      // ---- Gram-Schmidt on the kept rows, twice (one wavefront, entries lane and lane + 64) ----
-      if (wv == 0) {
-        const int a0 = lane, a1 = lane + 64;
-        const bool v0 = a0 < nk, v1 = a1 < nk;
-        for (int j = 0; j < kept; ++j) {
-          T x0 = v0 ? sV[j * LDH + a0] : T(0), x1 = v1 ? sV[j * LDH + a1] : T(0);
-          const T n2 = wave_sum(x0 * x0 + x1 * x1);
-          // classical Gram-Schmidt, twice: the projections on the earlier rows are independent
-          // reductions, taken four at a time
-          for (int pass = 0; pass < 2; ++pass)
-            for (int i0 = 0; i0 < j; i0 += 4) {
-              T u0[4], u1[4], d[4];
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                const int i = i0 + u < j ? i0 + u : j - 1;
-                u0[u] = (v0 && i0 + u < j) ? sV[i * LDH + a0] : T(0);
-                u1[u] = (v1 && i0 + u < j) ? sV[i * LDH + a1] : T(0);
-              }
-#pragma unroll
-              for (int u = 0; u < 4; ++u) d[u] = wave_sum(x0 * u0[u] + x1 * u1[u]);
-#pragma unroll
-              for (int u = 0; u < 4; ++u) {
-                x0 -= d[u] * u0[u];
-                x1 -= d[u] * u1[u];
-              }
-            }
-          const T r2 = wave_sum(x0 * x0 + x1 * x1);
-          const T s = (n2 > T(0) && r2 > T(Tol::eta) * n2) ? T(1) / sqrt(r2) : T(0);
-          if (v0) sV[j * LDH + a0] = x0 * s;
-          if (v1) sV[j * LDH + a1] = x1 * s;
-        }
-      }
-      __syncthreads();
+      const int kept = factor_rows(nk, [&](T* H, int ldh) {
+        big_gemm<T>(
+            nk, nk, nz, [&](int i, int kk) { return (i < nk && kk < nz) ? Zs[kk * N2 + i] : T(0); },
+            [&](int kk, int j) { return (kk < nz && j < nk) ? Wz[kk * N2 + j] : T(0); },
+            [&](int i, int j, T v) { H[i * ldh + j] = v; });
+      });
       // site c of E_{r-1}: A'[x][ka][be] = V[ka][x k + be]
       write_site(Aout + size_t(c) * site, [&](int x, int ka, int be) {
         return (ka < kept && be < k) ? sV[ka * LDH + x * k + be] : T(0);
@@ -590,6 +608,113 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
         bdout[L] = 1;
       }
     }
+    } else {
+    // ------------------------- zip-up, left to right (alternate rows) -------------------------
+    // The carried factor C (rows kappa < k of the new left bond, columns (a, al) of the left bond
+    // of the operator-applied site) is kept transposed in Xs: Ct[(a l + al) CHI + kappa].  At
+    // site c: T_c[x k + kappa][b m + al'] = wv(x,b) sum_a wh(a,b) (C^(a) A_c[b])[kappa][al'];
+    // its leading left singular directions (H = T T^T, factor_rows) become site c of E_{r-1}
+    // (A'[x][kappa][kappa'] = V[kappa'][x k + kappa]) and C_c = V T_c is carried right.  The last
+    // site sums b and takes the norm.
+    if (tid == 0) Xs[0] = T(1);                        // C_{-1} = [1]: k = 1, no a
+    __syncthreads();
+    for (int c = 0; c <= L - 1; ++c) {
+      const int l = bdin[c], m = bdin[c + 1], k = bdout[c];
+      const bool fv = vbit(c);
+      const bool fh = c > 0 ? hbit(c - 1) : false;
+      stage(Ain + size_t(c) * site, l, m);
+      __syncthreads();
+      const T* Ct = Xs + size_t(xb) * N2 * CHI;
+      {
+        using MT = MfmaTile<T>;
+        const int i16 = lane & 15, q = lane >> 4;
+        const int TM = (k + 15) >> 4, TN = (m + 15) >> 4;
+        for (int t = wv; t < TM * TN; t += BIG_NW) {
+          const int ti = t / TN, tj = t % TN;
+          typename MT::v4 y0 = {T(0), T(0), T(0), T(0)}, y1 = y0;
+          for (int k0 = 0; k0 < l; k0 += 16) {
+            T a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int ka = ti * 16 + i16, al = k0 + 4 * u + q, j = tj * 16 + i16;
+              const bool ok_a = ka < k && al < l, ok_b = al < l && j < m;
+              const T c0 = ok_a ? Ct[al * CHI + ka] : T(0);                       // a = 0
+              const T c1 = (ok_a && c > 0) ? Ct[(l + al) * CHI + ka] : T(0);      // a = 1
+              a0[u] = c > 0 ? w(fh, 0, 0) * c0 + w(fh, 1, 0) * c1 : c0;          // P_0
+              a1[u] = c > 0 ? w(fh, 0, 1) * c0 + w(fh, 1, 1) * c1 : c0;          // P_1
+              b0[u] = ok_b ? sA[(0 * CHI + al) * LDA + j] : T(0);
+              b1[u] = ok_b ? sA[(1 * CHI + al) * LDA + j] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              y0 = MT::mac(a0[u], b0[u], y0);
+              y1 = MT::mac(a1[u], b1[u], y1);
+            }
+          }
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int ka = ti * 16 + MT::row(q, rr), ap = tj * 16 + i16;
+            if (ka < k && ap < m)
+              for (int x = 0; x < 2; ++x) {
+                Zs[(x * k + ka) * N2 + ap] = w(fv, x, 0) * y0[rr];
+                Zs[(x * k + ka) * N2 + m + ap] = w(fv, x, 1) * y1[rr];
+              }
+          }
+        }
+      }
+      __syncthreads();
+      const int nr = 2 * k, nc = 2 * m;
+      if (c == L - 1) {
+        // last site: b summed (m = 1); its norm is divided out
+        T part = 0;
+        for (int o = tid; o < nr; o += NT) {
+          const T z = Zs[o * N2 + 0] + Zs[o * N2 + 1];
+          vec[o] = z;
+          part += z * z;
+        }
+        const T nrm = sqrt(block_sum<NT>(part, red));
+        write_site(Aout + size_t(c) * site, [&](int x, int ka, int be) {
+          return (be == 0 && ka < k && nrm > T(0)) ? vec[x * k + ka] / nrm : T(0);
+        });
+        lambda += double(texp) * 0.69314718055994530942 + log(double(nrm));
+        if (tid == 0) {
+          lognorm[r - 1] = lambda;
+          bdout[0] = 1;
+          bdout[L] = 1;
+        }
+        break;
+      }
+      const int kept = factor_rows(nr, [&](T* H, int ldh) {
+        big_gemm<T>(
+            nr, nr, nc, [&](int i, int kk) { return (i < nr && kk < nc) ? Zs[i * N2 + kk] : T(0); },
+            [&](int kk, int j) { return (kk < nc && j < nr) ? Zs[j * N2 + kk] : T(0); },
+            [&](int i, int j, T v) { H[i * ldh + j] = v; });
+      });
+      // site c of E_{r-1}: A'[x][ka][ka'] = V[ka'][x k + ka]
+      write_site(Aout + size_t(c) * site, [&](int x, int ka, int kp) {
+        return (ka < k && kp < kept) ? sV[kp * LDH + x * k + ka] : T(0);
+      });
+      if (tid == 0) bdout[c + 1] = (unsigned char)kept;
+      // C_c = V T_c (kept x nc), kept transposed, rescaled by 2^-e
+      T* Cn = Xs + size_t(xb ^ 1) * N2 * CHI;
+      T mx = 0;
+      big_gemm<T>(
+          nc, kept, nr, [&](int i, int kk) { return (i < nc && kk < nr) ? Zs[kk * N2 + i] : T(0); },
+          [&](int kk, int j) { return (kk < nr && j < kept) ? sV[j * LDH + kk] : T(0); },
+          [&](int i, int j, T v) {
+            Cn[i * CHI + j] = v;
+            mx = fmax(mx, fabs(v));
+          });
+      const int e = pow2_exponent(block_absmax(mx));
+      for (int o = tid; o < nc * kept; o += NT) {
+        const int i = o / kept, j = o % kept;
+        Cn[i * CHI + j] = T(ldexp(Cn[i * CHI + j], -e));
+      }
+      texp += e;
+      xb ^= 1;
+      __syncthreads();
+    }
+    }
     __syncthreads();
     if (R.bonds != nullptr)
       for (int c = tid; c <= L; c += NT) R.bonds[size_t(r - 1) * (L + 1) + c] = bdout[c];
@@ -640,7 +765,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
   }
 }
 
-template <typename T, typename E, int CHI>
+template <typename T, typename E, int CHI, bool ZIP>
 hipError_t launch_env_build_big(const DevReal* d_reals, int n, double* d_lnZ, hipStream_t stream) {
   using S = BigSmem<T, CHI>;
   static_assert(S::bytes <= 160 * 1024, "LDS of one workgroup");
@@ -652,11 +777,11 @@ hipError_t launch_env_build_big(const DevReal* d_reals, int n, double* d_lnZ, hi
   if (err != hipSuccess) return err;
   if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
   std::call_once(once[dev], [dev] {
-    attr[dev] = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_big_kernel<T, E, CHI>),
+    attr[dev] = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_big_kernel<T, E, CHI, ZIP>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(S::bytes));
   });
   if (attr[dev] != hipSuccess) return attr[dev];
-  hipLaunchKernelGGL((env_build_big_kernel<T, E, CHI>), dim3(n), dim3(BIG_NT), S::bytes, stream,
+  hipLaunchKernelGGL((env_build_big_kernel<T, E, CHI, ZIP>), dim3(n), dim3(BIG_NT), S::bytes, stream,
                      d_reals, d_lnZ);
   return hipGetLastError();
 }
@@ -666,12 +791,16 @@ int env_build_big_ok(tnmc_precision prec, int chi) {
          (chi == 8 || chi == 16 || chi == 32 || chi == 48 || chi == 64);
 }
 
-hipError_t env_build_big(tnmc_precision prec, int chi, const DevReal* d_reals, int n,
+hipError_t env_build_big(tnmc_precision prec, int chi, bool zipup, const DevReal* d_reals, int n,
                          double* d_lnZ, hipStream_t stream) {
-#define TNMC_BIG_CASE(C)                                                                  \
-  case C:                                                                                 \
-    return prec == TNMC_BF16 ? launch_env_build_big<float, bf16_t, C>(d_reals, n, d_lnZ, stream) \
-                             : launch_env_build_big<double, float, C>(d_reals, n, d_lnZ, stream);
+#define TNMC_BIG_CASE(C)                                                                       \
+  case C:                                                                                      \
+    if (zipup)                                                                                 \
+      return prec == TNMC_BF16                                                                 \
+                 ? launch_env_build_big<float, bf16_t, C, true>(d_reals, n, d_lnZ, stream)     \
+                 : launch_env_build_big<double, float, C, true>(d_reals, n, d_lnZ, stream);    \
+    return prec == TNMC_BF16 ? launch_env_build_big<float, bf16_t, C, false>(d_reals, n, d_lnZ, stream) \
+                             : launch_env_build_big<double, float, C, false>(d_reals, n, d_lnZ, stream);
   if (prec != TNMC_BF16 && prec != TNMC_FP32) return hipErrorInvalidValue;
   switch (chi) {
     TNMC_BIG_CASE(8)

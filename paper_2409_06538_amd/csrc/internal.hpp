@@ -33,7 +33,7 @@ size_t env_build_scratch_bytes(tnmc_precision prec, int chi, int L);
 // The Gram form with global scratch (envbuild_big.hip): the build of chi = 64 (FP32 and BF16
 // environments), and a selectable form at chi = 8 .. 48
 int env_build_big_ok(tnmc_precision prec, int chi);
-hipError_t env_build_big(tnmc_precision prec, int chi, const DevReal* d_reals, int n,
+hipError_t env_build_big(tnmc_precision prec, int chi, bool zipup, const DevReal* d_reals, int n,
                          double* d_lnZ, hipStream_t stream);
 size_t env_build_big_scratch_bytes(tnmc_precision prec, int chi, int L);
 

@@ -146,3 +146,25 @@ def test_tuning_table_host_side(lib):
     assert lib.tnmc_tune_set(8, binding.FP32, 64, 64, 1000, 2) == -1   # one thread per proposal
     assert lib.tnmc_tune_set(32, binding.FP32, 64, 64, 1000, 0) == 0   # erase
     assert lib.tnmc_tune_get(32, binding.FP32, 64, 64, 1000) == 8
+
+
+def test_build_forms_host_side(lib):
+    """The build forms of the header match the binding; a form that does not exist, or one not
+    built for the precision, is TNMC_EINVAL before anything is enqueued."""
+    from paper_2409_06538_amd import binding
+    text = open(HEADER).read()
+    forms = dict(re.findall(r"#define (TNMC_FORM_[A-Z0-9_]+) (\d+)", text))
+    assert int(forms["TNMC_FORM_DEFAULT"]) == binding.FORM_DEFAULT
+    assert int(forms["TNMC_FORM_GRAM_L2"]) == binding.FORM_GRAM_L2
+    assert int(forms["TNMC_FORM_ZIPUP"]) == binding.FORM_ZIPUP
+    tab = (binding.Instance * 1)()
+    tab[0].L, tab[0].beta, tab[0].id = 16, 0.9, 0
+    tab[0].d_Jh = tab[0].d_Jv = tab[0].d_env = tab[0].d_lognorm = 1 << 20
+    fake = ctypes.c_void_p(1 << 20)
+    big = 1 << 40
+    for form, prec, chi in ((3, binding.FP32, 16), (-1, binding.FP32, 16),
+                            (binding.FORM_ZIPUP, binding.FP64, 16),
+                            (binding.FORM_GRAM_L2, binding.FP64, 16),
+                            (binding.FORM_ZIPUP, binding.FP32, 4)):
+        assert lib.tnmc_build_env_form(tab, 1, chi, prec, form, fake, big, None, None) == -1, \
+            (form, prec, chi)

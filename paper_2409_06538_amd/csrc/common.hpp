@@ -102,6 +102,18 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Unsigned maximum over aligned groups of G lanes (G = 16 or 32); every lane of a group gets it.
+template <int G>
+__device__ __forceinline__ uint32_t group_max_u32(uint32_t v) {
+  auto mx = [](uint32_t a, uint32_t b) { return a > b ? a : b; };
+  v = mx(v, uint32_t(dpp<0xB1>(int(v))));
+  v = mx(v, uint32_t(dpp<0x4E>(int(v))));
+  v = mx(v, uint32_t(dpp<0x141>(int(v))));
+  v = mx(v, uint32_t(dpp<0x140>(int(v))));
+  if (G >= 32) v = mx(v, uint32_t(__shfl_xor(int(v), 16)));
+  return v;
+}
+
 // Sum / max over a whole wavefront (all 64 lanes active); every lane gets the result.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

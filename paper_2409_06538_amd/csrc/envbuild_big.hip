@@ -228,6 +228,75 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
   // factor in sV (nk entries each); returns how many.  Pivoted Cholesky stopped at the
   // numerical rank, one-sided Jacobi and the CHI largest directions when the rank exceeds CHI,
   // Gram-Schmidt twice.  Shared by both sweep directions.
+  // The small-H factorisation behind factor_rows (run by wavefront 0): rank and the kept rows
+  // of V (orthonormal, in sV) from H (nk x nk, ld ldh, in LDS); the rank goes to imisc[0].
+  auto small_factor = [&](auto gsize, const T* H, const int ldh, const int nk) {
+    constexpr int G = decltype(gsize)::value;
+    const int a = lane & (G - 1);
+    const bool va = a < nk;
+    T Lr[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) Lr[u] = T(0);
+    T d = va ? H[a * ldh + a] : T(0);
+    const T tol2 = T(Tol::rank2) * group_sum<G>(fmax(d, T(0)));
+    bool pk = !va;
+    int rk = nk;
+    for (int j = 0; j < nk; ++j) {
+      const uint32_t key =
+          pk ? 0u : ((__float_as_uint(float(fmax(d, T(0)))) & ~127u) | uint32_t(127 - a));
+      const uint32_t bk = group_max_u32<G>(key);
+      const int piv = 127 - int(readlane_i(int(bk), 0) & 127);
+      const T best = readlane_v(d, piv);
+      if (readlane_i(int(bk), 0) == 0 || !(best > tol2)) {
+        rk = j;
+        break;
+      }
+      const T h = va ? H[a * ldh + piv] : T(0);
+      const T inv = T(1) / sqrt(best);
+      T dot = 0;   // entries j.. of both rows are still zero
+#pragma unroll
+      for (int i = 0; i < G; ++i) dot += Lr[i] * readlane_v(Lr[i], piv);
+      const T l = (a == piv) ? best * inv : (!pk ? (h - dot) * inv : T(0));
+#pragma unroll
+      for (int i = 0; i < G; ++i) Lr[i] = (i == j) ? l : Lr[i];
+      if (!pk && a != piv) d -= l * l;
+      if (a == piv) pk = true;
+    }
+    // rows J[j][a] = Lr[j]: classical Gram-Schmidt twice; the projections of a pass are taken
+    // from the same vector (independent sums, four per group)
+    for (int j = 0; j < rk; ++j) {
+      T x = 0;
+#pragma unroll
+      for (int i = 0; i < G; ++i) x = (i == j) ? Lr[i] : x;
+      const T n2 = group_sum<G>(x * x);
+      for (int pass = 0; pass < 2; ++pass) {
+        T dd[G];
+#pragma unroll
+        for (int g = 0; g < G; g += 4) {
+          if (g < j) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dd[g + u] = group_sum<G>(g + u < j ? x * Lr[g + u] : T(0));
+          } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) dd[g + u] = T(0);
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) x -= dd[i] * Lr[i];   // dd[i] = 0 for i >= j
+      }
+      const T r2 = group_sum<G>(x * x);
+      const T sc = (n2 > T(0) && r2 > T(Tol::eta) * n2) ? T(1) / sqrt(r2) : T(0);
+      x *= sc;
+#pragma unroll
+      for (int i = 0; i < G; ++i) Lr[i] = (i == j) ? x : Lr[i];
+    }
+    // H is dead (it may share the V buffer): this wavefront's reads of it are done
+    if (lane < G && va)
+#pragma unroll
+      for (int i = 0; i < G; ++i)
+        if (i < rk) sV[i * LDH + a] = Lr[i];
+    if (lane == 0) imisc[0] = rk;
+  };
   auto factor_rows = [&](const int nk, auto fill_h) -> int {
     // H in LDS (its own buffer, or the V buffer when it is small enough), else global memory
     const bool h_in_v = !S::H_IN_LDS && nk <= S::HS;
@@ -236,6 +305,23 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
     const bool h_global = !S::H_IN_LDS && !h_in_v;
     fill_h(H, ldh);
     __syncthreads();
+
+    // ---- small H (nk <= G, G = 16 or 32, and nk <= CHI, so the rank cannot exceed CHI): one
+    // wavefront holds the problem G lanes wide, replicated 64 / G times, with row `a` of the
+    // Cholesky factor in registers of lane a from the factorisation through Gram-Schmidt; sums
+    // and the pivot search are butterflies inside each group of G lanes (every lane gets the
+    // result), the pivot row's entries come by readlane, and only H and the final rows of V
+    // touch LDS.  Same steps and tolerances as the general path below. ----
+    if (nk <= CHI && nk <= (sizeof(T) == 4 ? 32 : 16)) {
+      if (wv == 0) {
+        if (nk <= 16)
+          small_factor(std::integral_constant<int, 16>{}, H, ldh, nk);
+        else
+          small_factor(std::integral_constant<int, 32>{}, H, ldh, nk);
+      }
+      __syncthreads();
+      return int(imisc[0]);
+    }
 
     // ---- pivoted Cholesky of H in place (one wavefront, rows lane and lane + 64) ----
     // Left-looking: with p_j the row of largest remaining diagonal d,

@@ -138,12 +138,16 @@ def add_rooflines(res, args, Ls):
     per pass, 2 passes x 2 chi^2 L^2 elements, and every proposal costs 8 chi^2 L^2 flops; the
     kernel is quoted against the matrix-core peak of its arithmetic when that intensity is past
     the ridge point, else against HBM."""
-    chi, K, build_ms, prop_ms = res["chi"], res["K"], res["build_ms"], res["propose_ms"]
+    chi, K, prop_ms = res["chi"], res["K"], res["propose_ms"]
+    # one build launch may cover the batches of several stages (grouped steps)
+    units = res.get("build_units_per_launch", 1)
+    build_ms = res.get("build_launch_ms", res["build_ms"])
     prec = args.precision
     bar = build_arithmetic(prec, chi)
-    flops = sum(build_flops_per_site(chi) * (L - 1) * L for L in Ls)
+    flops = units * sum(build_flops_per_site(chi) * (L - 1) * L for L in Ls)
     carry = 8 if bar == "f64" else 4
-    bbytes = sum(build_bytes_per_site(chi, ENV_BYTES[prec], carry) * (L - 1) * L for L in Ls)
+    bbytes = units * sum(build_bytes_per_site(chi, ENV_BYTES[prec], carry) * (L - 1) * L
+                         for L in Ls)
     peak = PEAK_TFLOPS[bar]
     achieved = flops / (build_ms * 1e-3) / 1e12
     rec = counted(args.workload, prec, "env_build")
@@ -152,7 +156,8 @@ def add_rooflines(res, args, Ls):
                        "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                        "frac": achieved / peak, "traffic": traffic,
                        "traffic_over_algorithmic": None if traffic is None else traffic / bbytes,
-                       "launch_ms": build_ms, "algorithmic_flops_per_launch": flops,
+                       "launch_ms": build_ms, "batches_per_launch": units,
+                       "algorithmic_flops_per_launch": flops,
                        "algorithmic_bytes_per_launch": bbytes,
                        "mfma_counters": mfma_counters(rec, build_ms, peak)}
     sar = sampler_arithmetic(prec)
@@ -269,19 +274,15 @@ def error_vs_oracle(envs, args, w, Ls, seeds):
 
 
 def narrow_fraction(batch):
-    """Fraction of the environment sites whose entries all lie in the leading 16 x 16 block of
-    both matrices (the proposal kernel then stores one 16-row tile of V per spin value)."""
-    import torch
-    tot = wide = 0
+    """Fraction of the environment sites whose both bonds are at most 16 by the bond table the
+    build wrote (their entries all lie in the leading 16 x 16 block of both matrices: the
+    proposal kernel then stores one 16-row tile of V per spin value)."""
+    tot = narrow = 0
     for i, L in enumerate(batch.Ls):
-        e = batch.env_tensor(i)
-        if batch.chi <= 16:
-            tot += L * L
-            continue
-        w = ((e[..., 16:, :] != 0).flatten(2).any(-1) | (e[..., :, 16:] != 0).flatten(2).any(-1))
+        bt = batch.bond_table(i)
         tot += L * L
-        wide += int(w.sum().item())
-    return 1.0 - wide / max(1, tot)
+        narrow += int(((bt[:, :L] <= 16) & (bt[:, 1:] <= 16)).sum().item())
+    return narrow / max(1, tot)
 
 
 def disorder_strengths(w):
@@ -440,6 +441,132 @@ def cu_masked_stream(reserve):
     ext = torch.cuda.ExternalStream(stream.value)
     ext.destroy = lambda: hip.hipStreamDestroy(stream)    # the library owns it, not torch
     return ext, [hex(v) for v in vals]
+
+
+def run_gpu_grouped(args):
+    """Consecutive steps overlapped in groups: the batches of `group` consecutive pipeline
+    stages are built by one launch (one workgroup per realization, group x n of them) on one
+    stream, while the proposals and accepts of the previous group run on a second stream; two
+    groups of batches alternate, so a build never overwrites environments that proposals still
+    read.  For workloads with few realizations (rbim1024: 2), whose build occupies a few CUs for
+    seconds per launch while the proposals leave most of the chip free."""
+    import torch
+    from paper_2409_06538_amd import binding
+    import synth
+
+    w = synth.WORKLOADS[args.workload]
+    Ls, seeds = workload_sizes(w)
+    ps = disorder_strengths(w)
+    chi, K = w["chi"], args.proposals or w["proposals"]
+    n = len(seeds)
+    D = args.group_steps
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    s_build, s_prop = torch.cuda.Stream(), torch.cuda.Stream()
+    groups = []
+    for _ in range(2):
+        members = []
+        for _ in range(D):
+            b = binding.Batch(Ls, [binding.nishimori_beta(ps[0])] * n, seeds, chi, args.precision,
+                              K=K, device=dev)
+            out = (torch.empty(b.spins_shape(K), dtype=torch.int64, device=dev),
+                   torch.empty((n, K), dtype=torch.float64, device=dev),
+                   torch.empty((n, K), dtype=torch.int32, device=dev))
+            members.append({"b": b, "out": out, "p": None,
+                            "accum": torch.zeros((n, binding.OBS_COUNT), dtype=torch.float64,
+                                                 device=dev)})
+        ws = torch.empty(binding.group_workspace_bytes([m["b"] for m in members]),
+                         dtype=torch.uint8, device=dev)
+        groups.append({"members": members, "ws": ws, "done": None})
+    chains = [groups[0]["members"][0]["b"].new_chains(1) for _ in ps]
+    stage = [0] * len(ps)
+    L2 = torch.tensor([L * L for L in Ls], dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    def run(steps):
+        """`steps` passes over every p; stages (step, p) in order, D per build launch."""
+        sums, ev = [], []
+        n_stage = steps * len(ps)
+        for g0 in range(0, n_stage, D):
+            grp = groups[(g0 // D) % 2]
+            us = list(range(g0, min(g0 + D, n_stage)))
+            mem = grp["members"][:len(us)]
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            with torch.cuda.stream(s_build):
+                if grp["done"] is not None:
+                    s_build.wait_event(grp["done"])   # proposals of the group before still read
+                for u, m in zip(us, mem):
+                    m["p"] = ps[u % len(ps)]
+                    m["b"].set_betas([binding.nishimori_beta(m["p"])] * n)
+                    m["b"].make_couplings(seeds, m["p"])
+                e[0].record(s_build)
+                binding.build_env_group([m["b"] for m in mem], grp["ws"])
+                e[1].record(s_build)
+            with torch.cuda.stream(s_prop):
+                s_prop.wait_event(e[1])
+                for u, m in zip(us, mem):
+                    jp = u % len(ps)
+                    ep = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+                    ep[0].record(s_prop)
+                    first = stage[jp] * K
+                    stage[jp] += 1
+                    m["b"].propose(K, args.seed, first_proposal=first, out=m["out"])
+                    ep[1].record(s_prop)
+                    ch = chains[jp]
+                    fresh = (ch["init"] == 0).sum(dtype=torch.float64)
+                    acc, _ = m["b"].accept(m["out"], ch, seed=args.seed, first_step=first,
+                                           accum=m["accum"])
+                    per_real = acc.sum(dim=1, dtype=torch.float64)
+                    sums.append(torch.stack([per_real.sum(), (per_real * L2).sum(), n * K - fresh]))
+                    ev.append(("propose", ep))
+                done = torch.cuda.Event()
+                done.record(s_prop)
+                grp["done"] = done
+            ev.append(("build", e, len(us)))
+        return sums, ev
+
+    run(max(1, args.warmup))
+    torch.cuda.synchronize()
+    progress("warm-up stages done")
+    tune = autotune(args, groups[0]["members"][0]["b"], K)
+    t0 = time.perf_counter()
+    sums, ev = run(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    progress(f"timed steps done ({t1 - t0:.1f} s)")
+    per_stage = torch.stack(sums).tolist()
+    accepted = int(sum(a for a, _, _ in per_stage))
+    updates = sum(x for _, x, _ in per_stage)
+    attempted = int(sum(t for _, _, t in per_stage))
+    builds = [x for x in ev if x[0] == "build"]
+    props = [x for x in ev if x[0] == "propose"]
+    build_launch_ms = sum(x[1][0].elapsed_time(x[1][1]) for x in builds) / len(builds)
+    units = sum(x[2] for x in builds) / len(builds)
+    build_ms = build_launch_ms / units     # per batch
+    prop_ms = sum(x[1][0].elapsed_time(x[1][1]) for x in props) / len(props)
+    wall = t1 - t0
+    last = groups[((len(range(0, args.steps * len(ps), D)) - 1)) % 2]["members"]
+    nfrac = narrow_fraction(last[0]["b"])
+    envs = [(m["b"], m["p"]) for g in groups for m in g["members"] if m["p"] is not None]
+    err = error_vs_oracle(envs, args, w, Ls, seeds)
+    del envs, groups, sums, ev, last
+    torch.cuda.synchronize()
+    res = {"Ls": sorted(set(Ls)), "chi": chi, "n": n, "K": K, "p": ps[0] if len(ps) == 1 else ps,
+           "wall_s": wall, "ms_per_step": 1e3 * wall / args.steps,
+           "value": updates / wall, "accepted": accepted, "attempted": attempted,
+           "acceptance": accepted / attempted, "build_ms": build_ms,
+           "build_launch_ms": build_launch_ms, "build_units_per_launch": units,
+           "propose_ms": prop_ms,
+           "graph": False, "pipelined": True, "group_steps": D, "builds_in_flight": D,
+           "narrow_fraction": nfrac, "propose_cu_mask": None, "error_vs_oracle": err,
+           "autotune": tune}
+    if len(ps) > 1:
+        res["acceptance_per_p"] = {
+            str(p): sum(per_stage[u][0] for u in range(j, len(per_stage), len(ps)))
+            / sum(per_stage[u][2] for u in range(j, len(per_stage), len(ps)))
+            for j, p in enumerate(ps)}
+        res["batches_per_step"] = len(ps)
+    return add_rooflines(res, args, Ls)
 
 
 def run_gpu_pipelined(args):
@@ -742,8 +869,10 @@ def calib_copy(mib):
     del src, dst
 
 
+# stages built per launch in the overlapped mode (1: one build per stage, several in flight)
+DEFAULT_GROUP_STEPS = {"rbim1024": 3}
 DEFAULT_STEPS = {"rbim16": 50, "rbim64": 50, "mixed": 4, "rbim256": 2, "rbim256_chi32": 2,
-                 "rbim1024": 2}
+                 "rbim1024": 6}
 
 SWEEP_LS = (16, 32, 64, 128, 256)
 SWEEP_CHIS = (8, 16, 32, 48)
@@ -888,7 +1017,8 @@ def main():
     ap.add_argument("--steps", type=int, default=0,
                     help="timed steps (default: 2 for rbim256, whose steps take seconds; 50 for "
                          "rbim64 and rbim16, whose steps take milliseconds, so that the pipeline "
-                         "fill and drain inside the timed region are amortised; 4 for mixed)")
+                         "fill and drain inside the timed region are amortised; 4 for mixed; 6 "
+                         "(two build groups) for rbim1024)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16"],
@@ -906,6 +1036,11 @@ def main():
     ap.add_argument("--reserve-cus", type=int, default=1, choices=[0, 1],
                     help="overlapped steps: keep 8 CUs of every XCD per build in flight free of "
                          "proposal work (0: no CU mask)")
+    ap.add_argument("--group-steps", type=int, default=0,
+                    help="overlapped steps: build the batches of this many consecutive stages in "
+                         "one launch while the proposals of the previous group run (default: 3 "
+                         "for rbim1024, whose two realizations leave the chip idle during a "
+                         "build; 1 elsewhere: one build per stage with --builds-in-flight)")
     ap.add_argument("--builds-in-flight", type=int, default=2, choices=[1, 2],
                     help="overlapped steps: environment builds of later steps running at once")
     ap.add_argument("--sweep", default=None,
@@ -948,7 +1083,10 @@ def main():
         cpu_all = run_cpu_all_cores(wl["L"], wl["chi"], p_cpu, K_full, args.seed)
         progress("oracle on all host cores done")
     serial = args.serial or args.graph
-    res = run_gpu(args) if serial else run_gpu_pipelined(args)
+    if not args.group_steps:
+        args.group_steps = DEFAULT_GROUP_STEPS.get(args.workload, 1)
+    res = run_gpu(args) if serial else (run_gpu_grouped(args) if args.group_steps > 1
+                                        else run_gpu_pipelined(args))
     if not serial and not args.no_serial:
         # the same steps one after the other on one stream, for comparison
         import copy
@@ -1010,13 +1148,18 @@ def main():
                                + (", one HIP graph per step (its replays repeat one batch of "
                                   "proposals from restarted chains)" if res["graph"] else
                                   "; every step draws new proposals and continues the chains")
-                               + (f", consecutive steps overlapped (builds of the next "
-                                  f"{res.get('builds_in_flight')} stage(s) during the proposals "
-                                  f"of the current one)" if res.get("pipelined") else ""),
+                               + ((f", consecutive steps overlapped (the batches of "
+                                   f"{res['group_steps']} consecutive steps built by one launch "
+                                   f"while the proposals of the previous group run)"
+                                   if res.get("group_steps") else
+                                   f", consecutive steps overlapped (builds of the next "
+                                   f"{res.get('builds_in_flight')} stage(s) during the proposals "
+                                   f"of the current one)") if res.get("pipelined") else ""),
                    "L": L0 if uniform else res["Ls"], "chi": res["chi"], "realizations": res["n"],
                    "proposals": res["K"], "p": res["p"], "precision": args.precision,
                    "graph": res["graph"], "pipelined": bool(res.get("pipelined")),
                    "builds_in_flight": res.get("builds_in_flight"),
+                   "group_steps": res.get("group_steps"),
                    "propose_cu_mask": res.get("propose_cu_mask")},
         "acceptance": res["acceptance"],
         "acceptance_per_p": res.get("acceptance_per_p"),

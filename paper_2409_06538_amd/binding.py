@@ -119,6 +119,39 @@ def nishimori_beta(p):
     return 0.5 * math.log((1.0 - p) / p)
 
 
+def group_table(batches):
+    """One instance table over the realizations of several batches (same chi and precision),
+    in order: the device buffers stay the batches' own."""
+    tab = (Instance * sum(b.n for b in batches))()
+    k = 0
+    for b in batches:
+        for i in range(b.n):
+            tab[k] = b.table[i]
+            k += 1
+    return tab
+
+
+def group_workspace_bytes(batches):
+    """Workspace for tnmc_build_env over the realizations of several batches in one call."""
+    b0 = batches[0]
+    tab = group_table(batches)
+    return int(load().tnmc_workspace_bytes(tab, len(tab), b0.chi, 1, b0.prec))
+
+
+def build_env_group(batches, workspace):
+    """tnmc_build_env over the realizations of several batches in one launch (each batch's
+    environments, log-norms, bond tables and status words are written in place); `workspace` is
+    a uint8 tensor of at least group_workspace_bytes(batches)."""
+    b0 = batches[0]
+    if any(b.chi != b0.chi or b.prec != b0.prec for b in batches):
+        raise TNMCError("build_env_group: batches differ in chi or precision")
+    tab = group_table(batches)
+    _check(load().tnmc_build_env(tab, len(tab), b0.chi, b0.prec,
+                                 ctypes.c_void_p(workspace.data_ptr()),
+                                 ctypes.c_size_t(workspace.numel()), None, _stream()),
+           "tnmc_build_env")
+
+
 class Batch:
     """Device buffers for a batch of realizations plus the host instance table."""
 

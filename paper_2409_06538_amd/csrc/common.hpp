@@ -102,6 +102,30 @@ __device__ __forceinline__ T group_sum(T v) {
   return v;
 }
 
+// Workgroup barrier that orders LDS accesses only: global loads and stores stay in flight across
+// it (their consumers wait for them through the registers they fill).  For kernels whose threads
+// exchange data through LDS alone.
+__device__ __forceinline__ void lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// lds_sync() that also returns the OR of `pred` over the workgroup (NW wavefronts).  `flags`
+// holds 2 NW ints of LDS; `par` alternates between calls, so that a wavefront running ahead to
+// the next call cannot overwrite flags that a slower one still reads.
+template <int NW>
+__device__ __forceinline__ bool lds_sync_or(bool pred, int* flags, int& par) {
+  const bool any = __ballot(pred) != 0ull;
+  if ((threadIdx.x & 63) == 0) flags[par * NW + (threadIdx.x >> 6)] = any ? 1 : 0;
+  lds_sync();
+  int r = 0;
+#pragma unroll
+  for (int i = 0; i < NW; ++i) r |= flags[par * NW + i];
+  par ^= 1;
+  return r != 0;
+}
+
 // Unsigned maximum over aligned groups of G lanes (G = 16 or 32); every lane of a group gets it.
 template <int G>
 __device__ __forceinline__ uint32_t group_max_u32(uint32_t v) {

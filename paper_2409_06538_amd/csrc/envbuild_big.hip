@@ -255,7 +255,11 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       const T inv = T(1) / sqrt(best);
       T dot = 0;   // entries j.. of both rows are still zero
 #pragma unroll
-      for (int i = 0; i < G; ++i) dot += Lr[i] * readlane_v(Lr[i], piv);
+      for (int g = 0; g < G; g += 4)
+        if (g < j) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) dot += Lr[g + u] * readlane_v(Lr[g + u], piv);
+        }
       const T l = (a == piv) ? best * inv : (!pk ? (h - dot) * inv : T(0));
 #pragma unroll
       for (int i = 0; i < G; ++i) Lr[i] = (i == j) ? l : Lr[i];
@@ -263,26 +267,29 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       if (a == piv) pk = true;
     }
     // rows J[j][a] = Lr[j]: classical Gram-Schmidt twice; the projections of a pass are taken
-    // from the same vector (independent sums, four per group)
+    // from the same vector.  The 64 / G lane groups hold the same vector, so one group sum
+    // gives 64 / G projections at once, group u taking row g + u.
+    constexpr int P = 64 / G;
+    const int slot = lane / G;
     for (int j = 0; j < rk; ++j) {
       T x = 0;
 #pragma unroll
       for (int i = 0; i < G; ++i) x = (i == j) ? Lr[i] : x;
       const T n2 = group_sum<G>(x * x);
       for (int pass = 0; pass < 2; ++pass) {
-        T dd[G];
+        T acc = 0;
 #pragma unroll
-        for (int g = 0; g < G; g += 4) {
+        for (int g = 0; g < G; g += P) {
           if (g < j) {
+            T ls = Lr[g];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) dd[g + u] = group_sum<G>(g + u < j ? x * Lr[g + u] : T(0));
-          } else {
+            for (int u = 1; u < P; ++u) ls = (slot == u) ? Lr[g + u] : ls;
+            const T dv = group_sum<G>(g + slot < j ? x * ls : T(0));
 #pragma unroll
-            for (int u = 0; u < 4; ++u) dd[g + u] = T(0);
+            for (int u = 0; u < P; ++u) acc += readlane_v(dv, u * G) * Lr[g + u];   // 0 past j
           }
         }
-#pragma unroll
-        for (int i = 0; i < G; ++i) x -= dd[i] * Lr[i];   // dd[i] = 0 for i >= j
+        x -= acc;
       }
       const T r2 = group_sum<G>(x * x);
       const T sc = (n2 > T(0) && r2 > T(Tol::eta) * n2) ? T(1) / sqrt(r2) : T(0);

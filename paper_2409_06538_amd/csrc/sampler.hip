@@ -310,12 +310,6 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   constexpr int SPT = (SITE + MF_NT - 1) / MF_NT;   // site elements loaded per thread
   __shared__ __align__(16) T Bs[2][2 * CHI * LDB];
   __shared__ uint64_t rows[2][MAX_W][MF_PROP];
-  // bond dimensions of the current row's cuts (from the bond table), and the flags of
-  // lds_sync_or: the threads exchange data through LDS only, so the per-site barriers leave the
-  // global traffic (the next site's staging loads, the V store) in flight
-  __shared__ uint8_t brow[MAX_W * 64 + 1];
-  __shared__ int sflags[2 * MF_WAVES];
-  int spar = 0;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
   const int pl = lane & 15, q = lane >> 4;
   const int slot = wv * 16 + pl;
@@ -375,7 +369,8 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   auto load_site = [&](int r, int c) {
     const gmem<E>* src = env + (size_t(r) * L + c) * SITE;
     if (CHI > 16 && bonds != nullptr) {
-      nsite = brow[c] <= 16 && brow[c + 1] <= 16;
+      const size_t bi = size_t(r) * (L + 1) + c;
+      nsite = bonds[bi] <= 16 && bonds[bi + 1] <= 16;
       if (nsite) {
 #pragma unroll
         for (int t = 0; t < NN; ++t) {
@@ -479,11 +474,6 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
     const uint64_t* prow = &rows[pr][0][slot];       // word w at prow[w * MF_PROP]
     uint64_t* crow = &rows[pr ^ 1][0][slot];
 
-    if (CHI > 16 && bonds != nullptr) {
-      for (int e = tid; e <= L; e += MF_NT) brow[e] = bonds[size_t(r) * (L + 1) + e];
-      lds_sync();
-    }
-
     // ---- right sweep: V_c(y) = B_c[y] R_c(y) for c = L-1 .. 0 ----
     T rc[2][RT][4];
 #pragma unroll
@@ -493,7 +483,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
 #pragma unroll
         for (int i = 0; i < 4; ++i) rc[y][t][i] = (t == 0 && M::row(q, i) == 0) ? T(1) : T(0);
     load_site(r, L - 1);
-    int nt = lds_sync_or<MF_WAVES>(store_site(Bs[b], false), sflags, spar) ? RT : 1;
+    int nt = __syncthreads_or(store_site(Bs[b], false)) ? RT : 1;
     for (int c = L - 1; c >= 0; --c) {
       if (c > 0) load_site(r, c - 1);
       bool wide = false;
@@ -545,7 +535,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
             for (int i = 0; i < 4; ++i) rc[y][t][i] = T(ldexp(rc[y][t][i], -e));
         wide = store_site(Bs[b ^ 1], false);
       }
-      const int nt_next = lds_sync_or<MF_WAVES>(wide, sflags, spar) ? RT : 1;
+      const int nt_next = __syncthreads_or(wide) ? RT : 1;
       if (c > 0) {
         b ^= 1;
         nt = nt_next;
@@ -562,7 +552,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
         for (int i = 0; i < 4; ++i) el[y][t][i] = (t == 0 && M::row(q, i) == 0) ? T(1) : T(0);
     b ^= 1;
     load_site(r, 0);
-    nt = lds_sync_or<MF_WAVES>(store_site(Bs[b], true), sflags, spar) ? RT : 1;
+    nt = __syncthreads_or(store_site(Bs[b], true)) ? RT : 1;
     Philox4 blk{};
     int sprev = 0;   // 0 <-> +1, 1 <-> -1 (spin at c-1 of this row)
     uint64_t curw = 0, tword = 0;
@@ -665,7 +655,7 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
         }
       sprev = s;
       const bool wide_next = (c + 1 < L) ? store_site(Bs[b ^ 1], true) : false;
-      const int nt_next = lds_sync_or<MF_WAVES>(wide_next, sflags, spar) ? RT : 1;
+      const int nt_next = __syncthreads_or(wide_next) ? RT : 1;
       if (c + 1 < L) {
         b ^= 1;
         nt = nt_next;

@@ -172,12 +172,14 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
   const T ep = T(exp(R.beta)), em = T(exp(-R.beta));
   gmem<E>* env = as_global(reinterpret_cast<E*>(R.env));
   gmem<double>* lognorm = as_global(R.lognorm);
-  T* ws = reinterpret_cast<T*>(R.ws);
-  T* Gs = ws;                             // L blocks: G_c at Gs + c BLK, row-major, ld N2
-  T* Zs = ws + size_t(L) * BLK;           // Z_c (ld N2); first sweep: P_bb' (3 x CHI x CHI)
-  T* Ws = Zs + BLK;                       // W (ld N2); Y_b; first sweep: Q_bb'; Jacobi rows
-  T* Xs = Ws + BLK;                       // two carried factors, N2 x CHI each
-  T* Hg = Xs + BLK;                       // H in global memory (FP64)
+  // the scratch in the global address space (global_load / global_store, counted by the
+  // vector-memory counter only: FLAT accesses would also hold every LDS wait)
+  gmem<T>* ws = as_global(reinterpret_cast<T*>(R.ws));
+  gmem<T>* Gs = ws;                       // L blocks: G_c at Gs + c BLK, row-major, ld N2
+  gmem<T>* Zs = ws + size_t(L) * BLK;     // Z_c (ld N2); first sweep: P_bb' (3 x CHI x CHI)
+  gmem<T>* Ws = Zs + BLK;                 // W (ld N2); Y_b; first sweep: Q_bb'; Jacobi rows
+  gmem<T>* Xs = Ws + BLK;                 // two carried factors, N2 x CHI each
+  T* Hg = reinterpret_cast<T*>(R.ws) + size_t(L + 3) * BLK;   // H in global memory (FP64)
   const size_t site = size_t(2) * CHI * CHI;
   const size_t rowst = site * L;
 
@@ -384,7 +386,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
     // J row j = column perm[j] of the factor: J[j][a] = H[a][perm[j]]
     if (rank > CHI) {
       // ---- one-sided Jacobi on the rows of J (rank x nk), then the CHI largest ----
-      T* Jr = Ws;   // rows, ld N2 (W is no longer needed)
+      gmem<T>* Jr = Ws;   // rows, ld N2 (W is no longer needed)
       const int nr = rank + (rank & 1);
       for (int o = tid; o < nr * nk; o += NT) {
         const int j = o / nk, a = o % nk;
@@ -527,10 +529,10 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       T kx[2][2];
       for (int b = 0; b < 2; ++b)
         for (int b2 = 0; b2 < 2; ++b2) kx[b][b2] = w(fv, 0, b) * w(fv, 0, b2) + w(fv, 1, b) * w(fv, 1, b2);
-      T* P = Zs;   // P_bb' for (b, b') = (0,0), (0,1), (1,1): CHI x CHI each, ld CHI
+      gmem<T>* P = Zs;   // P_bb' for (b, b') = (0,0), (0,1), (1,1): CHI x CHI each, ld CHI
       if (c > 0) {
         const bool fh = hbit(c - 1);
-        const T* Gp = Gs + size_t(c - 1) * BLK;
+        const gmem<T>* Gp = Gs + size_t(c - 1) * BLK;
         for (int o = tid; o < 3 * l * l; o += NT) {
           const int pb = o / (l * l), al = (o / l) % l, be = o % l;
           const int b = pb == 2 ? 1 : 0, b2 = pb == 0 ? 0 : 1;
@@ -543,10 +545,10 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       }
       __syncthreads();
       // Q_bb' = P_bb' A_c[b'] (l x m)
-      T* Q = Ws;
+      gmem<T>* Q = Ws;
       for (int pb = 0; pb < 3; ++pb) {
         const int b2 = pb == 0 ? 0 : 1;
-        const T* Pp = P + size_t(pb) * CHI * CHI;
+        const gmem<T>* Pp = P + size_t(pb) * CHI * CHI;
         big_gemm<T>(
             l, m, l,
             [&](int i, int k) { return (i < l && k < l) ? (c > 0 ? Pp[i * CHI + k] : T(1)) : T(0); },
@@ -555,11 +557,11 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       }
       __syncthreads();
       // G_c^(b,b') = kx(b,b') A_c[b]^T Q_bb' (m x m); (1,0) is the transpose of (0,1)
-      T* Gc = Gs + size_t(c) * BLK;
+      gmem<T>* Gc = Gs + size_t(c) * BLK;
       T mx = 0;
       for (int pb = 0; pb < 3; ++pb) {
         const int b = pb == 2 ? 1 : 0, b2 = pb == 0 ? 0 : 1;
-        const T* Qp = Q + size_t(pb) * CHI * CHI;
+        const gmem<T>* Qp = Q + size_t(pb) * CHI * CHI;
         const T k = kx[b][b2];
         big_gemm<T>(
             m, m, l,
@@ -592,7 +594,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       const bool fh = hbit(c - 1), fv = vbit(c);
       stage(Ain + size_t(c) * site, l, m);
       __syncthreads();
-      const T* X = Xs + size_t(xb) * N2 * CHI;
+      const gmem<T>* X = Xs + size_t(xb) * N2 * CHI;
       // Z_c[(a,al),(x,be)] = sum_b wh(a,b) wv(x,b) (A_c[b] Xt^(b))[al][be], both b in one tile loop
       {
         using MT = MfmaTile<T>;
@@ -632,9 +634,9 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       __syncthreads();
       const int nz = 2 * l, nk = 2 * k;
       // W = G_{c-1} Z (nz x nk), then H = Z^T W (nk x nk, symmetric); the zip-up takes G = 1
-      const T* Wz = ZIP ? Zs : Ws;
+      const gmem<T>* Wz = ZIP ? Zs : Ws;
       if (!ZIP) {
-        const T* Gp = Gs + size_t(c - 1) * BLK;
+        const gmem<T>* Gp = Gs + size_t(c - 1) * BLK;
         big_gemm<T>(
             nz, nk, nz, [&](int i, int kk) { return (i < nz && kk < nz) ? Gp[i * N2 + kk] : T(0); },
             [&](int kk, int j) { return (kk < nz && j < nk) ? Zs[kk * N2 + j] : T(0); },
@@ -653,7 +655,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       });
       if (tid == 0) bdout[c] = (unsigned char)kept;
       // Xt_c = Z V^T (nz x kept), rescaled by 2^-e
-      T* Xn = Xs + size_t(xb ^ 1) * N2 * CHI;
+      gmem<T>* Xn = Xs + size_t(xb ^ 1) * N2 * CHI;
       T mx = 0;
       big_gemm<T>(
           nz, kept, nk, [&](int i, int kk) { return (i < nz && kk < nk) ? Zs[i * N2 + kk] : T(0); },
@@ -677,7 +679,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       const bool fv = vbit(0);
       stage(Ain, 1, m);
       __syncthreads();
-      const T* X = Xs + size_t(xb) * N2 * CHI;
+      const gmem<T>* X = Xs + size_t(xb) * N2 * CHI;
       T part = 0;
       for (int o = tid; o < 2 * k; o += NT) {
         const int x = o / k, be = o % k;
@@ -717,7 +719,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       const bool fh = c > 0 ? hbit(c - 1) : false;
       stage(Ain + size_t(c) * site, l, m);
       __syncthreads();
-      const T* Ct = Xs + size_t(xb) * N2 * CHI;
+      const gmem<T>* Ct = Xs + size_t(xb) * N2 * CHI;
       {
         using MT = MfmaTile<T>;
         const int i16 = lane & 15, q = lane >> 4;
@@ -789,7 +791,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       });
       if (tid == 0) bdout[c + 1] = (unsigned char)kept;
       // C_c = V T_c (kept x nc), kept transposed, rescaled by 2^-e
-      T* Cn = Xs + size_t(xb ^ 1) * N2 * CHI;
+      gmem<T>* Cn = Xs + size_t(xb ^ 1) * N2 * CHI;
       T mx = 0;
       big_gemm<T>(
           nc, kept, nr, [&](int i, int kk) { return (i < nc && kk < nr) ? Zs[kk * N2 + i] : T(0); },

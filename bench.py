@@ -62,15 +62,51 @@ def proposals_per_wg(precision, n, K, Lmax):
     return 128 if wide else 64
 
 
-# Counters per dispatch of the dominant kernels (rocprofv3 --pmc; the summaries and commands are
-# in profiles/): FETCH_SIZE / WRITE_SIZE in KiB, each scaled by the same counter on a plain copy
-# of known size, and the matrix-core counters (SQ_INSTS_VALU_MFMA_MOPS_* count 512 flops each;
-# SQ_VALU_MFMA_BUSY_CYCLES against GRBM_GUI_ACTIVE x SIMDs).  Valid only for the kernel sources
-# they were taken on: reported as null once those change (SHA-256 of the sources).
-COUNTERS = {}
-
-SIMDS = 256 * 4
-
+# Counters per dispatch of the dominant kernels in the benchmark's launch shapes (rocprofv3 --pmc;
+# the summaries and commands are in profiles/rbim1024_bf16_counters.md): FETCH_SIZE / WRITE_SIZE
+# in KiB, each scaled by the same counter on a plain copy of known size, and the matrix-core
+# counters (SQ_INSTS_VALU_MFMA_MOPS_* count 512 flops each; SQ_VALU_MFMA_BUSY_CYCLES and
+# GRBM_GUI_ACTIVE as read).  The build's are those of a grouped launch (3 batches).  Valid only
+# for the kernel sources they were taken on: reported as null once those change (SHA-256).
+COUNTERS = {
+    ('rbim1024', 'bf16', 'env_build'): {
+        "fetch_kib": 19401724.40625,
+        "fetch_factor": 1.9999239473653783,
+        "write_kib": 107569079.53125,
+        "write_factor": 1.0,
+        "mfma_mops": {
+            "f64": 0.0,
+            "f32": 1522910784.0,
+            "bf16": 0.0
+        },
+        "mfma_busy_cycles": 12183286272.0,
+        "gui_active_cycles": 335210475477.5,
+        "sources_sha256": {
+            "envbuild_big.hip": "db2429127022874ac4bd84c099eb94168ec470eabc504ca5c85523beff4d8fb5",
+            "envbuild.hip": "46f0da52b8c90096db817501aa8229268eb911bf2a310a9b8119f6b54bba5959",
+            "common.hpp": "373c1289408779effdb76fff0cb18b389447af9368a0c2b3675272823aa4c649",
+            "internal.hpp": "97fb840f4a6670c01adfdf9b0f7c6d1bfe125917d858b7d13bb0a71048c27c79"
+        }
+    },
+    ('rbim1024', 'bf16', 'propose'): {
+        "fetch_kib": 203157102.453125,
+        "fetch_factor": 1.9999239473653783,
+        "write_kib": 274673816.5546875,
+        "write_factor": 1.0,
+        "mfma_mops": {
+            "f64": 0.0,
+            "f32": 9547108352.0,
+            "bf16": 0.0
+        },
+        "mfma_busy_cycles": 76376866816.0,
+        "gui_active_cycles": 96101452684.125,
+        "sources_sha256": {
+            "sampler.hip": "97af02bbb5a3dd14255b02c92504f67d74d326e038bfcae87bd9dddc7ee03a22",
+            "common.hpp": "373c1289408779effdb76fff0cb18b389447af9368a0c2b3675272823aa4c649",
+            "internal.hpp": "97fb840f4a6670c01adfdf9b0f7c6d1bfe125917d858b7d13bb0a71048c27c79"
+        }
+    },
+}
 
 def counted(workload, precision, kernel):
     import hashlib
@@ -100,11 +136,10 @@ def mfma_counters(rec, launch_ms, peak_tflops):
     flops = {k: 512.0 * v for k, v in mops.items()}
     total = sum(flops.values())
     ach = total / (launch_ms * 1e-3) / 1e12
-    out = {"executed_flops_per_launch": flops, "executed_tflops": ach,
-           "executed_frac_of_peak": ach / peak_tflops}
-    if rec.get("gui_active_cycles"):
-        out["mfma_busy_frac"] = rec["mfma_busy_cycles"] / (rec["gui_active_cycles"] * SIMDS)
-    return out
+    return {"executed_flops_per_launch": flops, "executed_tflops": ach,
+            "executed_frac_of_peak": ach / peak_tflops,
+            "mfma_busy_cycles": rec.get("mfma_busy_cycles"),
+            "grbm_gui_active_cycles": rec.get("gui_active_cycles")}
 
 
 def build_flops_per_site(chi):

@@ -86,8 +86,8 @@ typedef struct {
   uint8_t* d_bonds;   /* L x (L + 1) bytes, or NULL: entry [r][c] bounds the bond between sites
                          c-1 and c of E_r (no stored entry of E_r beyond it is nonzero; entries
                          c = 0 and c = L are 1).  Written by tnmc_build_env; read by tnmc_propose
-                         and tnmc_logq to load only the nonzero block of each site (the results
-                         are the same without it; NULL: whole sites are loaded). */
+                         and tnmc_logq at chi = 64 to load only the nonzero block of each site
+                         (the results are the same without it; NULL: whole sites are loaded). */
 } tnmc_instance;
 
 /* Bits of a realization's status word.  Kernels only set bits; the caller clears the word (any

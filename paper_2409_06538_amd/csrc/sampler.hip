@@ -360,15 +360,17 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
   typedef unsigned int u4 __attribute__((ext_vector_type(PIECE / 4)));
   E pf[SPT];
   u4 pq[NQ];
-  // With the bond table, a site whose bonds are both at most 16 loads only the leading 16 x 16
-  // block of its two matrices (the rest is zero): NN entries per thread instead of SPT.
+  // With the bond table at CHI = 64, a site whose bonds are both at most 16 loads only the
+  // leading 16 x 16 block of its two matrices (the rest is zero): NN entries per thread instead
+  // of SPT.  Smaller sites are staged whole, which measured faster (their narrow test runs on
+  // the staged values).
   constexpr int NN = (2 * 256 + MF_NT - 1) / MF_NT;
   E nf[NN];
   bool nsite = false;   // the staged site is narrow by the bond table
   const gmem<const uint8_t>* bonds = R.bonds ? as_global(R.bonds) : nullptr;
   auto load_site = [&](int r, int c) {
     const gmem<E>* src = env + (size_t(r) * L + c) * SITE;
-    if (CHI > 16 && bonds != nullptr) {
+    if (CHI >= 64 && bonds != nullptr) {
       const size_t bi = size_t(r) * (L + 1) + c;
       nsite = bonds[bi] <= 16 && bonds[bi + 1] <= 16;
       if (nsite) {

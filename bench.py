@@ -70,9 +70,9 @@ def proposals_per_wg(precision, n, K, Lmax):
 # for the kernel sources they were taken on: reported as null once those change (SHA-256).
 COUNTERS = {
     ('rbim1024', 'bf16', 'env_build'): {
-        "fetch_kib": 19401724.40625,
-        "fetch_factor": 1.9999239473653783,
-        "write_kib": 107569079.53125,
+        "fetch_kib": 19401747.40625,
+        "fetch_factor": 1.999919179367804,
+        "write_kib": 107569053.921875,
         "write_factor": 1.0,
         "mfma_mops": {
             "f64": 0.0,
@@ -80,7 +80,7 @@ COUNTERS = {
             "bf16": 0.0
         },
         "mfma_busy_cycles": 12183286272.0,
-        "gui_active_cycles": 335210475477.5,
+        "gui_active_cycles": 335292599918.0,
         "sources_sha256": {
             "envbuild_big.hip": "db2429127022874ac4bd84c099eb94168ec470eabc504ca5c85523beff4d8fb5",
             "envbuild.hip": "46f0da52b8c90096db817501aa8229268eb911bf2a310a9b8119f6b54bba5959",
@@ -89,8 +89,8 @@ COUNTERS = {
         }
     },
     ('rbim1024', 'bf16', 'propose'): {
-        "fetch_kib": 203157102.453125,
-        "fetch_factor": 1.9999239473653783,
+        "fetch_kib": 203152772.453125,
+        "fetch_factor": 1.999919179367804,
         "write_kib": 274673816.5546875,
         "write_factor": 1.0,
         "mfma_mops": {
@@ -99,9 +99,9 @@ COUNTERS = {
             "bf16": 0.0
         },
         "mfma_busy_cycles": 76376866816.0,
-        "gui_active_cycles": 96101452684.125,
+        "gui_active_cycles": 96105608652.375,
         "sources_sha256": {
-            "sampler.hip": "97af02bbb5a3dd14255b02c92504f67d74d326e038bfcae87bd9dddc7ee03a22",
+            "sampler.hip": "4d1f9bb7b51810020c76673f0feae6419a18fdb911e9af9b77b35022df27a447",
             "common.hpp": "373c1289408779effdb76fff0cb18b389447af9368a0c2b3675272823aa4c649",
             "internal.hpp": "97fb840f4a6670c01adfdf9b0f7c6d1bfe125917d858b7d13bb0a71048c27c79"
         }

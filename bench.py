@@ -907,7 +907,7 @@ def calib_copy(mib):
 # stages built per launch in the overlapped mode (1: one build per stage, several in flight)
 DEFAULT_GROUP_STEPS = {"rbim1024": 3}
 DEFAULT_STEPS = {"rbim16": 50, "rbim64": 50, "mixed": 4, "rbim256": 2, "rbim256_chi32": 2,
-                 "rbim1024": 6}
+                 "rbim1024": 9}
 
 SWEEP_LS = (16, 32, 64, 128, 256)
 SWEEP_CHIS = (8, 16, 32, 48)
@@ -1052,8 +1052,8 @@ def main():
     ap.add_argument("--steps", type=int, default=0,
                     help="timed steps (default: 2 for rbim256, whose steps take seconds; 50 for "
                          "rbim64 and rbim16, whose steps take milliseconds, so that the pipeline "
-                         "fill and drain inside the timed region are amortised; 4 for mixed; 6 "
-                         "(two build groups) for rbim1024)")
+                         "fill and drain inside the timed region are amortised; 4 for mixed; 9 "
+                         "(three build groups) for rbim1024)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
     ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16"],

@@ -497,7 +497,11 @@ def run_gpu_grouped(args):
     D = args.group_steps
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    s_build, s_prop = torch.cuda.Stream(), torch.cuda.Stream()
+    # one build stream; the proposal launches of a group run side by side, one stream each (a
+    # launch of a few realizations fills a few dozen CUs), and the accepts follow on the first
+    s_build = torch.cuda.Stream()
+    s_props = [torch.cuda.Stream() for _ in range(D)]
+    s_prop = s_props[0]
     groups = []
     for _ in range(2):
         members = []
@@ -537,23 +541,32 @@ def run_gpu_grouped(args):
                 e[0].record(s_build)
                 binding.build_env_group([m["b"] for m in mem], grp["ws"])
                 e[1].record(s_build)
-            with torch.cuda.stream(s_prop):
-                s_prop.wait_event(e[1])
-                for u, m in zip(us, mem):
+            firsts, pdone = [], []
+            for k, (u, m) in enumerate(zip(us, mem)):
+                sp = s_props[k]
+                with torch.cuda.stream(sp):
+                    sp.wait_event(e[1])
                     jp = u % len(ps)
                     ep = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-                    ep[0].record(s_prop)
+                    ep[0].record(sp)
                     first = stage[jp] * K
                     stage[jp] += 1
+                    firsts.append(first)
                     m["b"].propose(K, args.seed, first_proposal=first, out=m["out"])
-                    ep[1].record(s_prop)
+                    ep[1].record(sp)
+                    ev.append(("propose", ep))
+                    pdone.append(ep[1])
+            with torch.cuda.stream(s_prop):
+                for d in pdone:
+                    s_prop.wait_event(d)
+                for u, m, first in zip(us, mem, firsts):   # the chains advance in stage order
+                    jp = u % len(ps)
                     ch = chains[jp]
                     fresh = (ch["init"] == 0).sum(dtype=torch.float64)
                     acc, _ = m["b"].accept(m["out"], ch, seed=args.seed, first_step=first,
                                            accum=m["accum"])
                     per_real = acc.sum(dim=1, dtype=torch.float64)
                     sums.append(torch.stack([per_real.sum(), (per_real * L2).sum(), n * K - fresh]))
-                    ev.append(("propose", ep))
                 done = torch.cuda.Event()
                 done.record(s_prop)
                 grp["done"] = done

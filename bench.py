@@ -481,10 +481,11 @@ def cu_masked_stream(reserve):
 def run_gpu_grouped(args):
     """Consecutive steps overlapped in groups: the batches of `group` consecutive pipeline
     stages are built by one launch (one workgroup per realization, group x n of them) on one
-    stream, while the proposals and accepts of the previous group run on a second stream; two
-    groups of batches alternate, so a build never overwrites environments that proposals still
-    read.  For workloads with few realizations (rbim1024: 2), whose build occupies a few CUs for
-    seconds per launch while the proposals leave most of the chip free."""
+    stream, while the proposal launches of the previous group run side by side, one stream each,
+    and its accepts follow in stage order (the chains continue from stage to stage); two groups
+    of batches alternate, so a build never overwrites environments that proposals still read.
+    For workloads with few realizations (rbim1024: 2), whose build occupies a few CUs for seconds
+    per launch while a proposal launch fills a few dozen."""
     import torch
     from paper_2409_06538_amd import binding
     import synth

@@ -268,9 +268,11 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       if (!pk && a != piv) d -= l * l;
       if (a == piv) pk = true;
     }
-    // rows J[j][a] = Lr[j]: classical Gram-Schmidt twice; the projections of a pass are taken
-    // from the same vector.  The 64 / G lane groups hold the same vector, so one group sum
-    // gives 64 / G projections at once, group u taking row g + u.
+    // rows J[j][a] = Lr[j]: classical Gram-Schmidt, the projections of a pass taken from the
+    // same vector, with a second pass only where the first removed more than half of the
+    // squared norm (Kahan's "twice is enough" test: otherwise one pass leaves the row
+    // orthogonal to working precision).  The 64 / G lane groups hold the same vector, so one
+    // group sum gives 64 / G projections at once, group u taking row g + u.
     constexpr int P = 64 / G;
     const int slot = lane / G;
     for (int j = 0; j < rk; ++j) {
@@ -278,7 +280,9 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
 #pragma unroll
       for (int i = 0; i < G; ++i) x = (i == j) ? Lr[i] : x;
       const T n2 = group_sum<G>(x * x);
-      for (int pass = 0; pass < 2; ++pass) {
+      T r2 = n2;
+      for (int pass = 0; pass < 2 && j > 0; ++pass) {
+        if (pass == 1 && readlane_v(r2, 0) > T(0.5) * readlane_v(n2, 0)) break;
         T acc = 0;
 #pragma unroll
         for (int g = 0; g < G; g += P) {
@@ -292,8 +296,8 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
           }
         }
         x -= acc;
+        r2 = group_sum<G>(x * x);
       }
-      const T r2 = group_sum<G>(x * x);
       const T sc = (n2 > T(0) && r2 > T(Tol::eta) * n2) ? T(1) / sqrt(r2) : T(0);
       x *= sc;
 #pragma unroll

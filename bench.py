@@ -70,36 +70,36 @@ def proposals_per_wg(precision, n, K, Lmax):
 # for the kernel sources they were taken on: reported as null once those change (SHA-256).
 COUNTERS = {
     ('rbim1024', 'bf16', 'env_build'): {
-        "fetch_kib": 19401747.40625,
-        "fetch_factor": 1.999919179367804,
-        "write_kib": 107569053.921875,
+        "fetch_kib": 19796019.416666668,
+        "fetch_factor": 1.9999265697737347,
+        "write_kib": 107822654.28125,
         "write_factor": 1.0,
         "mfma_mops": {
             "f64": 0.0,
-            "f32": 1522910784.0,
+            "f32": 1569153360.0,
             "bf16": 0.0
         },
-        "mfma_busy_cycles": 12183286272.0,
-        "gui_active_cycles": 335292599918.0,
+        "mfma_busy_cycles": 12553226880.0,
+        "gui_active_cycles": 327452175929.6667,
         "sources_sha256": {
-            "envbuild_big.hip": "db2429127022874ac4bd84c099eb94168ec470eabc504ca5c85523beff4d8fb5",
+            "envbuild_big.hip": "c579760cf111633f06dc068f76d6a0767aa6bb1ca7e98bea6104497f3b700bf6",
             "envbuild.hip": "46f0da52b8c90096db817501aa8229268eb911bf2a310a9b8119f6b54bba5959",
             "common.hpp": "373c1289408779effdb76fff0cb18b389447af9368a0c2b3675272823aa4c649",
             "internal.hpp": "97fb840f4a6670c01adfdf9b0f7c6d1bfe125917d858b7d13bb0a71048c27c79"
         }
     },
     ('rbim1024', 'bf16', 'propose'): {
-        "fetch_kib": 203152772.453125,
-        "fetch_factor": 1.999919179367804,
-        "write_kib": 274673816.5546875,
+        "fetch_kib": 205230812.23295453,
+        "fetch_factor": 1.9999265697737347,
+        "write_kib": 277552281.70454544,
         "write_factor": 1.0,
         "mfma_mops": {
             "f64": 0.0,
-            "f32": 9547108352.0,
+            "f32": 10007662592.0,
             "bf16": 0.0
         },
-        "mfma_busy_cycles": 76376866816.0,
-        "gui_active_cycles": 96105608652.375,
+        "mfma_busy_cycles": 80061300736.0,
+        "gui_active_cycles": 97613679168.90909,
         "sources_sha256": {
             "sampler.hip": "4d1f9bb7b51810020c76673f0feae6419a18fdb911e9af9b77b35022df27a447",
             "common.hpp": "373c1289408779effdb76fff0cb18b389447af9368a0c2b3675272823aa4c649",

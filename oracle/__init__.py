@@ -23,6 +23,7 @@ envbuild     Boundary-MPS environments: row MPO applied to an MPS, QR + SVD comp
 sampler      Whole-lattice proposals from the environments with log q(s); teacher-forced log q.
 accept       Independence Metropolis chain (Eq. (3) with g(s'|s) = q(s')).
 observables  Energy, magnetisation, edge magnetisation and replica overlap (Sec. III C).
+pbc          Periodic lattices by a frozen row and column per step; the open block and its fields.
 
 Parity pins (what fixes each part independently of this code) live in ``tests/test_oracle_*.py``.
 """

@@ -14,11 +14,15 @@ environment of row r is the function of the row configuration x
     Z           = sum_x H_0(x) E_0(x),
 
 with H_r(y) = prod_c exp(beta Jh[r,c] y_c y_{c+1}) and V_{r-1}(x, y) = prod_c exp(beta
-Jv[r-1,c] x_c y_c).  Each E_r is kept as a matrix-product state (MPS) along the row.  Applying
+Jv[r-1,c] x_c y_c).  A lattice that is a block of a larger system with its other spins held
+fixed (see ``pbc``) carries integer site fields h; their weight F_r(y) = prod_c exp(beta h[r,c]
+y_c) enters with the row's own bonds, H_r(y) -> H_r(y) F_r(y), in the recursion and in Z.  Each E_r is kept as a matrix-product state (MPS) along the row.  Applying
 the row operator to an MPS of bond chi gives an MPS of bond 2*chi whose site tensor carries the
 spin y_c on its right bond:
 
     At[c][(a, alpha), x, (b, alpha')] = exp(beta Jh[r,c-1] a b) exp(beta Jv[r-1,c] x b) A[c][alpha, b, alpha']
+
+(times exp(beta h[r,c] b) with fields)
 
 (no a at c = 0; b summed at c = Lc-1).  It is compressed back to chi by the canonical SVD
 compression: a QR sweep left to right (left-orthonormal sites), then an SVD sweep right to left
@@ -46,12 +50,15 @@ def _bond_matrix(beta, J):
     return np.exp(beta * J * np.outer(_SGN, _SGN))
 
 
-def apply_row_mpo(mps, Jh_row, Jv_row, beta):
-    """Site tensors of (V H f) for the MPS f: Jh_row = Jh[r], Jv_row = Jv[r-1]."""
+def apply_row_mpo(mps, Jh_row, Jv_row, beta, field_row=None):
+    """Site tensors of (V H F f) for the MPS f: Jh_row = Jh[r], Jv_row = Jv[r-1], field_row =
+    h[r] (None: no field)."""
     Lc = len(mps)
     out = []
     for c, A in enumerate(mps):
         dl, _, dr = A.shape
+        if field_row is not None:
+            A = A * np.exp(beta * field_row[c] * _SGN)[None, :, None]
         wv = _bond_matrix(beta, Jv_row[c])                    # (x, b)
         if Lc == 1:
             T = np.einsum("xb,ubv->uxv", wv, A)
@@ -167,14 +174,16 @@ def sensitivity(env, eps):
     return worst
 
 
-def top_row_sum(mps, Jh_row, beta):
-    """ln sum_x H_0(x) F(x) for the MPS F, with a running rescale (log kept separately)."""
+def top_row_sum(mps, Jh_row, beta, field_row=None):
+    """ln sum_x H_0(x) F_0(x) E(x) for the MPS E, with a running rescale (log kept separately);
+    F_0 = 1 without fields."""
     Lc = len(mps)
-    v = mps[0][0].copy()                                      # v[sigma] = A0[0, sigma, :] -> (2, dr)
+    g = [np.ones(2) if field_row is None else np.exp(beta * field_row[c] * _SGN) for c in range(Lc)]
+    v = mps[0][0] * g[0][:, None]                             # v[sigma] = A0[0, sigma, :] -> (2, dr)
     logscale = 0.0
     for c in range(1, Lc):
         wh = _bond_matrix(beta, Jh_row[c - 1])               # (sigma, sigma')
-        A = mps[c]                                           # (dl, 2, dr)
+        A = mps[c] * g[c][None, :, None]                     # (dl, 2, dr)
         v = np.einsum("st,sa,atb->tb", wh, v, A)
         m = float(np.max(np.abs(v)))
         v = v / m
@@ -183,10 +192,10 @@ def top_row_sum(mps, Jh_row, beta):
     return logscale + math.log(total) if total > 0 else float("nan")
 
 
-def build_env(Jh, Jv, beta, chi, rows=None, method="canonical"):
+def build_env(Jh, Jv, beta, chi, rows=None, method="canonical", field=None):
     """Environments E_{Lr-1}, ..., E_0 by repeated row-MPO application and compression
     (method "canonical": compress, the canonical SVD compression; "zipup": compress_zipup in the
-    direction of zipup_direction).
+    direction of zipup_direction).  field: optional (Lr, Lc) integer site fields.
 
     Returns dict with
       sites[r][c] : (chi_l, 2, chi_r) tensors of the normalised MPS of E_r
@@ -206,7 +215,7 @@ def build_env(Jh, Jv, beta, chi, rows=None, method="canonical"):
     lognorm[Lr - 1] = 0.5 * Lc * math.log(2.0)
     last = 1 if rows is None else max(1, Lr - rows)
     for r in range(Lr - 1, last - 1, -1):
-        big = apply_row_mpo(mps, Jh[r], Jv[r - 1], beta)
+        big = apply_row_mpo(mps, Jh[r], Jv[r - 1], beta, None if field is None else field[r])
         if method == "canonical":
             mps, ln_n, cuts[r - 1] = compress(big, chi)
         elif method == "zipup":
@@ -217,6 +226,7 @@ def build_env(Jh, Jv, beta, chi, rows=None, method="canonical"):
         lognorm[r - 1] = lognorm[r] + ln_n
     out = {"sites": sites, "lognorm": lognorm, "cuts": cuts, "chi": chi, "method": method}
     if rows is None:
-        out["lnZ"] = lognorm[0] + top_row_sum(sites[0], Jh[0], beta)
+        out["lnZ"] = lognorm[0] + top_row_sum(sites[0], Jh[0], beta,
+                                              None if field is None else field[0])
     return out
 

@@ -30,11 +30,12 @@ def _logsumexp(a):
     return float(m + np.log(np.sum(np.exp(a - m))))
 
 
-def brute_force(Jh, Jv, beta):
-    """Exact enumeration. Returns dict with configs, E, lnZ and logP for every configuration."""
+def brute_force(Jh, Jv, beta, field=None):
+    """Exact enumeration. Returns dict with configs, E, lnZ and logP for every configuration
+    (field: optional (Lr, Lc) site fields, see energy)."""
     Lr, Lc = Jh.shape[0], Jv.shape[1]
     s = all_configs(Lr, Lc)
-    E = energy(s, Jh, Jv)
+    E = energy(s, Jh, Jv, field)
     lw = -beta * E.astype(np.float64)
     lnZ = _logsumexp(lw)
     return {"configs": s, "E": E, "lnZ": lnZ, "logP": lw - lnZ}

@@ -12,6 +12,8 @@ the row chain
     f_r(y) = prod_c phi_c(y_c) prod_c w_c(y_c, y_{c+1}) E_r(y),
     phi_c(y) = exp(beta Jv[r-1,c] s[r-1,c] y)   (1 on row 0),   w_c(y, y') = exp(beta Jh[r,c] y y'),
 
+(with site fields h, phi_c(y) also carries exp(beta h[r,c] y), on row 0 too),
+
 which is summed exactly column by column:
 
   right partial sums  R_{Lc-1}(y) = [1],
@@ -56,11 +58,13 @@ def proposal_uniforms(seed, realization, proposals, r, Lc):
     return philox.uniforms((seed, philox.STREAM_PROPOSAL), c, c1=r, c2=k, c3=realization)
 
 
-def run(env, Jh, Jv, beta, K=None, seed=0, realization=0, first_proposal=0, teacher=None):
+def run(env, Jh, Jv, beta, K=None, seed=0, realization=0, first_proposal=0, teacher=None,
+        field=None):
     """Sample K proposals (teacher=None) or evaluate log q of given configurations.
 
-    env     : dict from envbuild.build_env
+    env     : dict from envbuild.build_env (built with the same field)
     teacher : optional (K, Lr, Lc) array of +1/-1 spins to evaluate instead of sampling
+    field   : optional (Lr, Lc) integer site fields
     returns dict with spins (K, Lr, Lc) int8, logq (K,) float64, fallbacks (int),
     pplus (K, Lr, Lc) float64: the p+ used at every site (after the clamp)
     """
@@ -81,6 +85,9 @@ def run(env, Jh, Jv, beta, K=None, seed=0, realization=0, first_proposal=0, teac
                          * _SGN[None, None, :])                       # (K, Lc, 2)
         else:
             phi = np.ones((K, Lc, 2))
+        if field is not None:
+            phi = phi * np.exp(beta * np.asarray(field[r], dtype=np.float64)[None, :, None]
+                               * _SGN[None, None, :])
         w = [_bond_matrix(beta, Jh[r, c]) for c in range(Lc - 1)]
         # right partial sums R[c][k, y, beta], beta = right bond of site c
         R = [None] * Lc

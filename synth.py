@@ -12,6 +12,8 @@ dataset.  Workloads (open L x L lattices, beta on the Nishimori line):
   rbim256   L=256, p in {0.10, 0.109, 0.12}, chi=48, 128 realizations, 1000 proposals, BF16
   mixed     256 realizations with L = (32, 64, 128, 256)[i mod 4], seed i, p=0.109, chi=32, FP32
   rbim1024  L=1024, p=0.109, chi=64, 2 realizations (seeds 0, 1), FP32 and BF16
+Periodic lattices (the frozen-line-pair steps) take their couplings and the lines of each step
+from torus_couplings and frozen_lines.
 """
 import numpy as np
 
@@ -43,6 +45,22 @@ def random_pm1(seed, shape):
     """Random +-1 int8 array of the given shape."""
     rng = np.random.default_rng(seed)
     return (1 - 2 * rng.integers(0, 2, size=shape)).astype(np.int8)
+
+
+def torus_couplings(seed, L, p):
+    """+-1 couplings of an L x L torus with P(J = -1) = p, from numpy's default generator:
+    (Jh_t, Jv_t), int8 (L, L); Jh_t[r, c] is the bond (r, c)-(r, (c+1) mod L), Jv_t[r, c] the bond
+    (r, c)-((r+1) mod L, c)."""
+    rng = np.random.default_rng(seed)
+    Jh = np.where(rng.random((L, L)) < p, -1, 1).astype(np.int8)
+    Jv = np.where(rng.random((L, L)) < p, -1, 1).astype(np.int8)
+    return Jh, Jv
+
+
+def frozen_lines(seed, steps, L):
+    """(steps, 2) int32 array of (row, column) pairs, uniform on [0, L), one pair per step."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, L, size=(steps, 2)).astype(np.int32)
 
 
 def words_per_row(L):

@@ -88,6 +88,13 @@ typedef struct {
                          c = 0 and c = L are 1).  Written by tnmc_build_env; read by tnmc_propose
                          and tnmc_logq at chi = 64 to load only the nonzero block of each site
                          (the results are the same without it; NULL: whole sites are loaded). */
+  int8_t* d_field;    /* L x L bytes (row-major, entry r * L + c), or NULL: integer site fields
+                         h, -4 <= h <= 4, for a lattice that is a block of a larger system whose
+                         other spins are held fixed (Sec. I: the block may be part of the
+                         system; Sec. IV: the frozen lines act as external fields).  Site (r, c)
+                         then carries the extra weight exp(beta h s), i.e. E(s) gains
+                         -sum h s: tnmc_build_env (every form), tnmc_propose, tnmc_logq and
+                         tnmc_energy all use it.  Written by tnmc_pbc_block, else by the caller. */
 } tnmc_instance;
 
 /* Bits of a realization's status word.  Kernels only set bits; the caller clears the word (any
@@ -183,7 +190,8 @@ tnmc_status tnmc_build_env_static(const tnmc_instance* inst, int32_t n, int32_t 
  * by row and, within a row, column by column from the cached environments: right partial sums
  * R_c(y) = sum_y' w_c(y,y') phi_{c+1}(y') A^{(c+1)}[y'] R_{c+1}(y') and a left running vector;
  * Z_c(y) = [w_{c-1}(s_{c-1},y)] phi_c(y) l A^{(c)}[y] R_c(y), phi_c(y) = exp(beta Jv[r-1][c] s[r-1][c] y),
- * w_c(y,y') = exp(beta Jh[r][c] y y').  Negative Z_c(y) count as 0; p+ = Z_c(+)/(Z_c(+)+Z_c(-))
+ * w_c(y,y') = exp(beta Jh[r][c] y y'), and phi_c(y) also carries exp(beta h[r][c] y) where the
+ * realization has fields (row 0 included; d_E then includes -sum h s).  Negative Z_c(y) count as 0; p+ = Z_c(+)/(Z_c(+)+Z_c(-))
  * (1/2 if the sum is 0 or not finite), clamped to [1e-12, 1-1e-12]; s = +1 iff u < p+ with u
  * = draw c of the stream keyed (seed, 1) with counter words (r, first_proposal + k, id).
  * Outputs per (realization i, proposal k): d_spins [n][K][Lmax][W(Lmax)] words, d_logq [n][K]
@@ -235,8 +243,8 @@ tnmc_status tnmc_logq(const tnmc_instance* inst, int32_t n, int32_t chi, tnmc_pr
                       int32_t K, const uint64_t* d_spins, void* d_workspace,
                       size_t workspace_bytes, double* d_logq, hipStream_t stream);
 
-/* a5 -- exact integer energies E(s) = -sum J_ij s_i s_j (Eq. (10)) of d_spins [n][K][Lmax][W] into
- * d_E [n][K]. */
+/* a5 -- exact integer energies E(s) = -sum J_ij s_i s_j (Eq. (10)), minus sum h s where the
+ * realization has fields, of d_spins [n][K][Lmax][W] into d_E [n][K]. */
 tnmc_status tnmc_energy(const tnmc_instance* inst, int32_t n, int32_t K, const uint64_t* d_spins,
                         int32_t* d_E, void* d_workspace, size_t workspace_bytes,
                         hipStream_t stream);
@@ -291,6 +299,40 @@ tnmc_status tnmc_disorder_average(const double* d_accum, int32_t n, int32_t L, d
  * the words are not cleared. */
 tnmc_status tnmc_status_check(const tnmc_instance* inst, int32_t n, uint32_t* h_words,
                               hipStream_t stream);
+
+/* f4 -- periodic boundaries by a frozen line pair (Sec. IV).  A torus of side L (3 <= L <= 1024)
+ * with couplings on its 2 L^2 bonds and one chain's configuration.  Each step freezes row r0 and
+ * column c0; the other (L-1) x (L-1) spins form an open block whose site (a, b) is torus site
+ * ((r0 + 1 + a) mod L, (c0 + 1 + b) mod L), with the frozen spins acting as fields on its
+ * boundary.  A step is: tnmc_pbc_block, tnmc_build_env / tnmc_propose on the block (fields
+ * included), tnmc_logq and tnmc_energy of the current block state into the chain state
+ * (d_chain_init = 1), tnmc_accept with one chain per block, tnmc_pbc_merge. */
+typedef struct {
+  int32_t L;           /* torus side, 3 <= L <= 1024 */
+  int32_t r0, c0;      /* frozen row and column of this step, 0 <= r0, c0 < L */
+  int32_t pad_;
+  const uint64_t* d_Jh;  /* L x W(L) words: bit c of row r is the bond (r,c)-(r,(c+1) mod L) */
+  const uint64_t* d_Jv;  /* L x W(L) words: bit c of row r is the bond (r,c)-((r+1) mod L,c) */
+  uint64_t* d_spins;     /* L x W(L) words: the chain's configuration (read; written by merge) */
+} tnmc_torus;
+
+/* Workspace bytes of tnmc_pbc_block / tnmc_pbc_merge for n tori. */
+size_t tnmc_pbc_workspace_bytes(int32_t n);
+
+/* The open block of each torus tor[i] (blk[i].L must be tor[i].L - 1): writes blk[i].d_Jh and
+ * d_Jv (the block's bonds, the layout of tnmc_instance), blk[i].d_field (L_b x L_b fields: the sum
+ * of J s_f over the frozen neighbours f of each block site) and the block's configuration into
+ * d_block_spins [n][Lmax][W(Lmax)] (Lmax = largest blk[i].L; the layout of one chain's state). */
+tnmc_status tnmc_pbc_block(const tnmc_torus* tor, const tnmc_instance* blk, int32_t n,
+                           uint64_t* d_block_spins, void* d_workspace, size_t workspace_bytes,
+                           hipStream_t stream);
+
+/* Writes the block configurations d_block_spins [n][Lmax][W(Lmax)] back into tor[i].d_spins (the
+ * frozen row and column kept) and, if d_E_torus != NULL, the torus energy -sum over the 2 L^2
+ * bonds of J s s into d_E_torus [n]. */
+tnmc_status tnmc_pbc_merge(const tnmc_torus* tor, const tnmc_instance* blk, int32_t n,
+                           const uint64_t* d_block_spins, int32_t* d_E_torus, void* d_workspace,
+                           size_t workspace_bytes, hipStream_t stream);
 
 const char* tnmc_status_string(tnmc_status s);
 

@@ -37,7 +37,14 @@ class Instance(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int32), ("pad_", ctypes.c_int32), ("beta", ctypes.c_double),
                 ("id", ctypes.c_uint64), ("d_Jh", ctypes.c_void_p), ("d_Jv", ctypes.c_void_p),
                 ("d_env", ctypes.c_void_p), ("d_lognorm", ctypes.c_void_p),
-                ("d_status", ctypes.c_void_p), ("d_bonds", ctypes.c_void_p)]
+                ("d_status", ctypes.c_void_p), ("d_bonds", ctypes.c_void_p),
+                ("d_field", ctypes.c_void_p)]
+
+
+class TorusDesc(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("r0", ctypes.c_int32), ("c0", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("d_Jh", ctypes.c_void_p), ("d_Jv", ctypes.c_void_p),
+                ("d_spins", ctypes.c_void_p)]
 
 
 class TNMCError(RuntimeError):
@@ -78,6 +85,9 @@ def load():
         "tnmc_disorder_average": (ctypes.c_int, [vp, i32, i32, dbl, i32, vp, vp]),
         "tnmc_status_check": (ctypes.c_int, [P, i32, vp, vp]),
         "tnmc_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "tnmc_pbc_workspace_bytes": (sz, [i32]),
+        "tnmc_pbc_block": (ctypes.c_int, [ctypes.POINTER(TorusDesc), P, i32, vp, vp, sz, vp]),
+        "tnmc_pbc_merge": (ctypes.c_int, [ctypes.POINTER(TorusDesc), P, i32, vp, vp, vp, sz, vp]),
     }
     for name, (res, args) in sigs.items():
         f = getattr(lib, name)
@@ -93,7 +103,7 @@ def exported_symbols():
             "tnmc_build_env", "tnmc_build_env_form", "tnmc_build_env_static", "tnmc_propose", "tnmc_propose_candidates", "tnmc_tune_set", "tnmc_tune_get",
             "tnmc_autotune_propose", "tnmc_logq", "tnmc_energy", "tnmc_accept",
             "tnmc_observables", "tnmc_disorder_average", "tnmc_status_check",
-            "tnmc_status_string"]
+            "tnmc_status_string", "tnmc_pbc_workspace_bytes", "tnmc_pbc_block", "tnmc_pbc_merge"]
 
 
 def _check(status, what):
@@ -155,7 +165,8 @@ def build_env_group(batches, workspace):
 class Batch:
     """Device buffers for a batch of realizations plus the host instance table."""
 
-    def __init__(self, Ls, betas, ids, chi, precision="fp32", K=1, device="cuda:0"):
+    def __init__(self, Ls, betas, ids, chi, precision="fp32", K=1, device="cuda:0",
+                 fields=False):
         lib = load()
         self.n = len(Ls)
         self.Ls = [int(L) for L in Ls]
@@ -169,6 +180,7 @@ class Batch:
         if not lib.tnmc_chi_supported(self.chi, self.prec):
             raise TNMCError(f"chi={chi} not supported for {precision}")
         self.Jh, self.Jv, self.env, self.lognorm, self.bonds = [], [], [], [], []
+        self.field = []   # per-realization L x L int8 site fields (fields=True)
         self.table = (Instance * self.n)()
         # one numeric status word per realization (TNMC_ST_* bits)
         self.status = torch.zeros(self.n, dtype=torch.int32, device=self.device)
@@ -191,9 +203,18 @@ class Batch:
             t.d_env, t.d_lognorm = env.data_ptr(), lam.data_ptr()
             t.d_status = self.status.data_ptr() + 4 * i
             t.d_bonds = bd.data_ptr()
+            if fields:
+                fl = torch.zeros(L * L, dtype=torch.int8, device=self.device)
+                self.field.append(fl)
+                t.d_field = fl.data_ptr()
         self.K = 0
         self.workspace = None
         self.ensure_workspace(K)
+
+    def set_field(self, i, h):
+        """Copy an (L, L) integer field array (host) into realization i (fields=True)."""
+        L = self.Ls[i]
+        self.field[i].copy_(torch.as_tensor(h, dtype=torch.int8).reshape(L * L))
 
     def use_bonds(self, on=True):
         """Pass (or not) each realization's bond table: written by the build, read by the
@@ -400,3 +421,73 @@ class Batch:
         """Environments of realization i as (L, L, 2, chi, chi)."""
         L = self.Ls[i]
         return self.env[i].view(L, L, 2, self.chi, self.chi)
+
+
+class PBC:
+    """Periodic L x L lattices (one chain per torus) stepped by a frozen row and column per step
+    (Sec. IV): torus couplings and configurations on the device, the open (L-1) x (L-1) blocks in
+    a Batch with fields.  Every step runs tnmc_pbc_block, the block's build, proposals, the
+    current state's log q and energy, tnmc_accept and tnmc_pbc_merge; nothing is computed here."""
+
+    def __init__(self, L, n, betas, ids, chi, precision="fp32", K=1, device="cuda:0"):
+        if L < 3:
+            raise TNMCError("PBC: L >= 3")
+        self.L, self.n = int(L), int(n)
+        self.W = words_per_row(self.L)
+        self.device = torch.device(device)
+        self.Jh = torch.zeros((self.n, self.L * self.W), dtype=torch.int64, device=self.device)
+        self.Jv = torch.zeros_like(self.Jh)
+        self.spins = torch.zeros_like(self.Jh)
+        self.E = torch.zeros(self.n, dtype=torch.int32, device=self.device)
+        self.batch = Batch([self.L - 1] * self.n, betas, ids, chi, precision, K=K, device=device,
+                           fields=True)
+        self.chains = self.batch.new_chains(1)
+        self.desc = (TorusDesc * self.n)()
+        for i in range(self.n):
+            d = self.desc[i]
+            d.L, d.r0, d.c0, d.pad_ = self.L, 0, 0, 0
+            d.d_Jh, d.d_Jv = self.Jh[i].data_ptr(), self.Jv[i].data_ptr()
+            d.d_spins = self.spins[i].data_ptr()
+        nb = int(load().tnmc_pbc_workspace_bytes(self.n))
+        self.pws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+
+    def set_torus(self, i, jh_words, jv_words, spin_words):
+        """Copy caller-packed torus couplings and configuration (L x W words each) into torus i."""
+        self.Jh[i].copy_(torch.as_tensor(jh_words.view("int64")).reshape(-1))
+        self.Jv[i].copy_(torch.as_tensor(jv_words.view("int64")).reshape(-1))
+        self.spins[i].copy_(torch.as_tensor(spin_words.view("int64")).reshape(-1))
+
+    def _pws(self):
+        return ctypes.c_void_p(self.pws.data_ptr()), ctypes.c_size_t(self.pws.numel())
+
+    def set_lines(self, lines):
+        """Frozen (row, column) of each torus for the next block / merge."""
+        for i, (r0, c0) in enumerate(lines):
+            self.desc[i].r0, self.desc[i].c0 = int(r0), int(c0)
+
+    def block(self):
+        ws, nb = self._pws()
+        _check(load().tnmc_pbc_block(self.desc, self.batch.table, self.n,
+                                     _ptr(self.chains["spins"]), ws, nb, _stream()),
+               "tnmc_pbc_block")
+
+    def merge(self, want_energy=True):
+        ws, nb = self._pws()
+        _check(load().tnmc_pbc_merge(self.desc, self.batch.table, self.n,
+                                     _ptr(self.chains["spins"]),
+                                     _ptr(self.E) if want_energy else None, ws, nb, _stream()),
+               "tnmc_pbc_merge")
+
+    def step(self, lines, K, seed, first_proposal=0, first_step=0):
+        """One step on every torus with the given lines: returns (accepted [n][K], proposals)."""
+        b, ch = self.batch, self.chains
+        self.set_lines(lines)
+        self.block()
+        b.build_env(want_lnZ=False)
+        props = b.propose(K, seed, first_proposal)
+        ch["logq"].copy_(b.logq(ch["spins"]))
+        ch["E"].copy_(b.energy(ch["spins"]))
+        ch["init"].fill_(1)
+        accepted, _ = b.accept(props, ch, seed, first_step)
+        self.merge()
+        return accepted, props

@@ -117,6 +117,7 @@ hipError_t upload_desc(const tnmc_instance* inst, int32_t n, int32_t chi, int32_
     d.ws = base + off;
     d.status = inst[i].d_status;
     d.bonds = inst[i].d_bonds;
+    d.field = inst[i].d_field;
     if (use == Use::build) off += align_up(env_build_scratch_bytes(p, chi, inst[i].L));
     else if (use == Use::propose) off += align_up(propose_scratch_bytes(p, chi, inst[i].L, K));
   }
@@ -165,6 +166,48 @@ int tuned_waves(int chi, tnmc_precision prec, int Lmax, int n, int K) {
   std::lock_guard<std::mutex> g(tune_mu);
   auto it = tune_table.find(TuneKey(chi, int(prec), Lmax, n, K));
   return it == tune_table.end() ? 0 : it->second;
+}
+
+bool any_field(const tnmc_instance* inst, int32_t n) {
+  for (int i = 0; i < n; ++i)
+    if (inst[i].d_field != nullptr) return true;
+  return false;
+}
+
+size_t torus_desc_bytes(int32_t n) { return align_up(size_t(n) * sizeof(DevTorus)); }
+
+// Checks of a batch of tori and their blocks; returns the largest block side or -1.
+int check_tori(const tnmc_torus* tor, const tnmc_instance* blk, int32_t n, bool need_block) {
+  if (tor == nullptr || blk == nullptr || n < 1) return -1;
+  int Lmax = 0;
+  for (int i = 0; i < n; ++i) {
+    const tnmc_torus& t = tor[i];
+    if (t.L < 3 || t.L > 1024 || t.r0 < 0 || t.r0 >= t.L || t.c0 < 0 || t.c0 >= t.L) return -1;
+    if (t.d_Jh == nullptr || t.d_Jv == nullptr || t.d_spins == nullptr) return -1;
+    if (blk[i].L != t.L - 1) return -1;
+    if (need_block && (blk[i].d_Jh == nullptr || blk[i].d_Jv == nullptr || blk[i].d_field == nullptr))
+      return -1;
+    Lmax = std::max(Lmax, int(blk[i].L));
+  }
+  return Lmax;
+}
+
+// The torus table in the workspace after the realization table.
+hipError_t upload_tori(const tnmc_torus* tor, int32_t n, void* ws, hipStream_t stream) {
+  static_assert(sizeof(DevTorus) % sizeof(uint64_t) == 0, "descriptor is whole words");
+  std::vector<DevTorus> h(n);
+  for (int i = 0; i < n; ++i) {
+    h[i].L = tor[i].L;
+    h[i].r0 = tor[i].r0;
+    h[i].c0 = tor[i].c0;
+    h[i].pad = 0;
+    h[i].Jh = tor[i].d_Jh;
+    h[i].Jv = tor[i].d_Jv;
+    h[i].spins = tor[i].d_spins;
+  }
+  return store_words(reinterpret_cast<const uint64_t*>(h.data()),
+                     sizeof(DevTorus) * n / sizeof(uint64_t),
+                     reinterpret_cast<uint64_t*>(static_cast<char*>(ws) + desc_bytes(n)), stream);
 }
 
 int batch_lmax(const tnmc_instance* inst, int32_t n) {
@@ -268,9 +311,12 @@ static tnmc_status propose_common(const tnmc_instance* inst, int32_t n, int32_t 
   if (waves <= 0) waves = tuned_waves(chi, prec, Lmax, n, K);
   hipError_t e = upload_desc(inst, n, chi, K, prec, Use::propose, d_workspace, stream);
   if (e != hipSuccess) return TNMC_EHIP;
-  return hip_status(propose(prec, chi, static_cast<const DevReal*>(d_workspace), n, K, Lmax, seed,
-                            first_proposal, d_teacher, d_spins, d_logq, d_E, d_fallbacks, waves,
-                            stream));
+  e = propose(prec, chi, static_cast<const DevReal*>(d_workspace), n, K, Lmax, seed,
+              first_proposal, d_teacher, d_spins, d_logq, d_E, d_fallbacks, waves, stream);
+  if (e == hipSuccess && d_teacher == nullptr && any_field(inst, n))
+    e = field_energy_launch(static_cast<const DevReal*>(d_workspace), n, K, Lmax, d_spins, d_E,
+                            stream);
+  return hip_status(e);
 }
 
 int32_t tnmc_propose_candidates(int32_t chi, int32_t* waves) {
@@ -378,6 +424,9 @@ tnmc_status tnmc_energy(const tnmc_instance* inst, int32_t n, int32_t K, const u
   hipError_t e = upload_desc(inst, n, 4, 1, TNMC_FP32, Use::none, d_workspace, stream);
   if (e == hipSuccess)
     e = energy_launch(static_cast<const DevReal*>(d_workspace), n, K, Lmax, d_spins, d_E, stream);
+  if (e == hipSuccess && any_field(inst, n))
+    e = field_energy_launch(static_cast<const DevReal*>(d_workspace), n, K, Lmax, d_spins, d_E,
+                            stream);
   return hip_status(e);
 }
 
@@ -446,6 +495,40 @@ tnmc_status tnmc_status_check(const tnmc_instance* inst, int32_t n, uint32_t* h_
     fault = fault || (w[i] & TNMC_ST_FAULTS) != 0;
   }
   return fault ? TNMC_ENUMERIC : TNMC_OK;
+}
+
+size_t tnmc_pbc_workspace_bytes(int32_t n) {
+  if (n < 1) return 0;
+  return desc_bytes(n) + torus_desc_bytes(n);
+}
+
+tnmc_status tnmc_pbc_block(const tnmc_torus* tor, const tnmc_instance* blk, int32_t n,
+                           uint64_t* d_block_spins, void* d_workspace, size_t workspace_bytes,
+                           hipStream_t stream) {
+  const int Lmax = check_tori(tor, blk, n, true);
+  if (Lmax < 0 || d_block_spins == nullptr || d_workspace == nullptr) return TNMC_EINVAL;
+  if (workspace_bytes < tnmc_pbc_workspace_bytes(n)) return TNMC_ENOMEM;
+  hipError_t e = upload_desc(blk, n, 4, 1, TNMC_FP32, Use::none, d_workspace, stream);
+  if (e == hipSuccess) e = upload_tori(tor, n, d_workspace, stream);
+  if (e == hipSuccess)
+    e = pbc_block_launch(reinterpret_cast<const DevTorus*>(static_cast<char*>(d_workspace) +
+                                                           desc_bytes(n)),
+                         static_cast<const DevReal*>(d_workspace), n, Lmax, d_block_spins, stream);
+  return hip_status(e);
+}
+
+tnmc_status tnmc_pbc_merge(const tnmc_torus* tor, const tnmc_instance* blk, int32_t n,
+                           const uint64_t* d_block_spins, int32_t* d_E_torus, void* d_workspace,
+                           size_t workspace_bytes, hipStream_t stream) {
+  const int Lmax = check_tori(tor, blk, n, false);
+  if (Lmax < 0 || d_block_spins == nullptr || d_workspace == nullptr) return TNMC_EINVAL;
+  if (workspace_bytes < tnmc_pbc_workspace_bytes(n)) return TNMC_ENOMEM;
+  hipError_t e = upload_tori(tor, n, d_workspace, stream);
+  if (e == hipSuccess)
+    e = pbc_merge_launch(reinterpret_cast<const DevTorus*>(static_cast<char*>(d_workspace) +
+                                                           desc_bytes(n)),
+                         n, Lmax, d_block_spins, d_E_torus, stream);
+  return hip_status(e);
 }
 
 const char* tnmc_status_string(tnmc_status s) {

@@ -100,6 +100,158 @@ hipError_t energy_launch(const DevReal* d_reals, int n, int K, int Lmax, const u
   return hipGetLastError();
 }
 
+// Field part of the energy, -sum h s over the sites of a realization with fields: one wavefront
+// per configuration (realization slot, proposal), lanes over the columns of each row.
+__global__ void field_energy_kernel(const DevReal* reals, int K, int Lmax, const uint64_t* spins,
+                                    int32_t* E) {
+  const DevReal R = reals[blockIdx.y];
+  if (R.field == nullptr) return;
+  const int lane = threadIdx.x % WAVE;
+  const int k = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  if (k >= K) return;
+  const int L = R.L, Wmax = words_per_row(Lmax);
+  const size_t cfg = size_t(R.slot) * K + k;
+  const uint64_t* s = spins + cfg * Lmax * Wmax;
+  int acc = 0;
+  for (int r = 0; r < L; ++r)
+    for (int c = lane; c < L; c += WAVE) {
+      const int h = R.field[size_t(r) * L + c];
+      const bool neg = (s[size_t(r) * Wmax + (c >> 6)] >> (c & 63)) & 1ull;
+      acc += neg ? h : -h;   // -h s
+    }
+  acc = wave_sum(acc);
+  if (lane == 0) E[cfg] += acc;
+}
+
+hipError_t field_energy_launch(const DevReal* d_reals, int n, int K, int Lmax,
+                               const uint64_t* d_spins, int32_t* d_E, hipStream_t stream) {
+  const int per = 4;   // configurations per workgroup of 256 threads
+  hipLaunchKernelGGL(field_energy_kernel, dim3(unsigned((K + per - 1) / per), n), dim3(per * WAVE),
+                     0, stream, d_reals, K, Lmax, d_spins, d_E);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Periodic lattices by a frozen line pair (Sec. IV).  Block site (a, b) is torus site
+// (R(a), C(b)) = ((r0 + 1 + a) mod L, (c0 + 1 + b) mod L); block bonds are the torus bonds between
+// block sites, and a block site's field is the sum of J s_f over its frozen neighbours f.
+__device__ __forceinline__ int tbit(const uint64_t* row, int c) { return int((row[c >> 6] >> (c & 63)) & 1ull); }
+
+// One workgroup per (torus, block row a); one 64-bit word (or one site of the fields) per thread.
+__global__ void __launch_bounds__(256) pbc_block_kernel(const DevTorus* tor, const DevReal* blk,
+                                                        int Lmax, uint64_t* bspins) {
+  const DevTorus T = tor[blockIdx.y];
+  const DevReal B = blk[blockIdx.y];
+  const int L = T.L, Lb = L - 1, a = blockIdx.x;
+  const int W = words_per_row(L), Wb = words_per_row(Lb), Wmax = words_per_row(Lmax);
+  uint64_t* so = bspins + size_t(blockIdx.y) * Lmax * Wmax + size_t(a) * Wmax;
+  if (a >= Lb) {   // rows past this block's side: zero
+    for (int w = threadIdx.x; w < Wmax; w += blockDim.x) so[w] = 0ull;
+    return;
+  }
+  const int r = (T.r0 + 1 + a) % L, rup = (r + L - 1) % L, rdn = (r + 1) % L;
+  const uint64_t* jh = T.Jh + size_t(r) * W;
+  const uint64_t* jv = T.Jv + size_t(r) * W;
+  const uint64_t* jvup = T.Jv + size_t(rup) * W;
+  const uint64_t* st = T.spins + size_t(r) * W;
+  const uint64_t* stup = T.spins + size_t(rup) * W;
+  const uint64_t* stdn = T.spins + size_t(rdn) * W;
+  uint64_t* bjh = const_cast<uint64_t*>(B.Jh) + size_t(a) * Wb;
+  uint64_t* bjv = const_cast<uint64_t*>(B.Jv) + size_t(a) * Wb;
+  for (int w = threadIdx.x; w < Wmax; w += blockDim.x) {
+    uint64_t wh = 0, wv = 0, ws = 0;
+    for (int u = 0; u < 64; ++u) {
+      const int b = 64 * w + u;
+      if (b >= Lb) break;
+      const int c = (T.c0 + 1 + b) % L;
+      ws |= uint64_t(tbit(st, c)) << u;
+      if (b + 1 < Lb) wh |= uint64_t(tbit(jh, c)) << u;
+      if (a + 1 < Lb) wv |= uint64_t(tbit(jv, c)) << u;
+    }
+    so[w] = ws;
+    if (w < Wb) {
+      bjh[w] = wh;
+      if (a + 1 < Lb) bjv[w] = wv;
+    }
+  }
+  // J s_f = +1 iff the bits of J and s_f agree
+  auto js = [](int bj, int bs) { return (bj ^ bs) ? -1 : 1; };
+  for (int b = threadIdx.x; b < Lb; b += blockDim.x) {
+    const int c = (T.c0 + 1 + b) % L, cl = (c + L - 1) % L, cr = (c + 1) % L;
+    int h = 0;
+    if (rup == T.r0) h += js(tbit(jvup, c), tbit(stup, c));     // above
+    if (rdn == T.r0) h += js(tbit(jv, c), tbit(stdn, c));       // below
+    if (cl == T.c0) h += js(tbit(jh, cl), tbit(st, cl));        // left
+    if (cr == T.c0) h += js(tbit(jh, c), tbit(st, cr));         // right
+    const_cast<int8_t*>(B.field)[size_t(a) * Lb + b] = int8_t(h);
+  }
+}
+
+hipError_t pbc_block_launch(const DevTorus* d_tor, const DevReal* d_blk, int n, int Lmax,
+                            uint64_t* d_block_spins, hipStream_t stream) {
+  hipLaunchKernelGGL(pbc_block_kernel, dim3(Lmax, n), dim3(64), 0, stream, d_tor, d_blk, Lmax,
+                     d_block_spins);
+  return hipGetLastError();
+}
+
+// Block configuration back into the torus: one workgroup per (torus, block row), one torus word
+// per thread (the frozen column's bit kept).
+__global__ void __launch_bounds__(64) pbc_merge_kernel(const DevTorus* tor, int Lmax,
+                                                       const uint64_t* bspins) {
+  const DevTorus T = tor[blockIdx.y];
+  const int L = T.L, Lb = L - 1, a = blockIdx.x;
+  if (a >= Lb) return;
+  const int W = words_per_row(L), Wmax = words_per_row(Lmax);
+  const uint64_t* sb = bspins + size_t(blockIdx.y) * Lmax * Wmax + size_t(a) * Wmax;
+  const int r = (T.r0 + 1 + a) % L;
+  uint64_t* st = T.spins + size_t(r) * W;
+  for (int w = threadIdx.x; w < W; w += blockDim.x) {
+    uint64_t word = st[w];
+    for (int u = 0; u < 64; ++u) {
+      const int c = 64 * w + u;
+      if (c >= L) break;
+      if (c == T.c0) continue;
+      const int b = (c - T.c0 - 1 + L) % L;
+      word = (word & ~(1ull << u)) | (uint64_t(tbit(sb, b)) << u);
+    }
+    st[w] = word;
+  }
+}
+
+// Torus energy E = 2U - 2L^2: one wavefront per torus, lanes over (row, word).
+__global__ void __launch_bounds__(64) torus_energy_kernel(const DevTorus* tor, int32_t* E) {
+  const DevTorus T = tor[blockIdx.x];
+  const int L = T.L, W = words_per_row(L), lane = threadIdx.x;
+  int u = 0;
+  for (int o = lane; o < L * W; o += WAVE) {
+    const int r = o / W, w = o % W;
+    const uint64_t* sr = T.spins + size_t(r) * W;
+    const uint64_t cw = sr[w];
+    // right neighbour of column c is (c + 1) mod L
+    uint64_t right = (cw >> 1) | ((w + 1 < W ? sr[w + 1] : 0ull) << 63);
+    const int last = L - 1;
+    if ((last >> 6) == w) right = (right & ~(1ull << (last & 63))) | (uint64_t(sr[0] & 1ull) << (last & 63));
+    const int nb = L - 64 * w;
+    const uint64_t m = nb >= 64 ? ~0ull : ((1ull << nb) - 1);
+    u += __popcll((cw ^ right ^ T.Jh[size_t(r) * W + w]) & m);
+    u += __popcll((cw ^ T.spins[size_t((r + 1) % L) * W + w] ^ T.Jv[size_t(r) * W + w]) & m);
+  }
+  u = wave_sum(u);
+  if (lane == 0) E[blockIdx.x] = 2 * u - 2 * L * L;
+}
+
+hipError_t pbc_merge_launch(const DevTorus* d_tor, int n, int Lmax, const uint64_t* d_block_spins,
+                            int32_t* d_E_torus, hipStream_t stream) {
+  hipLaunchKernelGGL(pbc_merge_kernel, dim3(Lmax, n), dim3(64), 0, stream, d_tor, Lmax,
+                     d_block_spins);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && d_E_torus != nullptr) {
+    hipLaunchKernelGGL(torus_energy_kernel, dim3(n), dim3(WAVE), 0, stream, d_tor, d_E_torus);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Independence Metropolis: one thread runs one chain over its proposals in order.
 __global__ void accept_kernel(const DevReal* reals, int n, int n_chain, int K,

@@ -642,20 +642,24 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       // also stores the rescaled G_c for the second sweep.
       constexpr int SPT = (2 * CHI * CHI + NT - 1) / NT;
       E lpf[SPT];
+      int lcc = 0;   // the fetched site (its field weights are applied when it is parked)
       auto lfetch = [&](int cc) {
 #pragma unroll
         for (int t = 0; t < SPT; ++t) {
           const int e = tid + NT * t;
           if ((2 * CHI * CHI) % NT == 0 || e < int(site)) lpf[t] = gld<E>(Ain, size_t(cc) * site + e);
         }
+        lcc = cc;
       };
       auto lpark = [&]() {
+        T lg0, lg1;
+        site_field<T>(R, r, lcc, ep, em, lg0, lg1);
 #pragma unroll
         for (int t = 0; t < SPT; ++t) {
           const int e = tid + NT * t;
           if ((2 * CHI * CHI) % NT == 0 || e < int(site)) {
             const int b = e / (CHI * CHI), al = (e / CHI) % CHI, ap = e % CHI;
-            Anx[(b * CHI + al) * LDC + ap] = widen(lpf[t]);
+            Anx[(b * CHI + al) * LDC + ap] = (b ? lg1 : lg0) * widen(lpf[t]);
           }
         }
       };
@@ -902,11 +906,13 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         // only the block (al < bdin[c], ap < bdin[c+1]) of site c of E_r can be nonzero; the
         // rest of AsT is never read
         const int bl = bdin[c], br = bdin[c + 1], blk = bl * br;
+        T fg0, fg1;   // the site's field weights
+        site_field<T>(R, r, c, ep, em, fg0, fg1);
         for (int o = tid; o < 2 * blk; o += NT) {
           const int b = o >= blk ? 1 : 0, rem = o - b * blk;
           const int al = rem / br, ap = rem - al * br;
           AsT[(b * CHI + ap) * LDAT + al] =
-              widen(gld<E>(Ain, size_t(c) * site + size_t(b) * CHI * CHI + al * CHI + ap));
+              (b ? fg1 : fg0) * widen(gld<E>(Ain, size_t(c) * site + size_t(b) * CHI * CHI + al * CHI + ap));
         }
         if (c > 0) {
           T wh2[2][2];   // wh2[a][b]
@@ -1052,18 +1058,23 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     constexpr int GPT = GRAM ? (N2 * N2 + NT - 1) / NT : 1;
     E apf[SPT];
     T gpf[GPT];
+    int acc_site = 0;   // the fetched site (its field weights are applied when it is parked)
     auto fetch_site = [&](int cc) {
 #pragma unroll
       for (int t = 0; t < SPT; ++t) {
         const int e = tid + NT * t;
         if ((2 * CHI * CHI) % NT == 0 || e < int(site)) apf[t] = gld<E>(Ain, size_t(cc) * site + e);
       }
+      acc_site = cc;
     };
     auto park_site = [&]() {
+      T ag0, ag1;
+      site_field<T>(R, r, acc_site, ep, em, ag0, ag1);
 #pragma unroll
       for (int t = 0; t < SPT; ++t) {
         const int e = tid + NT * t;
-        if ((2 * CHI * CHI) % NT == 0 || e < int(site)) Astage[e] = widen(apf[t]);
+        if ((2 * CHI * CHI) % NT == 0 || e < int(site))
+          Astage[e] = (e >= CHI * CHI ? ag1 : ag0) * widen(apf[t]);
       }
     };
     fetch_site(L - 1);
@@ -1786,7 +1797,13 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     __syncthreads();
     const gmem<E>* A0 = env;   // row 0
     const gmem<const uint64_t>* jh0 = as_global(R.Jh);
-    for (int o = tid; o < 2 * CHI; o += NT) sc[o] = widen(gld<E>(A0, (o / CHI) * CHI * CHI + (o % CHI)));
+    // (row 0's fields, if any, weight each site of E_0 by exp(beta h s))
+    {
+      T g0, g1;
+      site_field<T>(R, 0, 0, ep, em, g0, g1);
+      for (int o = tid; o < 2 * CHI; o += NT)
+        sc[o] = (o >= CHI ? g1 : g0) * widen(gld<E>(A0, (o / CHI) * CHI * CHI + (o % CHI)));
+    }
     double logacc = 0;
     for (int c = 1; c < L; ++c) {
       __syncthreads();
@@ -1794,12 +1811,15 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       T mx = 0, val = 0;
       if (tid < 2 * CHI) {
         const int sp = tid / CHI, be = tid % CHI;
+        T g0, g1;
+        site_field<T>(R, 0, c, ep, em, g0, g1);
         for (int s2 = 0; s2 < 2; ++s2) {
           const T w = bond_weight<T>(jh0, c - 1, s2, sp, ep, em);
           T dd = 0;
           for (int al = 0; al < CHI; ++al) dd += sc[s2 * CHI + al] * widen(gld<E>(A, (sp * CHI + al) * CHI + be));
           val += w * dd;
         }
+        val *= sp ? g1 : g0;
         mx = fabs(val);
       }
       mx = block_max<NT>(mx, red);

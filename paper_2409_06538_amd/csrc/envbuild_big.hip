@@ -185,10 +185,13 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
 
   // exp(beta J s s') for the bond whose coupling bit is `af`; spin index 0 <-> +1, 1 <-> -1
   auto w = [&](bool af, int s, int t) { return ((s == t) != af) ? ep : em; };
-  auto stage = [&](const gmem<E>* src, int l, int m) {   // site -> sA[b][al][be], al < l, be < m
+  // site c of E_r -> sA[b][al][be], al < l, be < m, times the site's field weights exp(beta h b)
+  auto stage = [&](const gmem<E>* src, int l, int m, int r, int c) {
+    T g0, g1;
+    site_field<T>(R, r, c, ep, em, g0, g1);
     for (int o = tid; o < 2 * l * m; o += NT) {
       const int b = o / (l * m), al = (o / m) % l, be = o % m;
-      sA[(b * CHI + al) * LDA + be] = T(widen(gld<E>(src, (b * CHI + al) * CHI + be)));
+      sA[(b * CHI + al) * LDA + be] = (b ? g1 : g0) * T(widen(gld<E>(src, (b * CHI + al) * CHI + be)));
     }
   };
   // Write one whole site (2 CHI^2 entries, the zero padding included) in 16-byte stores:
@@ -528,7 +531,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
     // ------------------------------ left to right: Gram matrices ------------------------------
     for (int c = 0; c <= L - 2 && !ZIP; ++c) {
       const int l = bdin[c], m = bdin[c + 1];
-      stage(Ain + size_t(c) * site, l, m);
+      stage(Ain + size_t(c) * site, l, m, r, c);
       const bool fv = vbit(c);
       T kx[2][2];
       for (int b = 0; b < 2; ++b)
@@ -596,7 +599,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
     for (int c = L - 1; c >= 1; --c) {
       const int l = bdin[c], m = bdin[c + 1], k = bdout[c + 1];
       const bool fh = hbit(c - 1), fv = vbit(c);
-      stage(Ain + size_t(c) * site, l, m);
+      stage(Ain + size_t(c) * site, l, m, r, c);
       __syncthreads();
       const gmem<T>* X = Xs + size_t(xb) * N2 * CHI;
       // Z_c[(a,al),(x,be)] = sum_b wh(a,b) wv(x,b) (A_c[b] Xt^(b))[al][be], both b in one tile loop
@@ -681,7 +684,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
     {
       const int m = bdin[1], k = bdout[1];
       const bool fv = vbit(0);
-      stage(Ain, 1, m);
+      stage(Ain, 1, m, r, 0);
       __syncthreads();
       const gmem<T>* X = Xs + size_t(xb) * N2 * CHI;
       T part = 0;
@@ -721,7 +724,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       const int l = bdin[c], m = bdin[c + 1], k = bdout[c];
       const bool fv = vbit(c);
       const bool fh = c > 0 ? hbit(c - 1) : false;
-      stage(Ain + size_t(c) * site, l, m);
+      stage(Ain + size_t(c) * site, l, m, r, c);
       __syncthreads();
       const gmem<T>* Ct = Xs + size_t(xb) * N2 * CHI;
       {
@@ -831,7 +834,13 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
     const gmem<E>* A0 = env;
     const gmem<const uint64_t>* jh0 = as_global(R.Jh);
     T* sc = vec;   // 2 CHI: running vector v[sigma][be]
-    for (int o = tid; o < 2 * CHI; o += NT) sc[o] = T(widen(gld<E>(A0, (o / CHI) * CHI * CHI + (o % CHI))));
+    // (row 0's fields, if any, weight each site of E_0 by exp(beta h s))
+    {
+      T g0, g1;
+      site_field<T>(R, 0, 0, ep, em, g0, g1);
+      for (int o = tid; o < 2 * CHI; o += NT)
+        sc[o] = (o >= CHI ? g1 : g0) * T(widen(gld<E>(A0, (o / CHI) * CHI * CHI + (o % CHI))));
+    }
     double logacc = 0;
     for (int c = 1; c < L; ++c) {
       __syncthreads();
@@ -840,12 +849,15 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       T mxv = 0, val = 0;
       if (tid < 2 * CHI) {
         const int sp = tid / CHI, be = tid % CHI;
+        T g0, g1;
+        site_field<T>(R, 0, c, ep, em, g0, g1);
         for (int s2 = 0; s2 < 2; ++s2) {
           const T wgt = w(fh, s2, sp);
           T dd = 0;
           for (int al = 0; al < CHI; ++al) dd += sc[s2 * CHI + al] * T(widen(gld<E>(A, (sp * CHI + al) * CHI + be)));
           val += wgt * dd;
         }
+        val *= sp ? g1 : g0;
         mxv = fabs(val);
       }
       mxv = block_max<NT>(mxv, red);

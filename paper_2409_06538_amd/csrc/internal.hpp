@@ -22,7 +22,41 @@ struct DevReal {
   void* ws;   // this realization's slice of the workspace (call-specific use)
   uint32_t* status;   // numeric status word (TNMC_ST_* bits) or nullptr
   uint8_t* bonds;     // L x (L + 1) bond dimensions of the stored environments, or nullptr
+  const int8_t* field;   // L x L integer site fields, or nullptr
 };
+
+// Device-side descriptor of one torus (periodic lattice) and its frozen lines.
+struct DevTorus {
+  int L, r0, c0, pad;
+  const uint64_t* Jh;
+  const uint64_t* Jv;
+  uint64_t* spins;
+};
+
+// exp(beta h s) of an integer site field h for s = +1 (g0) and s = -1 (g1), from ep = e^beta and
+// em = e^-beta (|h| <= 4 multiplications)
+template <typename T>
+__device__ __forceinline__ void field_weights(int h, T ep, T em, T& g0, T& g1) {
+  const T u = h > 0 ? ep : em, v = h > 0 ? em : ep;
+  T a = T(1), b = T(1);
+  for (int k = 0, m = h < 0 ? -h : h; k < m; ++k) {
+    a *= u;
+    b *= v;
+  }
+  g0 = a;
+  g1 = b;
+}
+
+// The weights of site (r, c) of a realization (1 without a field).
+template <typename T>
+__device__ __forceinline__ void site_field(const DevReal& R, int r, int c, T ep, T em, T& g0, T& g1) {
+  g0 = T(1);
+  g1 = T(1);
+  if (R.field != nullptr) {
+    const int h = R.field[size_t(r) * R.L + c];
+    if (h != 0) field_weights<T>(h, ep, em, g0, g1);
+  }
+}
 
 hipError_t couplings_launch(const DevReal* d_reals, int n, const uint64_t* d_seeds, double p,
                             int Lmax, hipStream_t stream);
@@ -48,6 +82,15 @@ size_t propose_scratch_bytes(tnmc_precision prec, int chi, int L, int K);
 
 hipError_t energy_launch(const DevReal* d_reals, int n, int K, int Lmax, const uint64_t* d_spins,
                          int32_t* d_E, hipStream_t stream);
+// adds -sum h s to d_E [n][K] for the realizations with fields
+hipError_t field_energy_launch(const DevReal* d_reals, int n, int K, int Lmax,
+                               const uint64_t* d_spins, int32_t* d_E, hipStream_t stream);
+
+// Lmax: the largest block side (the row count of one block configuration in d_block_spins)
+hipError_t pbc_block_launch(const DevTorus* d_tor, const DevReal* d_blk, int n, int Lmax,
+                            uint64_t* d_block_spins, hipStream_t stream);
+hipError_t pbc_merge_launch(const DevTorus* d_tor, int n, int Lmax, const uint64_t* d_block_spins,
+                            int32_t* d_E_torus, hipStream_t stream);
 
 hipError_t accept_launch(const DevReal* d_reals, int n, int n_chain, int K, int Lmax,
                          const uint64_t* d_prop_spins, const double* d_prop_logq,

@@ -4,6 +4,7 @@
 // Row r of a proposal is drawn from the row chain
 //   f_r(y) = prod_c phi_c(y_c) prod_c w_c(y_c, y_{c+1}) E_r(y),
 //   phi_c(y) = exp(beta Jv[r-1][c] s[r-1][c] y),  w_c(y, y') = exp(beta Jh[r][c] y y'),
+//   (phi_c also carries exp(beta h[r][c] y) for a realization with site fields),
 // exactly marginalised column by column:
 //   right sweep (c = L-1 .. 0):  v_c(y) = B_c[y] R_c(y),  R_{c-1}(y) = sum_y' w_{c-1}(y,y') phi_c(y') v_c(y'),
 //   left sweep  (c = 0 .. L-1):  Z_c(y) = [w_{c-1}(s_{c-1}, y)] phi_c(y) (l . v_c(y)),  draw s_c,
@@ -104,6 +105,12 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
 #pragma unroll
           for (int yp = 0; yp < 2; ++yp) ph[yp] = spin_weight<T>(af, (yp == 1) == sm, ep, em);
         }
+        if (R.field != nullptr) {   // the site's field, exp(beta h y')
+          T g0, g1;
+          site_field<T>(R, r, c, ep, em, g0, g1);
+          ph[0] *= g0;
+          ph[1] *= g1;
+        }
         const bool afh = (jh[(c - 1) >> 6] >> ((c - 1) & 63)) & 1ull;
         const T wpp = spin_weight<T>(afh, true, ep, em), wpm = spin_weight<T>(afh, false, ep, em);
         T mx = 0;
@@ -140,6 +147,12 @@ __global__ __launch_bounds__(PROP_NT) void propose_kernel(const DevReal* reals, 
         const bool sm = (prev[(c >> 6) * PROP_NT] >> (c & 63)) & 1ull;
 #pragma unroll
         for (int y = 0; y < 2; ++y) pre[y] = spin_weight<T>(af, (y == 1) == sm, ep, em);
+      }
+      if (R.field != nullptr) {
+        T g0, g1;
+        site_field<T>(R, r, c, ep, em, g0, g1);
+        pre[0] *= g0;
+        pre[1] *= g1;
       }
       if (c > 0) {
         const bool afh = (jh[(c - 1) >> 6] >> ((c - 1) & 63)) & 1ull;
@@ -516,6 +529,12 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
           ph[0] = spin_weight<T>(af, !sm, ep, em);
           ph[1] = spin_weight<T>(af, sm, ep, em);
         }
+        if (R.field != nullptr) {   // the site's field, exp(beta h y)
+          T g0, g1;
+          site_field<T>(R, r, c, ep, em, g0, g1);
+          ph[0] *= g0;
+          ph[1] *= g1;
+        }
         const bool afh = (jh[(c - 1) >> 6] >> ((c - 1) & 63)) & 1ull;
         const T wpp = spin_weight<T>(afh, true, ep, em), wpm = spin_weight<T>(afh, false, ep, em);
         T mx = 0;
@@ -578,6 +597,12 @@ __global__ __launch_bounds__(64 * MF_WAVES) void propose_mfma_kernel(const DevRe
         const bool sm = (prow[(c >> 6) * MF_PROP] >> (c & 63)) & 1ull;
         pre[0] = spin_weight<T>(af, !sm, ep, em);
         pre[1] = spin_weight<T>(af, sm, ep, em);
+      }
+      if (R.field != nullptr) {
+        T g0, g1;
+        site_field<T>(R, r, c, ep, em, g0, g1);
+        pre[0] *= g0;
+        pre[1] *= g1;
       }
       if (c > 0) {
         const bool afh = (jh[(c - 1) >> 6] >> ((c - 1) & 63)) & 1ull;

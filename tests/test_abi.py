@@ -84,6 +84,7 @@ def test_short_workspace_is_enomem_on_every_entry_point(lib):
         tab[i].L, tab[i].beta, tab[i].id = L, 0.9, i
         tab[i].d_Jh = tab[i].d_Jv = tab[i].d_env = tab[i].d_lognorm = 1 << 20
     seeds = (ctypes.c_uint64 * 2)(0, 1)
+    tori, btab = _tori(binding, (17, 41))
     short = 8
     enomem = -2
     calls = {
@@ -104,12 +105,54 @@ def test_short_workspace_is_enomem_on_every_entry_point(lib):
                                                fake, fake, fake, fake, None, fake, short, None),
         "tnmc_observables": lambda: lib.tnmc_observables(tab, 2, 1, fake, fake, fake, fake, short,
                                                          None),
+        "tnmc_pbc_block": lambda: lib.tnmc_pbc_block(tori, btab, 2, fake, fake, short, None),
+        "tnmc_pbc_merge": lambda: lib.tnmc_pbc_merge(tori, btab, 2, fake, None, fake, short, None),
     }
     takes_workspace = [n for n in declared_symbols()
                        if "workspace_bytes" in header_signature(n) and n != "tnmc_workspace_bytes"]
     assert sorted(calls) == sorted(takes_workspace)
     for name, call in calls.items():
         assert call() == enomem, name
+
+
+def _tori(binding, Ls):
+    """Torus descriptors and their block instances with placeholder device pointers (never
+    dereferenced: every call below returns before anything is enqueued)."""
+    tori = (binding.TorusDesc * len(Ls))()
+    btab = (binding.Instance * len(Ls))()
+    for i, L in enumerate(Ls):
+        tori[i].L, tori[i].r0, tori[i].c0 = L, i, L - 1
+        tori[i].d_Jh = tori[i].d_Jv = tori[i].d_spins = 1 << 20
+        btab[i].L, btab[i].beta, btab[i].id = L - 1, 0.9, i
+        btab[i].d_Jh = btab[i].d_Jv = btab[i].d_field = 1 << 20
+    return tori, btab
+
+
+def test_pbc_arguments_host_side(lib):
+    """tnmc_pbc_block / tnmc_pbc_merge reject, on the host, a block whose side is not L - 1,
+    frozen lines outside the torus, L < 3 and a block without a field buffer."""
+    from paper_2409_06538_amd import binding
+    fake = ctypes.c_void_p(1 << 20)
+    nb = lib.tnmc_pbc_workspace_bytes(2)
+    assert nb > 0 and lib.tnmc_pbc_workspace_bytes(0) == 0
+    cases = []
+    tori, btab = _tori(binding, (9, 12))
+    btab[1].L = 12
+    cases.append((tori, btab))
+    tori, btab = _tori(binding, (9, 12))
+    tori[0].r0 = 9
+    cases.append((tori, btab))
+    tori, btab = _tori(binding, (9, 12))
+    tori[1].c0 = -1
+    cases.append((tori, btab))
+    tori, btab = _tori(binding, (2, 12))
+    cases.append((tori, btab))
+    for tori, btab in cases:
+        assert lib.tnmc_pbc_block(tori, btab, 2, fake, fake, nb, None) == -1
+        assert lib.tnmc_pbc_merge(tori, btab, 2, fake, None, fake, nb, None) == -1
+    tori, btab = _tori(binding, (9, 12))
+    btab[0].d_field = None
+    assert lib.tnmc_pbc_block(tori, btab, 2, fake, fake, nb, None) == -1
 
 
 def header_signature(name):

@@ -1,0 +1,230 @@
+"""Site fields and periodic lattices by a frozen line pair (Sec. IV; Sec. I) through the C ABI,
+against the oracle (oracle.pbc, and envbuild / sampler / energy with field=h).
+
+* the open block of a torus (couplings, fields, configuration), the merge back and the torus
+  energy: bit-exact;
+* environments, ln Z and proposals of a lattice with fields, in every build form: FP64 log-norms
+  and log q within 1e-10 and spins bit-exact; FP32 within 1e-5 / 1e-4; BF16 within 5e-3;
+  energies (fields included) exact;
+* whole steps in FP64 (with rejections): the torus configurations and accept decisions of each
+  step equal the oracle's;
+* a chain of steps reproduces the exact torus energy histogram of a 4 x 4 torus.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+import synth
+from oracle import energy as o_energy
+from oracle import envbuild as o_env
+from oracle import exact as o_exact
+from oracle import pbc as o_pbc
+from oracle import sampler as o_samp
+
+pytestmark = pytest.mark.gpu
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(np.asarray(b)), 1e-300)
+
+
+def packed(pm1, W):
+    w = synth.pack_rows(pm1)
+    out = np.zeros(w.shape[:-1] + (W,), dtype=np.uint64)
+    out[..., :w.shape[-1]] = w
+    return out
+
+
+def torus_case(seed, L, p=0.109):
+    Jh_t, Jv_t = synth.torus_couplings(seed, L, p)
+    s_t = synth.random_spins(seed + 1000, 1, L)[0]
+    return Jh_t, Jv_t, s_t
+
+
+def make_pbc(L, n, chi, precision, K, beta, seeds, p=0.109):
+    from paper_2409_06538_amd import binding
+    P = binding.PBC(L, n, [beta] * n, list(range(n)), chi, precision, K=K)
+    W = synth.words_per_row(L)
+    cases = []
+    for i in range(n):
+        Jh_t, Jv_t, s_t = torus_case(seeds[i], L, p)
+        P.set_torus(i, packed(Jh_t, W), packed(Jv_t, W), packed(s_t, W))
+        cases.append((Jh_t, Jv_t, s_t))
+    return P, cases
+
+
+@pytest.mark.parametrize("L", [3, 5, 64, 66, 130])
+def test_block_merge_and_torus_energy_bit_exact(tnmc_gpu, L):
+    import torch
+    n = 3
+    P, cases = make_pbc(L, n, 4, "fp32", 1, 0.9, [11 * L + i for i in range(n)])
+    lines = synth.frozen_lines(L, n, L)
+    P.set_lines(lines)
+    P.block()
+    Lb = L - 1
+    Wb = synth.words_per_row(Lb)
+    blocks = []
+    for i, (Jh_t, Jv_t, s_t) in enumerate(cases):
+        Jh, Jv, h, s_b = o_pbc.block(Jh_t, Jv_t, s_t, int(lines[i][0]), int(lines[i][1]))
+        b = P.batch
+        np.testing.assert_array_equal(host(b.Jh[i]).view(np.uint64).reshape(Lb, Wb), packed(Jh, Wb))
+        np.testing.assert_array_equal(host(b.Jv[i]).view(np.uint64).reshape(Lb - 1, Wb),
+                                      packed(Jv, Wb))
+        np.testing.assert_array_equal(host(b.field[i]).reshape(Lb, Lb), h)
+        np.testing.assert_array_equal(host(P.chains["spins"])[i, 0].view(np.uint64), packed(s_b, Wb))
+        blocks.append(synth.random_spins(5 * L + i, 1, Lb)[0])
+    # a new block configuration merged back, and the torus energy
+    words = np.stack([packed(bl, Wb) for bl in blocks])[:, None]
+    P.chains["spins"].copy_(torch.from_numpy(words.view(np.int64)).to(P.device))
+    P.merge()
+    W = synth.words_per_row(L)
+    E = host(P.E)
+    for i, (Jh_t, Jv_t, s_t) in enumerate(cases):
+        new = o_pbc.merge(s_t, blocks[i], int(lines[i][0]), int(lines[i][1]))
+        np.testing.assert_array_equal(host(P.spins[i]).view(np.uint64).reshape(L, W), packed(new, W))
+        assert E[i] == o_pbc.torus_energy(new[None], Jh_t, Jv_t)[0]
+
+
+# (precision, chi, torus side, build form); the block is (L-1) x (L-1) with boundary fields
+FIELD_CASES = [("fp64", 8, 13, 0), ("fp32", 16, 17, 0), ("fp32", 48, 21, 0), ("bf16", 32, 25, 0),
+               ("bf16", 64, 17, 0), ("fp32", 16, 17, 1), ("fp32", 16, 17, 2)]
+TOL = {"fp64": (1e-10, 1e-10), "fp32": (1e-5, 1e-4), "bf16": (5e-3, 5e-3)}
+
+
+@pytest.mark.parametrize("precision,chi,L,form", FIELD_CASES)
+def test_fields_env_and_proposals(tnmc_gpu, precision, chi, L, form):
+    from paper_2409_06538_amd import binding
+    n, K, seed = 2, 48, 3
+    beta = binding.nishimori_beta(0.109)
+    P, cases = make_pbc(L, n, chi, precision, K, beta, [7 * L + i for i in range(n)])
+    lines = synth.frozen_lines(L + 1, n, L)
+    P.set_lines(lines)
+    P.block()
+    b = P.batch
+    lnZ = host(b.build_env_form(form))
+    st, words = b.status_check()
+    assert st == 0, words
+    spins, logq, E = b.propose(K, seed)
+    tol_env, tol_q = TOL[precision]
+    method = "zipup" if form == binding.FORM_ZIPUP else "canonical"
+    Lb = L - 1
+    for i, (Jh_t, Jv_t, s_t) in enumerate(cases):
+        Jh, Jv, h, s_b = o_pbc.block(Jh_t, Jv_t, s_t, int(lines[i][0]), int(lines[i][1]))
+        assert np.abs(h).sum() > 0
+        env = o_env.build_env(Jh, Jv, beta, chi, method=method, field=h)
+        r_lam = np.max(rel(host(b.lognorm[i]), env["lognorm"]))
+        print(f"{precision} chi={chi} L={L} form={form} torus {i}: lnZ rel "
+              f"{rel(lnZ[i], env['lnZ']):.2e}, lambda max rel {r_lam:.2e}", flush=True)
+        assert rel(lnZ[i], env["lnZ"]) < tol_env
+        assert r_lam < tol_env
+        sp = synth.unpack_rows(host(spins)[i].view(np.uint64)[:, :Lb, :], Lb)
+        np.testing.assert_array_equal(host(E)[i], o_energy.energy(sp, Jh, Jv, field=h))
+        if precision == "fp64":
+            ref = o_samp.run(env, Jh, Jv, beta, K=K, seed=seed, realization=i, field=h)
+            np.testing.assert_array_equal(sp, ref["spins"])
+            r = rel(host(logq)[i], ref["logq"])
+        else:
+            ref = o_samp.run(env, Jh, Jv, beta, teacher=sp, field=h)
+            r = rel(host(logq)[i], ref["logq"])
+        print(f"  log q of GPU proposals: max rel {np.max(r):.2e}, median {np.median(r):.2e}",
+              flush=True)
+        if precision == "bf16":
+            assert np.median(r) < tol_q and np.max(r) < 10 * tol_q
+        else:
+            assert np.max(r) < tol_q
+    np.testing.assert_array_equal(host(b.logq(spins)), host(logq))
+
+
+def test_random_fields_everywhere_fp64_exact_regime(tnmc_gpu):
+    """A partial block with a field on every site (|h| <= 4), exact chi: ln Z against brute
+    force enumeration and log q = log P for GPU proposals."""
+    import torch
+    from paper_2409_06538_amd import binding
+    from oracle import instance as o_inst
+    L, chi, K, beta = 4, 4, 64, 0.7
+    b = binding.Batch([L], [beta], [0], chi, "fp64", K=K, fields=True)
+    b.make_couplings([21], 0.3)
+    Jh, Jv = o_inst.couplings(21, L, 0.3)
+    h = np.random.default_rng(5).integers(-4, 5, size=(L, L)).astype(np.int8)
+    b.set_field(0, h)
+    lnZ = host(b.build_env())[0]
+    bf = o_exact.brute_force(Jh, Jv, beta, field=h)
+    assert rel(lnZ, bf["lnZ"]) < 1e-12
+    spins, logq, E = b.propose(K, 2)
+    sp = synth.unpack_rows(host(spins)[0].view(np.uint64)[:, :L, :], L)
+    idx = np.array([int(sum((1 << (r * L + c)) for r in range(L) for c in range(L) if s[r, c] < 0))
+                    for s in sp])
+    np.testing.assert_allclose(host(logq)[0], bf["logP"][idx], rtol=0, atol=1e-11)
+    np.testing.assert_array_equal(host(E)[0], bf["E"][idx])
+    assert torch.equal(b.energy(spins), E)
+
+
+def test_steps_fp64_match_oracle(tnmc_gpu):
+    """Whole steps (block, build, proposals, current log q and energy, accept, merge) on two
+    15 x 15 tori with chi = 2 (truncated: about a third of the proposals are rejected): the
+    configurations and accept decisions equal the oracle's after every step."""
+    L, n, chi, K, seed, beta = 15, 2, 2, 12, 4, 1.3
+    P, cases = make_pbc(L, n, chi, "fp64", K, beta, [31 + i for i in range(n)], p=0.25)
+    states = [c[2].copy() for c in cases]
+    W = synth.words_per_row(L)
+    rejected = 0
+    for t in range(4):
+        lines = synth.frozen_lines(100 + t, n, L)
+        acc, _ = P.step(lines, K, seed, first_proposal=K * t, first_step=K * t)
+        acc = host(acc)
+        for i, (Jh_t, Jv_t, _) in enumerate(cases):
+            states[i], info = o_pbc.step(Jh_t, Jv_t, states[i], beta, chi, int(lines[i][0]),
+                                         int(lines[i][1]), K, seed=seed, realization=i,
+                                         first_proposal=K * t, first_step=K * t)
+            np.testing.assert_array_equal(acc[i].astype(bool), info["chain"]["accepted"])
+            np.testing.assert_array_equal(host(P.spins[i]).view(np.uint64).reshape(L, W),
+                                          packed(states[i], W))
+            assert host(P.E)[i] == o_pbc.torus_energy(states[i][None], Jh_t, Jv_t)[0]
+        print(f"step {t}: accepted {acc.sum()} of {n * K}", flush=True)
+        rejected += n * K - int(acc.sum())
+    assert rejected > 0
+
+
+def test_chain_reproduces_torus_energy_histogram(tnmc_gpu):
+    """64 chains on one 4 x 4 torus, chi = 2 on the 3 x 3 blocks (FP32; exact for three
+    columns, so every proposal is accepted: the steps are block heat-bath updates): the torus
+    energies after each step follow the exact Boltzmann histogram of the periodic lattice."""
+    L, n, chi, K, steps, beta = 4, 64, 2, 4, 200, 0.7
+    from paper_2409_06538_amd import binding
+    P = binding.PBC(L, n, [beta] * n, list(range(n)), chi, "fp32", K=K)
+    Jh_t, Jv_t = synth.torus_couplings(5, L, 0.25)
+    W = synth.words_per_row(L)
+    init = synth.random_spins(9, n, L)
+    for i in range(n):
+        P.set_torus(i, packed(Jh_t, W), packed(Jv_t, W), packed(init[i], W))
+    Es, acc = [], 0
+    for t in range(steps):
+        a, _ = P.step(synth.frozen_lines(1000 + t, n, L), K, 3, first_proposal=K * t,
+                      first_step=K * t)
+        acc += int(host(a).sum())
+        if t >= 10:
+            Es.append(host(P.E).copy())
+    Es = np.concatenate(Es)
+    pa = acc / (n * K * steps)
+    allc = o_exact.all_configs(L, L)
+    Eall = o_pbc.torus_energy(allc, Jh_t, Jv_t)
+    lw = -beta * Eall.astype(np.float64)
+    Pw = np.exp(lw - lw.max())
+    Pw /= Pw.sum()
+    levels = np.unique(Eall)
+    Pl = np.array([Pw[Eall == e].sum() for e in levels])
+    counts = np.array([np.count_nonzero(Es == e) for e in levels], dtype=np.float64)
+    expected = len(Es) * Pl
+    keep = expected > 10
+    chi2 = float(np.sum((counts[keep] - expected[keep]) ** 2 / expected[keep])) / 4.0
+    pval = stats.chi2.sf(chi2, df=int(keep.sum()) - 1)
+    print(f"p_a {pa:.3f}, samples {len(Es)}, chi2/4 {chi2:.1f}, p {pval:.3g}, mean E "
+          f"{Es.mean():.3f} exact {(Pw * Eall).sum():.3f}", flush=True)
+    assert pa > 0.999
+    assert pval > 1e-4

@@ -995,6 +995,54 @@ def sweep_forms_point(L, chi, precision, n_real, K, p=0.109, seed=0):
             "lnZ_rel_diff_max": d.max().item(), "lnZ_rel_diff_mean": d.mean().item()}
 
 
+# (torus side, chi, precision, tori, proposals per step, steps) of the periodic-lattice sweep
+SWEEP_PBC = ((17, 16, "fp32", 64, 256, 8), (65, 32, "fp32", 64, 1000, 6),
+             (129, 32, "fp32", 16, 256, 5), (257, 48, "bf16", 16, 256, 4))
+
+
+def sweep_pbc_point(L, chi, precision, n, K, steps, p=0.109, seed=0):
+    """f4: periodic L x L lattices stepped by a frozen row and column per step (Sec. IV), one
+    chain per torus: per step the block of (L-1)^2 spins is built, sampled and accepted against.
+    Reports the step time (HIP events), the acceptance, accepted block spin-updates/s, and the
+    Nishimori-line check of the torus energy, [<E>] = -2 L^2 (1 - 2p), over the steps after the
+    first two."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2409_06538_amd import binding
+    dev = torch.device("cuda:0")
+    beta = binding.nishimori_beta(p)
+    P = binding.PBC(L, n, [beta] * n, list(range(n)), chi, precision, K=K, device=dev)
+    W = synth.words_per_row(L)
+    init = synth.random_spins(seed + 77, n, L)
+    for i in range(n):
+        Jh_t, Jv_t = synth.torus_couplings(seed + i, L, p)
+        P.set_torus(i, synth.pack_rows(Jh_t), synth.pack_rows(Jv_t), synth.pack_rows(init[i]))
+    lines = [synth.frozen_lines(seed + 1000 + t, n, L) for t in range(steps + 1)]
+    progress(f"pbc L={L} chi={chi} {precision}: warm-up step")
+    P.step(lines[0], K, seed, first_proposal=0, first_step=0)   # untimed (first launches)
+    ms, acc, Es = [], [], []
+    for t in range(1, steps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        a, _ = P.step(lines[t], K, seed, first_proposal=K * t, first_step=K * t)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        acc.append(a.float().sum().item())
+        Es.append(P.E.cpu().numpy().astype(np.float64))
+        progress(f"pbc L={L} step {t}: {ms[-1]:.1f} ms, accepted {acc[-1]:.0f}")
+    st, _ = P.batch.status_check()
+    E = np.array(Es[1:]).mean(axis=0)            # per-torus mean over the steps after the first two
+    step_ms = float(np.mean(ms))
+    return {"sweep": "pbc", "L": L, "block": L - 1, "chi": chi, "p": p, "precision": precision,
+            "tori": n, "proposals": K, "steps": steps, "ms_per_step": step_ms,
+            "acceptance": float(np.sum(acc)) / (n * K * steps),
+            "accepted_spin_updates_per_s": float(np.mean(acc)) * (L - 1) ** 2 / (step_ms * 1e-3),
+            "E_mean": float(E.mean()), "E_err": float(E.std(ddof=1) / np.sqrt(n)),
+            "E_nishimori": -2 * L * L * (1 - 2 * p), "status": st}
+
+
 def run_observables(args, L, chi, p, n_real, K, n_chain=2):
     """f1: the sampled quantities of Sec. III C through the GPU chains, disorder-averaged on the
     GPU (Q_q, chi_q, chi_edge), with the Nishimori-line check [<E>] = -N_B (1 - 2p)."""
@@ -1037,7 +1085,10 @@ def run_sweep(args):
       observables      Q_q, chi_q, chi_edge (Sec. III C) at the multicritical point p = 0.10926,
                        L = 8 .. 64, chi = 32, 128 realizations, two chains of 256 steps
       forms            canonical compression against the zip-up on the same batches (Sec. II B
-                       variants): build time, kept bonds, ln Z, acceptance"""
+                       variants): build time, kept bonds, ln Z, acceptance
+      pbc              periodic lattices by a frozen line pair per step (Sec. IV): step time,
+                       acceptance, accepted spin-updates/s and the Nishimori check of the torus
+                       energy"""
     if args.sweep == "acceptance_cost":
         for chi in SWEEP_CHIS:
             for L in SWEEP_LS:
@@ -1057,6 +1108,10 @@ def run_sweep(args):
     elif args.sweep == "forms":
         for L, chi, prec, n_real, K in SWEEP_FORMS:
             print(json.dumps(sweep_forms_point(L, chi, prec, n_real, K, seed=args.seed)),
+                  flush=True)
+    elif args.sweep == "pbc":
+        for L, chi, prec, n, K, steps in SWEEP_PBC:
+            print(json.dumps(sweep_pbc_point(L, chi, prec, n, K, steps, seed=args.seed)),
                   flush=True)
 
 
@@ -1093,7 +1148,8 @@ def main():
     ap.add_argument("--builds-in-flight", type=int, default=2, choices=[1, 2],
                     help="overlapped steps: environment builds of later steps running at once")
     ap.add_argument("--sweep", default=None,
-                    choices=["acceptance_cost", "nishimori", "large_L", "observables", "forms"],
+                    choices=["acceptance_cost", "nishimori", "large_L", "observables", "forms",
+                             "pbc"],
                     help="one JSON line per point instead of the benchmark line: acceptance and "
                          "cost against L and chi; against the temperature along the Nishimori "
                          "line; at L = 512 and 1024; or the disorder-averaged Binder ratio and "

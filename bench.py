@@ -70,9 +70,9 @@ def proposals_per_wg(precision, n, K, Lmax):
 # for the kernel sources they were taken on: reported as null once those change (SHA-256).
 COUNTERS = {
     ('rbim1024', 'bf16', 'env_build'): {
-        "fetch_kib": 19796019.416666668,
-        "fetch_factor": 1.9999265697737347,
-        "write_kib": 107822654.28125,
+        "fetch_kib": 19791756.125,
+        "fetch_factor": 1.9999215633637493,
+        "write_kib": 107822896.0625,
         "write_factor": 1.0,
         "mfma_mops": {
             "f64": 0.0,
@@ -80,17 +80,17 @@ COUNTERS = {
             "bf16": 0.0
         },
         "mfma_busy_cycles": 12553226880.0,
-        "gui_active_cycles": 327452175929.6667,
+        "gui_active_cycles": 327197643153.3333,
         "sources_sha256": {
-            "envbuild_big.hip": "c579760cf111633f06dc068f76d6a0767aa6bb1ca7e98bea6104497f3b700bf6",
-            "envbuild.hip": "46f0da52b8c90096db817501aa8229268eb911bf2a310a9b8119f6b54bba5959",
+            "envbuild_big.hip": "d6209715394e95d4116bd132216b20fc5332447b129ff980638cbc8edb6fe23a",
+            "envbuild.hip": "d97c38100d1f5525e3885a57b0b45f8f9c3c24d3e100170ee22714174da530d1",
             "common.hpp": "373c1289408779effdb76fff0cb18b389447af9368a0c2b3675272823aa4c649",
-            "internal.hpp": "97fb840f4a6670c01adfdf9b0f7c6d1bfe125917d858b7d13bb0a71048c27c79"
+            "internal.hpp": "3d0517399abdfb569676091d83432670ac9227b5acd41f4e53100848669d982a"
         }
     },
     ('rbim1024', 'bf16', 'propose'): {
-        "fetch_kib": 205230812.23295453,
-        "fetch_factor": 1.9999265697737347,
+        "fetch_kib": 205306683.9943182,
+        "fetch_factor": 1.9999215633637493,
         "write_kib": 277552281.70454544,
         "write_factor": 1.0,
         "mfma_mops": {
@@ -99,11 +99,11 @@ COUNTERS = {
             "bf16": 0.0
         },
         "mfma_busy_cycles": 80061300736.0,
-        "gui_active_cycles": 97613679168.90909,
+        "gui_active_cycles": 98373586976.45454,
         "sources_sha256": {
-            "sampler.hip": "4d1f9bb7b51810020c76673f0feae6419a18fdb911e9af9b77b35022df27a447",
+            "sampler.hip": "21f7e11f26a4a70d277c53c83d2085e292c1ca8e1f3769bf674d6adcdeb0eec1",
             "common.hpp": "373c1289408779effdb76fff0cb18b389447af9368a0c2b3675272823aa4c649",
-            "internal.hpp": "97fb840f4a6670c01adfdf9b0f7c6d1bfe125917d858b7d13bb0a71048c27c79"
+            "internal.hpp": "3d0517399abdfb569676091d83432670ac9227b5acd41f4e53100848669d982a"
         }
     },
 }
@@ -1004,8 +1004,8 @@ def sweep_pbc_point(L, chi, precision, n, K, steps, p=0.109, seed=0):
     """f4: periodic L x L lattices stepped by a frozen row and column per step (Sec. IV), one
     chain per torus: per step the block of (L-1)^2 spins is built, sampled and accepted against.
     Reports the step time (HIP events), the acceptance, accepted block spin-updates/s, and the
-    Nishimori-line check of the torus energy, [<E>] = -2 L^2 (1 - 2p), over the steps after the
-    first two."""
+    Nishimori-line check of the torus energy, [<E>] = -2 L^2 (1 - 2p), over the timed steps after
+    the first."""
     import numpy as np
     import torch
     import synth
@@ -1018,11 +1018,14 @@ def sweep_pbc_point(L, chi, precision, n, K, steps, p=0.109, seed=0):
     for i in range(n):
         Jh_t, Jv_t = synth.torus_couplings(seed + i, L, p)
         P.set_torus(i, synth.pack_rows(Jh_t), synth.pack_rows(Jv_t), synth.pack_rows(init[i]))
-    lines = [synth.frozen_lines(seed + 1000 + t, n, L) for t in range(steps + 1)]
-    progress(f"pbc L={L} chi={chi} {precision}: warm-up step")
-    P.step(lines[0], K, seed, first_proposal=0, first_step=0)   # untimed (first launches)
+    lines = [synth.frozen_lines(seed + 1000 + t, n, L) for t in range(steps + 2)]
+    # two untimed steps start the chains from proposals (a random configuration can hold an
+    # independence chain where q underrates it), covering all but the lines' crossings
+    for t in range(2):
+        progress(f"pbc L={L} chi={chi} {precision}: starting step {t}")
+        P.step(lines[t], K, seed, first_proposal=K * t, first_step=K * t, init=True)
     ms, acc, Es = [], [], []
-    for t in range(1, steps + 1):
+    for t in range(2, steps + 2):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         a, _ = P.step(lines[t], K, seed, first_proposal=K * t, first_step=K * t)
@@ -1033,7 +1036,7 @@ def sweep_pbc_point(L, chi, precision, n, K, steps, p=0.109, seed=0):
         Es.append(P.E.cpu().numpy().astype(np.float64))
         progress(f"pbc L={L} step {t}: {ms[-1]:.1f} ms, accepted {acc[-1]:.0f}")
     st, _ = P.batch.status_check()
-    E = np.array(Es[1:]).mean(axis=0)            # per-torus mean over the steps after the first two
+    E = np.array(Es[1:]).mean(axis=0)            # per-torus mean over the timed steps after the first
     step_ms = float(np.mean(ms))
     return {"sweep": "pbc", "L": L, "block": L - 1, "chi": chi, "p": p, "precision": precision,
             "tori": n, "proposals": K, "steps": steps, "ms_per_step": step_ms,

@@ -26,7 +26,9 @@ Each step's chain targets P(s_b | frozen), so the torus Boltzmann distribution i
 every choice of lines; picking the lines at random makes every spin movable.
 
 Readings where the paper is silent: the lines (r0, c0) of each step are inputs (the caller draws
-them); the torus couplings are inputs, Jh_t[r, c] on the bond (r, c)-(r, (c+1) mod L) and Jv_t[r,
+them); a chain may start afresh at a step (init), taking that step's first proposal
+unconditionally, which is how a chain is started from a configuration the proposals consider
+typical (a random start can hold a chain for many steps where q underrates it); the torus couplings are inputs, Jh_t[r, c] on the bond (r, c)-(r, (c+1) mod L) and Jv_t[r,
 c] on (r, c)-((r+1) mod L, c); L >= 3, so that the block has at least 2 x 2 sites.
 
 This is test infrastructure (see the package docstring).
@@ -94,20 +96,26 @@ def merge(s_t, s_b, r0, c0):
 
 
 def step(Jh_t, Jv_t, s_t, beta, chi, r0, c0, K, seed=0, realization=0, first_proposal=0,
-         first_step=0):
-    """One TNMC step on the torus with lines (r0, c0) frozen; returns (new s_t, info dict)."""
+         first_step=0, init=False):
+    """One TNMC step on the torus with lines (r0, c0) frozen; returns (new s_t, info dict).
+    init=True starts the chain afresh: the step's first proposal is taken unconditionally (as
+    ``accept`` does for a new chain) instead of the current block configuration."""
     Jh, Jv, h, s_b = block(Jh_t, Jv_t, s_t, r0, c0)
     env = envbuild.build_env(Jh, Jv, beta, chi, field=h)
     smp = sampler.run(env, Jh, Jv, beta, K=K, seed=seed, realization=realization,
                       first_proposal=first_proposal, field=h)
-    cur = sampler.run(env, Jh, Jv, beta, teacher=s_b[None], field=h)
     E_prop = energy.energy(smp["spins"], Jh, Jv, field=h)
-    E_cur = int(energy.energy(s_b[None], Jh, Jv, field=h)[0])
-    state = {"idx": -1, "E": E_cur, "logq": float(cur["logq"][0])}
+    if init:
+        state, E_cur, logq_cur = None, None, None
+    else:
+        cur = sampler.run(env, Jh, Jv, beta, teacher=s_b[None], field=h)
+        E_cur = int(energy.energy(s_b[None], Jh, Jv, field=h)[0])
+        logq_cur = float(cur["logq"][0])
+        state = {"idx": -1, "E": E_cur, "logq": logq_cur}
     out = accept.chain(E_prop, smp["logq"], beta, seed=seed, realization=realization,
                        chain_index=0, first_step=first_step, state=state)
     final = int(out["current"][-1])
     s_new = s_b if final < 0 else smp["spins"][final]
     info = {"block": (Jh, Jv, h, s_b), "env": env, "proposals": smp, "E_prop": E_prop,
-            "E_cur": E_cur, "logq_cur": state["logq"], "chain": out}
+            "E_cur": E_cur, "logq_cur": logq_cur, "chain": out}
     return merge(s_t, s_new, r0, c0), info

@@ -335,21 +335,29 @@ class Batch:
                "tnmc_autotune_propose")
         return best.value, {c: ms[j] for j, c in enumerate(cands)}
 
-    def logq(self, spins):
-        """tnmc_logq: log q of given configurations (spins words [n][K][Lmax][Wmax])."""
+    def logq(self, spins, workspace=None):
+        """tnmc_logq: log q of given configurations (spins words [n][K][Lmax][Wmax]); workspace:
+        an optional uint8 tensor of tnmc_workspace_bytes for K instead of the batch's own (for a
+        call on another stream)."""
         K = spins.shape[1]
-        self.ensure_workspace(K)
         out = torch.empty((self.n, K), dtype=torch.float64, device=self.device)
-        ws, nb = self._ws()
+        if workspace is None:
+            self.ensure_workspace(K)
+            ws, nb = self._ws()
+        else:
+            ws, nb = ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel())
         _check(load().tnmc_logq(self.table, self.n, self.chi, self.prec, int(K), _ptr(spins), ws,
                                 nb, _ptr(out), _stream()), "tnmc_logq")
         return out
 
-    def energy(self, spins):
-        """tnmc_energy: exact integer energies of given configurations."""
+    def energy(self, spins, workspace=None):
+        """tnmc_energy: exact integer energies of given configurations (workspace as for logq)."""
         K = spins.shape[1]
         E = torch.empty((self.n, K), dtype=torch.int32, device=self.device)
-        ws, nb = self._ws()
+        if workspace is None:
+            ws, nb = self._ws()
+        else:
+            ws, nb = ctypes.c_void_p(workspace.data_ptr()), ctypes.c_size_t(workspace.numel())
         _check(load().tnmc_energy(self.table, self.n, int(K), _ptr(spins), _ptr(E), ws, nb,
                                   _stream()), "tnmc_energy")
         return E
@@ -450,6 +458,12 @@ class PBC:
             d.d_spins = self.spins[i].data_ptr()
         nb = int(load().tnmc_pbc_workspace_bytes(self.n))
         self.pws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        # the current states' log q and energy run on a second stream beside the proposals,
+        # with a workspace of their own
+        nb = int(load().tnmc_workspace_bytes(self.batch.table, self.n, self.batch.chi, 1,
+                                             self.batch.prec))
+        self.ws_side = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self.side = torch.cuda.Stream(device=self.device)
 
     def set_torus(self, i, jh_words, jv_words, spin_words):
         """Copy caller-packed torus couplings and configuration (L x W words each) into torus i."""
@@ -478,16 +492,27 @@ class PBC:
                                      _ptr(self.E) if want_energy else None, ws, nb, _stream()),
                "tnmc_pbc_merge")
 
-    def step(self, lines, K, seed, first_proposal=0, first_step=0):
-        """One step on every torus with the given lines: returns (accepted [n][K], proposals)."""
+    def step(self, lines, K, seed, first_proposal=0, first_step=0, init=False):
+        """One step on every torus with the given lines: returns (accepted [n][K], proposals).
+        init=True starts every chain afresh from the step's first proposal (taken
+        unconditionally); otherwise the current block states' log q and energy under the step's
+        environments are evaluated on a second stream while the proposals are drawn."""
         b, ch = self.batch, self.chains
         self.set_lines(lines)
         self.block()
         b.build_env(want_lnZ=False)
+        cur = torch.cuda.current_stream(self.device)
+        if init:
+            ch["init"].fill_(0)
+        else:
+            self.side.wait_stream(cur)
+            with torch.cuda.stream(self.side):
+                ch["logq"].copy_(b.logq(ch["spins"], workspace=self.ws_side))
+                ch["E"].copy_(b.energy(ch["spins"], workspace=self.ws_side))
+                ch["init"].fill_(1)
         props = b.propose(K, seed, first_proposal)
-        ch["logq"].copy_(b.logq(ch["spins"]))
-        ch["E"].copy_(b.energy(ch["spins"]))
-        ch["init"].fill_(1)
+        if not init:
+            cur.wait_stream(self.side)
         accepted, _ = b.accept(props, ch, seed, first_step)
         self.merge()
         return accepted, props

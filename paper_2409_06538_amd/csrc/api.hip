@@ -262,7 +262,8 @@ tnmc_status tnmc_build_env(const tnmc_instance* inst, int32_t n, int32_t chi, tn
   if (workspace_bytes < desc_bytes(n) + build_region(inst, n, chi, prec)) return TNMC_ENOMEM;
   hipError_t e = upload_desc(inst, n, chi, 1, prec, Use::build, d_workspace, stream);
   if (e != hipSuccess) return TNMC_EHIP;
-  return hip_status(env_build(prec, chi, static_cast<const DevReal*>(d_workspace), n, d_lnZ, stream));
+  return hip_status(env_build(prec, chi, any_field(inst, n),
+                              static_cast<const DevReal*>(d_workspace), n, d_lnZ, stream));
 }
 
 tnmc_status tnmc_build_env_form(const tnmc_instance* inst, int32_t n, int32_t chi,
@@ -277,7 +278,7 @@ tnmc_status tnmc_build_env_form(const tnmc_instance* inst, int32_t n, int32_t ch
   if (workspace_bytes < desc_bytes(n) + build_region(inst, n, chi, prec)) return TNMC_ENOMEM;
   hipError_t e = upload_desc(inst, n, chi, 1, prec, Use::build, d_workspace, stream);
   if (e != hipSuccess) return TNMC_EHIP;
-  return hip_status(env_build_big(prec, chi, form == TNMC_FORM_ZIPUP,
+  return hip_status(env_build_big(prec, chi, form == TNMC_FORM_ZIPUP, any_field(inst, n),
                                   static_cast<const DevReal*>(d_workspace), n, d_lnZ, stream));
 }
 
@@ -292,7 +293,8 @@ tnmc_status tnmc_build_env_static(const tnmc_instance* inst, int32_t n, int32_t 
   if (static_scratch(&ws) != hipSuccess) return TNMC_EHIP;
   hipError_t e = upload_desc(inst, n, chi, 1, prec, Use::build, ws, stream);
   if (e != hipSuccess) return TNMC_EHIP;
-  return hip_status(env_build(prec, chi, static_cast<const DevReal*>(ws), n, d_lnZ, stream));
+  return hip_status(env_build(prec, chi, any_field(inst, n), static_cast<const DevReal*>(ws), n,
+                              d_lnZ, stream));
 }
 
 // waves > 0 forces a launch shape; otherwise the tuning table's entry or the default

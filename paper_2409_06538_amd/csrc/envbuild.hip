@@ -526,7 +526,7 @@ __device__ void mgs_pairs_rows(T* V, int k, T eta) {
 // sweeps (FP64 arithmetic for FP32 / BF16 environments): the QR sweep carries G_c = R_c^T R_c,
 // and the SVD step factors Z_c^T G_{c-1} Z_c = (R_{c-1} Z_c)^T (R_{c-1} Z_c) by pivoted Cholesky,
 // whose factor is the R of the pivoted QR of R_{c-1} Z_c (same pivots, same rows up to sign).
-template <typename T, typename E, int CHI, bool GRAM>
+template <typename T, typename E, int CHI, bool GRAM, bool FLD>
 __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevReal* reals,
                                                                      double* lnZ_out) {
   using Tol = JacobiTol<typename TolOf<E>::type>;
@@ -653,7 +653,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       };
       auto lpark = [&]() {
         T lg0, lg1;
-        site_field<T>(R, r, lcc, ep, em, lg0, lg1);
+        site_field_t<FLD, T>(R, r, lcc, ep, em, lg0, lg1);
 #pragma unroll
         for (int t = 0; t < SPT; ++t) {
           const int e = tid + NT * t;
@@ -907,7 +907,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
         // rest of AsT is never read
         const int bl = bdin[c], br = bdin[c + 1], blk = bl * br;
         T fg0, fg1;   // the site's field weights
-        site_field<T>(R, r, c, ep, em, fg0, fg1);
+        site_field_t<FLD, T>(R, r, c, ep, em, fg0, fg1);
         for (int o = tid; o < 2 * blk; o += NT) {
           const int b = o >= blk ? 1 : 0, rem = o - b * blk;
           const int al = rem / br, ap = rem - al * br;
@@ -1069,7 +1069,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     };
     auto park_site = [&]() {
       T ag0, ag1;
-      site_field<T>(R, r, acc_site, ep, em, ag0, ag1);
+      site_field_t<FLD, T>(R, r, acc_site, ep, em, ag0, ag1);
 #pragma unroll
       for (int t = 0; t < SPT; ++t) {
         const int e = tid + NT * t;
@@ -1800,7 +1800,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
     // (row 0's fields, if any, weight each site of E_0 by exp(beta h s))
     {
       T g0, g1;
-      site_field<T>(R, 0, 0, ep, em, g0, g1);
+      site_field_t<FLD, T>(R, 0, 0, ep, em, g0, g1);
       for (int o = tid; o < 2 * CHI; o += NT)
         sc[o] = (o >= CHI ? g1 : g0) * widen(gld<E>(A0, (o / CHI) * CHI * CHI + (o % CHI)));
     }
@@ -1812,7 +1812,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
       if (tid < 2 * CHI) {
         const int sp = tid / CHI, be = tid % CHI;
         T g0, g1;
-        site_field<T>(R, 0, c, ep, em, g0, g1);
+        site_field_t<FLD, T>(R, 0, c, ep, em, g0, g1);
         for (int s2 = 0; s2 < 2; ++s2) {
           const T w = bond_weight<T>(jh0, c - 1, s2, sp, ep, em);
           T dd = 0;
@@ -1837,7 +1837,7 @@ __global__ __launch_bounds__(env_threads(CHI)) void env_build_kernel(const DevRe
   }
 }
 
-template <typename T, typename E, int CHI, bool GRAM>
+template <typename T, typename E, int CHI, bool GRAM, bool FLD>
 hipError_t launch_env_build(const DevReal* d_reals, int n, double* d_lnZ, hipStream_t stream) {
   using S = EnvSmem<T, CHI>;
   static_assert(S::NT == env_tpc(CHI) * S::N2, "one group of TPC threads per column");
@@ -1856,19 +1856,21 @@ hipError_t launch_env_build(const DevReal* d_reals, int n, double* d_lnZ, hipStr
   if (err != hipSuccess) return err;
   if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
   std::call_once(once[dev], [dev] {
-    attr[dev] = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_kernel<T, E, CHI, GRAM>),
+    attr[dev] = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_kernel<T, E, CHI, GRAM, FLD>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(S::bytes));
   });
   if (attr[dev] != hipSuccess) return attr[dev];
-  hipLaunchKernelGGL((env_build_kernel<T, E, CHI, GRAM>), dim3(n), dim3(S::NT), S::bytes, stream, d_reals,
+  hipLaunchKernelGGL((env_build_kernel<T, E, CHI, GRAM, FLD>), dim3(n), dim3(S::NT), S::bytes, stream, d_reals,
                      d_lnZ);
   return hipGetLastError();
 }
 
-hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n, double* d_lnZ,
-                     hipStream_t stream) {
-#define TNMC_ENV_CASE(TY, EY, C, G) \
-  case C: return launch_env_build<TY, EY, C, G>(d_reals, n, d_lnZ, stream);
+hipError_t env_build(tnmc_precision prec, int chi, bool fields, const DevReal* d_reals, int n,
+                     double* d_lnZ, hipStream_t stream) {
+#define TNMC_ENV_CASE(TY, EY, C, G)                                                       \
+  case C:                                                                                 \
+    return fields ? launch_env_build<TY, EY, C, G, true>(d_reals, n, d_lnZ, stream)       \
+                  : launch_env_build<TY, EY, C, G, false>(d_reals, n, d_lnZ, stream);
 #define TNMC_ENV_CHIS(TY, EY, G) \
   TNMC_ENV_CASE(TY, EY, 2, G) TNMC_ENV_CASE(TY, EY, 4, G) TNMC_ENV_CASE(TY, EY, 8, G) \
   TNMC_ENV_CASE(TY, EY, 16, G) TNMC_ENV_CASE(TY, EY, 32, G)
@@ -1881,13 +1883,13 @@ hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n
     switch (chi) {
       TNMC_ENV_CHIS(double, float, true)
       TNMC_ENV_CASE(float, float, 48, false)
-      case 64: return env_build_big(prec, chi, false, d_reals, n, d_lnZ, stream);
+      case 64: return env_build_big(prec, chi, false, fields, d_reals, n, d_lnZ, stream);
     }
   } else if (prec == TNMC_BF16) {
     switch (chi) {
       TNMC_ENV_CHIS(double, bf16_t, true)
       TNMC_ENV_CASE(float, bf16_t, 48, false)
-      case 64: return env_build_big(prec, chi, false, d_reals, n, d_lnZ, stream);
+      case 64: return env_build_big(prec, chi, false, fields, d_reals, n, d_lnZ, stream);
     }
   }
 #undef TNMC_ENV_CHIS

@@ -146,7 +146,7 @@ constexpr size_t big_block() {
   return size_t(2 * CHI) * (2 * CHI);
 }
 
-template <typename T, typename E, int CHI, bool ZIP>
+template <typename T, typename E, int CHI, bool ZIP, bool FLD>
 __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* reals,
                                                                double* lnZ_out) {
   using S = BigSmem<T, CHI>;
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
   // site c of E_r -> sA[b][al][be], al < l, be < m, times the site's field weights exp(beta h b)
   auto stage = [&](const gmem<E>* src, int l, int m, int r, int c) {
     T g0, g1;
-    site_field<T>(R, r, c, ep, em, g0, g1);
+    site_field_t<FLD, T>(R, r, c, ep, em, g0, g1);
     for (int o = tid; o < 2 * l * m; o += NT) {
       const int b = o / (l * m), al = (o / m) % l, be = o % m;
       sA[(b * CHI + al) * LDA + be] = (b ? g1 : g0) * T(widen(gld<E>(src, (b * CHI + al) * CHI + be)));
@@ -837,7 +837,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
     // (row 0's fields, if any, weight each site of E_0 by exp(beta h s))
     {
       T g0, g1;
-      site_field<T>(R, 0, 0, ep, em, g0, g1);
+      site_field_t<FLD, T>(R, 0, 0, ep, em, g0, g1);
       for (int o = tid; o < 2 * CHI; o += NT)
         sc[o] = (o >= CHI ? g1 : g0) * T(widen(gld<E>(A0, (o / CHI) * CHI * CHI + (o % CHI))));
     }
@@ -850,7 +850,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
       if (tid < 2 * CHI) {
         const int sp = tid / CHI, be = tid % CHI;
         T g0, g1;
-        site_field<T>(R, 0, c, ep, em, g0, g1);
+        site_field_t<FLD, T>(R, 0, c, ep, em, g0, g1);
         for (int s2 = 0; s2 < 2; ++s2) {
           const T wgt = w(fh, s2, sp);
           T dd = 0;
@@ -876,7 +876,7 @@ __global__ __launch_bounds__(BIG_NT) void env_build_big_kernel(const DevReal* re
   }
 }
 
-template <typename T, typename E, int CHI, bool ZIP>
+template <typename T, typename E, int CHI, bool ZIP, bool FLD>
 hipError_t launch_env_build_big(const DevReal* d_reals, int n, double* d_lnZ, hipStream_t stream) {
   using S = BigSmem<T, CHI>;
   static_assert(S::bytes <= 160 * 1024, "LDS of one workgroup");
@@ -888,11 +888,11 @@ hipError_t launch_env_build_big(const DevReal* d_reals, int n, double* d_lnZ, hi
   if (err != hipSuccess) return err;
   if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
   std::call_once(once[dev], [dev] {
-    attr[dev] = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_big_kernel<T, E, CHI, ZIP>),
+    attr[dev] = hipFuncSetAttribute(reinterpret_cast<const void*>(&env_build_big_kernel<T, E, CHI, ZIP, FLD>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(S::bytes));
   });
   if (attr[dev] != hipSuccess) return attr[dev];
-  hipLaunchKernelGGL((env_build_big_kernel<T, E, CHI, ZIP>), dim3(n), dim3(BIG_NT), S::bytes, stream,
+  hipLaunchKernelGGL((env_build_big_kernel<T, E, CHI, ZIP, FLD>), dim3(n), dim3(BIG_NT), S::bytes, stream,
                      d_reals, d_lnZ);
   return hipGetLastError();
 }
@@ -902,16 +902,19 @@ int env_build_big_ok(tnmc_precision prec, int chi) {
          (chi == 8 || chi == 16 || chi == 32 || chi == 48 || chi == 64);
 }
 
-hipError_t env_build_big(tnmc_precision prec, int chi, bool zipup, const DevReal* d_reals, int n,
-                         double* d_lnZ, hipStream_t stream) {
+hipError_t env_build_big(tnmc_precision prec, int chi, bool zipup, bool fields,
+                         const DevReal* d_reals, int n, double* d_lnZ, hipStream_t stream) {
+#define TNMC_BIG_LAUNCH(C, Z, F)                                                               \
+  return prec == TNMC_BF16 ? launch_env_build_big<float, bf16_t, C, Z, F>(d_reals, n, d_lnZ, stream) \
+                           : launch_env_build_big<double, float, C, Z, F>(d_reals, n, d_lnZ, stream);
 #define TNMC_BIG_CASE(C)                                                                       \
   case C:                                                                                      \
-    if (zipup)                                                                                 \
-      return prec == TNMC_BF16                                                                 \
-                 ? launch_env_build_big<float, bf16_t, C, true>(d_reals, n, d_lnZ, stream)     \
-                 : launch_env_build_big<double, float, C, true>(d_reals, n, d_lnZ, stream);    \
-    return prec == TNMC_BF16 ? launch_env_build_big<float, bf16_t, C, false>(d_reals, n, d_lnZ, stream) \
-                             : launch_env_build_big<double, float, C, false>(d_reals, n, d_lnZ, stream);
+    if (zipup) {                                                                               \
+      if (fields) { TNMC_BIG_LAUNCH(C, true, true) }                                           \
+      TNMC_BIG_LAUNCH(C, true, false)                                                          \
+    }                                                                                          \
+    if (fields) { TNMC_BIG_LAUNCH(C, false, true) }                                            \
+    TNMC_BIG_LAUNCH(C, false, false)
   if (prec != TNMC_BF16 && prec != TNMC_FP32) return hipErrorInvalidValue;
   switch (chi) {
     TNMC_BIG_CASE(8)
@@ -921,6 +924,7 @@ hipError_t env_build_big(tnmc_precision prec, int chi, bool zipup, const DevReal
     TNMC_BIG_CASE(64)
   }
 #undef TNMC_BIG_CASE
+#undef TNMC_BIG_LAUNCH
   return hipErrorInvalidValue;
 }
 

@@ -58,17 +58,30 @@ __device__ __forceinline__ void site_field(const DevReal& R, int r, int c, T ep,
   }
 }
 
+// The same, compiled away (weights 1) where the batch has no fields.
+template <bool FLD, typename T>
+__device__ __forceinline__ void site_field_t(const DevReal& R, int r, int c, T ep, T em, T& g0,
+                                             T& g1) {
+  if constexpr (FLD) {
+    site_field<T>(R, r, c, ep, em, g0, g1);
+  } else {
+    g0 = T(1);
+    g1 = T(1);
+  }
+}
+
 hipError_t couplings_launch(const DevReal* d_reals, int n, const uint64_t* d_seeds, double p,
                             int Lmax, hipStream_t stream);
 
-hipError_t env_build(tnmc_precision prec, int chi, const DevReal* d_reals, int n, double* d_lnZ,
-                     hipStream_t stream);
+// fields: some realization of the batch has site fields (the kernels then read them)
+hipError_t env_build(tnmc_precision prec, int chi, bool fields, const DevReal* d_reals, int n,
+                     double* d_lnZ, hipStream_t stream);
 size_t env_build_scratch_bytes(tnmc_precision prec, int chi, int L);
 // The Gram form with global scratch (envbuild_big.hip): the build of chi = 64 (FP32 and BF16
 // environments), and a selectable form at chi = 8 .. 48
 int env_build_big_ok(tnmc_precision prec, int chi);
-hipError_t env_build_big(tnmc_precision prec, int chi, bool zipup, const DevReal* d_reals, int n,
-                         double* d_lnZ, hipStream_t stream);
+hipError_t env_build_big(tnmc_precision prec, int chi, bool zipup, bool fields,
+                         const DevReal* d_reals, int n, double* d_lnZ, hipStream_t stream);
 size_t env_build_big_scratch_bytes(tnmc_precision prec, int chi, int L);
 
 // waves: wavefronts per workgroup of the proposal kernel (propose_waves_ok), 0 = default

@@ -174,14 +174,15 @@ def test_steps_fp64_match_oracle(tnmc_gpu):
     states = [c[2].copy() for c in cases]
     W = synth.words_per_row(L)
     rejected = 0
-    for t in range(4):
+    for t in range(5):
         lines = synth.frozen_lines(100 + t, n, L)
-        acc, _ = P.step(lines, K, seed, first_proposal=K * t, first_step=K * t)
+        init = t == 0   # the first step starts the chains from a proposal
+        acc, _ = P.step(lines, K, seed, first_proposal=K * t, first_step=K * t, init=init)
         acc = host(acc)
         for i, (Jh_t, Jv_t, _) in enumerate(cases):
             states[i], info = o_pbc.step(Jh_t, Jv_t, states[i], beta, chi, int(lines[i][0]),
                                          int(lines[i][1]), K, seed=seed, realization=i,
-                                         first_proposal=K * t, first_step=K * t)
+                                         first_proposal=K * t, first_step=K * t, init=init)
             np.testing.assert_array_equal(acc[i].astype(bool), info["chain"]["accepted"])
             np.testing.assert_array_equal(host(P.spins[i]).view(np.uint64).reshape(L, W),
                                           packed(states[i], W))

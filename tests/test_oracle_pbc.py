@@ -113,6 +113,19 @@ def test_step_exact_chi_accepts_everything():
     assert acc == 6 * 10
 
 
+def test_step_init_takes_first_proposal():
+    """A fresh start: the step's first proposal becomes the state unconditionally (not counted
+    as accepted), and the rest of the step is the chain from there."""
+    L, beta = 5, 0.9
+    Jh_t, Jv_t, s_t = _torus_case(8, L)
+    s_new, info = pbc.step(Jh_t, Jv_t, s_t, beta, 2, 1, 3, K=6, seed=3, init=True)
+    ch = info["chain"]
+    assert ch["init"][0] and not ch["accepted"][0] and ch["current"][0] == 0
+    assert info["logq_cur"] is None
+    final = int(ch["current"][-1])
+    np.testing.assert_array_equal(s_new, pbc.merge(s_t, info["proposals"]["spins"][final], 1, 3))
+
+
 def test_pbc_chain_reproduces_torus_histogram():
     """chi = 1 on the 3 x 3 blocks of a 4 x 4 torus: biased proposals, exact chain."""
     L, beta, K, steps = 4, 0.7, 4, 3000

@@ -138,7 +138,7 @@ hipError_t field_energy_launch(const DevReal* d_reals, int n, int K, int Lmax,
 __device__ __forceinline__ int tbit(const uint64_t* row, int c) { return int((row[c >> 6] >> (c & 63)) & 1ull); }
 
 // One workgroup per (torus, block row a); one 64-bit word (or one site of the fields) per thread.
-__global__ void __launch_bounds__(256) pbc_block_kernel(const DevTorus* tor, const DevReal* blk,
+__global__ void __launch_bounds__(64) pbc_block_kernel(const DevTorus* tor, const DevReal* blk,
                                                         int Lmax, uint64_t* bspins) {
   const DevTorus T = tor[blockIdx.y];
   const DevReal B = blk[blockIdx.y];

@@ -229,3 +229,48 @@ def test_chain_reproduces_torus_energy_histogram(tnmc_gpu):
           f"{Es.mean():.3f} exact {(Pw * Eall).sum():.3f}", flush=True)
     assert pa > 0.999
     assert pval > 1e-4
+
+
+def test_static_build_with_fields_equals_workspace_build(tnmc_gpu):
+    """The allocation-free build of a batch with fields (the field-reading kernels through the
+    fixed scratch array) equals the workspace build bit for bit."""
+    import torch
+    from paper_2409_06538_amd import binding
+    L, n, chi = 17, 2, 16
+    P, _ = make_pbc(L, n, chi, "fp32", 1, 0.9, [61, 62])
+    P.set_lines(synth.frozen_lines(63, n, L))
+    P.block()
+    b = P.batch
+    lz = b.build_env()
+    ref = [(e.clone(), l.clone()) for e, l in zip(b.env, b.lognorm)]
+    for e, l in zip(b.env, b.lognorm):
+        e.zero_()
+        l.zero_()
+    lz2 = b.build_env_static()
+    torch.cuda.synchronize()
+    assert torch.equal(lz, lz2)
+    for (e, l), e2, l2 in zip(ref, b.env, b.lognorm):
+        assert torch.equal(e, e2) and torch.equal(l, l2)
+
+
+def test_steps_bf16_chi64(tnmc_gpu):
+    """Steps through the chi = 64 BF16 build with fields (the Gram form with global scratch):
+    every torus energy equals the oracle's energy of the GPU's configuration, and the chains
+    accept."""
+    from paper_2409_06538_amd import binding
+    L, n, chi, K = 17, 2, 64, 32
+    beta = binding.nishimori_beta(0.109)
+    P, cases = make_pbc(L, n, chi, "bf16", K, beta, [71, 72])
+    W = synth.words_per_row(L)
+    acc = 0
+    for t in range(3):
+        a, _ = P.step(synth.frozen_lines(300 + t, n, L), K, 5, first_proposal=K * t,
+                      first_step=K * t, init=(t == 0))
+        acc += int(host(a).sum())
+        E = host(P.E)
+        for i, (Jh_t, Jv_t, _) in enumerate(cases):
+            s = synth.unpack_rows(host(P.spins[i]).view(np.uint64).reshape(L, W), L)
+            assert E[i] == o_pbc.torus_energy(s[None], Jh_t, Jv_t)[0]
+    st, words = P.batch.status_check()
+    assert st == 0, words
+    assert acc > 0

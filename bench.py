@@ -996,16 +996,33 @@ def sweep_forms_point(L, chi, precision, n_real, K, p=0.109, seed=0):
 
 
 # (torus side, chi, precision, tori, proposals per step, steps) of the periodic-lattice sweep
-SWEEP_PBC = ((17, 16, "fp32", 64, 256, 8), (65, 32, "fp32", 64, 1000, 6),
+SWEEP_PBC = ((17, 16, "fp32", 64, 256, 40), (65, 32, "fp32", 64, 1000, 20),
              (129, 32, "fp32", 16, 256, 5), (257, 48, "bf16", 16, 256, 4))
+
+
+def step_autocorrelation(E, kmax=5):
+    """rho(k), k = 1..kmax, of a (steps, tori) array of per-step energies, pooled over tori
+    (each torus's own mean removed), and tau_int = 1/2 + sum of rho(k) up to the first k whose
+    rho is not positive."""
+    import numpy as np
+    x = E - E.mean(axis=0, keepdims=True)
+    var = float((x * x).sum())
+    rho = [float((x[:-k] * x[k:]).sum()) / var if var > 0 else 0.0
+           for k in range(1, min(kmax, E.shape[0] - 1) + 1)]
+    tau = 0.5
+    for r in rho:
+        if r <= 0:
+            break
+        tau += r
+    return rho, tau
 
 
 def sweep_pbc_point(L, chi, precision, n, K, steps, p=0.109, seed=0):
     """f4: periodic L x L lattices stepped by a frozen row and column per step (Sec. IV), one
     chain per torus: per step the block of (L-1)^2 spins is built, sampled and accepted against.
-    Reports the step time (HIP events), the acceptance, accepted block spin-updates/s, and the
+    Reports the step time (HIP events), the acceptance, accepted block spin-updates/s, the
     Nishimori-line check of the torus energy, [<E>] = -2 L^2 (1 - 2p), over the timed steps after
-    the first."""
+    the first, and the step-to-step autocorrelation of the torus energy."""
     import numpy as np
     import torch
     import synth
@@ -1037,13 +1054,17 @@ def sweep_pbc_point(L, chi, precision, n, K, steps, p=0.109, seed=0):
         progress(f"pbc L={L} step {t}: {ms[-1]:.1f} ms, accepted {acc[-1]:.0f}")
     st, _ = P.batch.status_check()
     E = np.array(Es[1:]).mean(axis=0)            # per-torus mean over the timed steps after the first
+    # successive steps share the frozen lines' spins (and the rest of the previous state, when a
+    # step's chain rejects everything): the correlation of the torus energy from step to step
+    rho, tau = step_autocorrelation(np.array(Es[1:]))
     step_ms = float(np.mean(ms))
     return {"sweep": "pbc", "L": L, "block": L - 1, "chi": chi, "p": p, "precision": precision,
             "tori": n, "proposals": K, "steps": steps, "ms_per_step": step_ms,
             "acceptance": float(np.sum(acc)) / (n * K * steps),
             "accepted_spin_updates_per_s": float(np.mean(acc)) * (L - 1) ** 2 / (step_ms * 1e-3),
             "E_mean": float(E.mean()), "E_err": float(E.std(ddof=1) / np.sqrt(n)),
-            "E_nishimori": -2 * L * L * (1 - 2 * p), "status": st}
+            "E_nishimori": -2 * L * L * (1 - 2 * p),
+            "E_step_autocorrelation": rho, "E_tau_int_steps": tau, "status": st}
 
 
 def run_observables(args, L, chi, p, n_real, K, n_chain=2):
